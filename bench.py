@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Throughput of the environment potential on one MI355X.
+
+A step is one evaluation of V(r) for the whole point batch of the workload
+(nuclear term, Boys function, Hermite recursion and contraction, FP64
+cancellation sums, output), with the pair list already on the device and the
+points already in HBM.  The metric is point-pair evaluations per second:
+n_points x n_pairs (unique screened primitive shell pairs) / time per step.
+
+Default workload "mid": 200 environment atoms in 20 neutral 10-atom fragments,
+contracted s/p/d shells, 375,461 screened pairs, 131,072 points
+(4096 walkers x 32 electrons) in the 8-bohr QM sphere.  The headline path is
+FP32C; the FP64 path is timed beside it.  The CPU-baseline leg times the FP64
+oracle on a bounded sample of the same points and reports the GPU paths'
+errors on that sample.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "point-pair evals/s at ≤1e-5 Ha max err: FP64 vs FP32 vs MLP surrogate, 1 GPU"
+
+PEAK_FP32 = 157.3e12   # MI355X FP32 vector (published, packed)
+PEAK_FP64 = 78.6e12    # MI355X FP64 vector
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_path(E, x, out, steps, warmup, torch):
+    for _ in range(warmup):
+        E.eval(x, out=out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, e in evs:
+        s.record(stream)
+        E.eval(x, out=out, stream=stream)
+        e.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    ms = [s.elapsed_time(e) for s, e in evs]
+    return wall, float(np.mean(ms))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="mid")
+    ap.add_argument("--cpu-sample", type=int, default=96,
+                    help="points of the oracle's CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--paths", default="fp32c,fp64")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(points would be sharded across GPUs with no communication)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1011_4687_amd import envpot, synth
+    from paper_1011_4687_amd.workcount import eval_flops
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+
+    env, pts = synth.workload(args.workload)
+    n = pts.shape[0]
+    x = torch.from_numpy(pts).cuda()
+    log(f"[bench] workload {args.workload}: {env.n_nuclei} atoms, nbf {env.nbf}, {n} points")
+
+    paths = {}
+    outs = {}
+    info = None
+    for prec in args.paths.split(","):
+        t0 = time.perf_counter()
+        E = envpot.Environment.from_synth(env, precision=prec, neutralize=True)
+        t_create = time.perf_counter() - t0
+        info = E.info()
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+        wall, ms = time_path(E, x, out, args.steps, args.warmup, torch)
+        npairs = info["n_pairs"]
+        flops = eval_flops(n, info["n_pairs_by_L"], info["n_nuclei"])
+        paths[prec] = {
+            "point_pairs_per_s": n * npairs / (ms * 1e-3),
+            "ms_per_step": ms,
+            "wall_ms_per_step": wall * 1e3,
+            "create_s": t_create,
+            "tflops_algorithmic": flops / (ms * 1e-3) / 1e12,
+        }
+        outs[prec] = out.cpu().numpy()
+        log(f"[bench] {prec}: {ms:.3f} ms/step, {paths[prec]['point_pairs_per_s']:.4g} pp/s")
+        E.close()
+
+    head = "fp32c" if "fp32c" in paths else list(paths)[0]
+    flops = eval_flops(n, info["n_pairs_by_L"], info["n_nuclei"])
+    ms = paths[head]["ms_per_step"]
+    peak = PEAK_FP32 if head == "fp32c" else PEAK_FP64
+    achieved = flops / (ms * 1e-3)
+    result = {
+        "metric": METRIC,
+        "value": paths[head]["point_pairs_per_s"],
+        "unit": "point-pair evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32" if head == "fp32c" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {env.n_nuclei} atoms in {env.n_fragments} neutral "
+                        f"fragments, contracted s/p/d basis (nbf {env.nbf}), "
+                        f"{info['n_pairs']} screened primitive pairs, {n} points in the "
+                        f"{8.0 if args.workload != 'tiny' else 4.0}-bohr QM sphere",
+            "n_points": n,
+            "n_pairs": info["n_pairs"],
+            "pairs_by_L": info["n_pairs_by_L"],
+            "n_nuclei": info["n_nuclei"],
+            "path": head,
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": peak / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / peak,
+            "traffic": None,
+        },
+        "paths": paths,
+    }
+
+    if not args.no_cpu_baseline:
+        # CPU-baseline leg: the FP64 oracle on a bounded sample of the same points
+        from oracle import oracle as O
+        rng = np.random.default_rng(12345)
+        idx = np.sort(rng.choice(n, size=min(args.cpu_sample, n), replace=False))
+        sc = O.neutral_scales(env)
+        cores = os.cpu_count() or 1
+        t0 = time.perf_counter()
+        Vo, Vn, Ve, A = O.potential(env, pts[idx], scale=sc, screen=True, nthreads=cores)
+        t_or = time.perf_counter() - t0
+        result["cpu_baseline"] = {
+            "value": len(idx) * info["n_pairs"] / t_or,
+            "unit": "point-pair evals/s",
+            "cores": cores,
+            "kind": "oracle",
+            "sample": f"{len(idx)} of the {n} points (seeded), screened FP64 oracle, "
+                      f"{t_or:.1f} s on {cores} threads",
+        }
+        acc = {}
+        for prec, V in outs.items():
+            err = np.abs(V[idx] - Vo)
+            acc[prec] = {"max_abs_err": float(err.max()), "rms_err": float(np.sqrt(np.mean(err ** 2))),
+                         "max_rel_to_A": float((err / A).max())}
+        result["accuracy_vs_oracle"] = acc
+        log(f"[bench] oracle {t_or:.1f}s; accuracy {acc}")
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

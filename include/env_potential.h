@@ -1,0 +1,191 @@
+/*
+ * env_potential.h -- C ABI of the MI355X (gfx950) environment-potential library.
+ *
+ * The library evaluates the electrostatic potential of a fixed QM/MM
+ * environment at QMC electron positions (paper Sec. II.B, Eq.
+ * ElectrostaticField, and the per-MC-step use of Sec. III):
+ *
+ *     V(r) = sum_A Z_A / |r - R_A|  -  sum_{mu,nu} P_{mu nu} [mu nu | r]
+ *
+ * with the environment electron density given by a density matrix P over
+ * contracted Cartesian Gaussian basis functions.  The paper's field
+ * U_ES(r) of Eq. ElectrostaticField is the potential energy of an electron,
+ * U_ES = -V.  All quantities are in atomic units (bohr, hartree, e).
+ *
+ * The shape of the interface follows the paper's host/device split
+ * (Sec. III): the read-only environment is uploaded once by
+ * env_potential_create, and each evaluation moves only the electron
+ * positions in and the potential out.  The nuclear and electronic parts are
+ * summed on the device (the paper summed them on the host, Sec. III).
+ *
+ * Conventions
+ *   Basis order      shells in array order; within a shell the Cartesian
+ *                    components in x-major order: p = x, y, z;
+ *                    d = xx, xy, xz, yy, yz, zz (six Cartesian d functions).
+ *   Normalisation    coefs multiply normalised primitives; each contracted
+ *                    Cartesian component is then rescaled to unit
+ *                    self-overlap.
+ *   Fragments        each nucleus carries a fragment id (>= 0, or -1 for
+ *                    "none": those form one group of their own).  Density
+ *                    elements between basis functions of different fragments
+ *                    are accepted and accumulated in a separate cross group.
+ *   Ownership        create deep-copies every input; the caller may free
+ *                    them on return.  points/out of an evaluation belong to
+ *                    the caller and must stay valid until the stream has
+ *                    completed the evaluation.
+ *   Streams          evaluation calls are asynchronous on the given HIP stream
+ *                    (NULL = the default stream) and never synchronise the
+ *                    host; a handle may be evaluated concurrently on several
+ *                    streams.
+ *   Errors           every call returns an env_status; no exception crosses
+ *                    the ABI.  Arguments are validated before any device
+ *                    work is queued.
+ *   Device           there is no CPU evaluation path: evaluation requires a
+ *                    gfx950 device; without one create returns ENV_E_DEVICE
+ *                    unless ENV_BUILD_ONLY is set.
+ */
+#ifndef ENV_POTENTIAL_H
+#define ENV_POTENTIAL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct env_potential env_potential; /* opaque, immutable after create */
+
+typedef enum {
+    ENV_OK = 0,
+    ENV_E_ARG = -1,         /* invalid argument (NULL, NaN, size, asymmetric P) */
+    ENV_E_UNSUPPORTED = -2, /* valid but not supported (l > 2, option combination) */
+    ENV_E_NOMEM = -3,       /* host or device allocation failed */
+    ENV_E_DEVICE = -4,      /* no usable device, or a HIP call / launch failed */
+    ENV_E_STATE = -5        /* handle cannot do this (e.g. built with ENV_BUILD_ONLY) */
+} env_status;
+
+typedef enum {
+    ENV_PREC_FP64 = 0,  /* every step in FP64 */
+    ENV_PREC_FP32C = 1  /* pair arithmetic in FP32, FP64 differences of coordinates,
+                           FP32 tile sums promoted to FP64, FP64 nuclear term and
+                           per-fragment nuclear-minus-electronic sums */
+} env_precision;
+
+/* Option flags */
+#define ENV_BUILD_ONLY 0x1u       /* build the pair list on the host, touch no device;
+                                     the handle supports info/export, not evaluation */
+#define ENV_NEUTRALIZE 0x2u       /* rescale each fragment's diagonal density block so
+                                     that its electron count tr(P_f S_f) equals the
+                                     fragment's nuclear charge (needs a block-diagonal P) */
+#define ENV_NO_SCREENING 0x4u     /* keep every primitive pair */
+
+typedef struct {
+    double xyz[3];     /* position, bohr */
+    double Z;          /* nuclear charge (0 allowed: a basis-only centre) */
+    int32_t fragment;  /* fragment id >= 0, or -1 */
+    int32_t reserved;  /* must be 0 */
+} env_nucleus;
+
+typedef struct {
+    int32_t atom;              /* index of the nucleus the shell sits on */
+    int32_t l;                 /* angular momentum, 0..2 */
+    int32_t nprim;             /* number of primitives, >= 1 */
+    int32_t reserved;          /* must be 0 */
+    const double* exponents;   /* nprim exponents, > 0 */
+    const double* coefs;       /* nprim contraction coefficients */
+} env_shell;
+
+#define ENV_DENSITY_DENSE 0   /* values: nbf x nbf row-major */
+#define ENV_DENSITY_CSR 1     /* row_ptr[nbf+1], col[nnz], values[nnz] */
+
+typedef struct {
+    int32_t nbf;              /* number of basis functions (must match the shells) */
+    int32_t format;           /* ENV_DENSITY_DENSE or ENV_DENSITY_CSR */
+    const double* values;
+    const int64_t* row_ptr;   /* CSR only */
+    const int32_t* col;       /* CSR only; both triangles of the symmetric P */
+} env_density;
+
+typedef struct {
+    int32_t precision;        /* env_precision */
+    int32_t device;           /* HIP device ordinal, -1 = current device */
+    double screen_threshold;  /* primitive-pair screening threshold (default 1e-12) */
+    uint32_t flags;           /* ENV_* option flags */
+    int32_t reserved[3];      /* must be 0 */
+} env_options;
+
+typedef struct {
+    int32_t nbf;
+    int32_t n_nuclei;             /* nuclei with Z != 0 */
+    int32_t n_groups;             /* fragment groups (incl. the cross group if used) */
+    int32_t n_segments;
+    int64_t n_pairs;              /* unique screened primitive shell pairs */
+    int64_t n_pairs_by_L[5];      /* by L = l_I + l_J */
+    int64_t n_pairs_unscreened;   /* unique primitive shell pairs in nonzero blocks */
+    double electrons;             /* sum over pairs of the pair charge = tr(P S) after
+                                     screening and neutralisation */
+    double nuclear_charge;        /* sum of Z */
+    double screened_bound;        /* sum over dropped pairs of |P|-weighted charge bound */
+    int64_t device_bytes;         /* bytes held on the device by the handle */
+    int32_t precision;
+    int32_t built_on_device;      /* 0 with ENV_BUILD_ONLY */
+} env_info;
+
+/* Default options: FP32C, current device, threshold 1e-12, no flags. */
+void env_options_default(env_options* opts);
+
+/* Build the environment (paper Sec. II.B: nuclei {Z_beta, R_beta} plus the
+ * electron density; Sec. III: uploaded once, read-only afterwards).
+ * Builds the screened primitive-pair list with its Hermite densities on the
+ * host, uploads it, and returns a handle in *out.
+ * Errors: ENV_E_ARG (NULL pointers, n < 0, non-finite input, exponent <= 0,
+ * atom index out of range, nbf mismatch, P not symmetric), ENV_E_UNSUPPORTED
+ * (l > 2; ENV_NEUTRALIZE with density between fragments), ENV_E_NOMEM,
+ * ENV_E_DEVICE. */
+env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
+                                const env_shell* shells, int32_t n_shells,
+                                const env_density* P, const env_options* opts,
+                                env_potential** out);
+
+/* V at n points (paper Sec. III: electron position in, potential out).
+ * points: device pointer to n x 3 float64 (x, y, z of each point, contiguous);
+ * out: device pointer to n float64.  stream: hipStream_t or NULL.
+ * n = 0 is a no-op.  A point exactly on a nucleus gives +inf.
+ * Errors: ENV_E_ARG (NULL with n > 0, n < 0), ENV_E_STATE (ENV_BUILD_ONLY
+ * handle), ENV_E_DEVICE (launch failure), ENV_E_NOMEM (workspace). */
+env_status env_potential_eval(env_potential* h, const double* points, int64_t n,
+                              double* out, void* stream);
+
+/* Several independent evaluations in one persistent launch: instance i
+ * evaluates handle hs[i] at points[i] (n[i] x 3) into out[i] (n[i]).
+ * All handles must share the device and precision of hs[0].  Work items
+ * (instance, point block, pair range) are balanced by cost across the chip.
+ * Same pointer/stream rules and errors as env_potential_eval. */
+env_status env_potential_eval_batched(env_potential* const* hs, int32_t n_inst,
+                                      const double* const* points, const int64_t* n,
+                                      double* const* out, void* stream);
+
+/* Statistics of the built pair list. */
+env_status env_potential_info(const env_potential* h, env_info* info);
+
+/* Copy of the pair list for inspection (host buffers, any handle):
+ * for each of the n_pairs pairs, in the library's internal order:
+ *   L[k] (int32), group[k] (int32), center[3k..3k+2], exponent p[k] and the
+ *   Hermite density D[35k .. 35k+ncomp(L)-1] (float64, scaled by
+ *   (pi/p)^{3/2}, so that D[35k] is the pair's electron count), with the
+ *   components t+u+v <= L ordered by t, then u, then v ascending.
+ * Any output pointer may be NULL.  cap is the capacity in pairs; returns
+ * ENV_E_ARG if cap < n_pairs. */
+env_status env_potential_export_pairs(const env_potential* h, int64_t cap, int32_t* L,
+                                      int32_t* group, double* center, double* p,
+                                      double* D);
+
+void env_potential_destroy(env_potential* h);
+
+const char* env_status_string(env_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ENV_POTENTIAL_H */

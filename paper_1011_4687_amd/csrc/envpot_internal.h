@@ -1,0 +1,120 @@
+// Internal layout shared by the host pair-list builder, the launcher and the
+// gfx950 kernels.  Nothing here is part of the C ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "env_potential.h"
+
+namespace envpot {
+
+constexpr int kLMax = 4;                  // largest L = l_I + l_J (d-d pairs)
+constexpr int kNComp[kLMax + 1] = {1, 4, 10, 20, 35};
+constexpr int kMaxSplitLog2 = 6;          // split-pair factors 1, 2, 4, ..., 64
+constexpr int kBlock = 256;               // threads per workgroup of the point kernels
+
+// Boys tables: grid T_k = k / 8, k = 0..rows-1.
+constexpr int kBoysGridInv = 8;
+constexpr int kBoysRowF32 = 12;           // floats per row: F_0..F_9 (+2 pad)
+constexpr int kBoysTaylorF32 = 6;         // Taylor terms j = 0..5, |dT| <= 1/16
+constexpr int kBoysRowF64 = 16;           // doubles per row: F_0..F_13 (+2 pad)
+constexpr int kBoysTaylorF64 = 10;        // Taylor terms j = 0..9
+constexpr int kBoysMaxRowsF32 = 8 * 40 + 1;
+
+// Index of Hermite component (t,u,v), t+u+v <= L, in the order t ascending,
+// then u, then v (the order of the generated recursion and of D in a record).
+constexpr int hermite_index(int L, int t, int u, int v) {
+    int idx = 0;
+    for (int a = 0; a <= L; ++a)
+        for (int b = 0; b <= L - a; ++b)
+            for (int c = 0; c <= L - a - b; ++c) {
+                if (a == t && b == u && c == v) return idx;
+                ++idx;
+            }
+    return -1;
+}
+
+// Pair-record sizes in 4-byte words.
+//  FP32C record: Px, Py, Pz (double), p, c1 = 2 sqrt(p/pi) (float), D[ncomp] (float)
+//  FP64  record: Px, Py, Pz, p, c1 (double), D[ncomp] (double)
+// D is the Hermite density scaled by (pi/p)^{3/2}.  Records are padded to an
+// even number of words so that every double is 8-byte aligned.
+constexpr int rec32_words(int L) { return ((6 + 2 + kNComp[L]) + 1) & ~1; }
+constexpr int rec64_words(int L) { return 2 * (5 + kNComp[L]); }
+
+// A run of pairs of one L inside one fragment group, plus (on the group's
+// first segment) the group's nuclei.
+struct Segment {
+    int32_t L;
+    int32_t n_pairs;
+    int64_t rec_off;     // offset of the first record, in 4-byte words
+    int32_t nuc_begin;   // nuclei [nuc_begin, nuc_end) of the device array
+    int32_t nuc_end;
+    int32_t flags;       // kSegEndGroup: fold nuclear-minus-electronic sum afterwards
+    int32_t pad;
+};
+constexpr int32_t kSegEndGroup = 1;
+
+struct BoysParams {
+    float tfar32[kLMax + 1];   // FP32 path: asymptotic form for T >= tfar32[L]
+    int32_t rows32;
+    double tfar64[kLMax + 1];  // FP64 path
+    int32_t rows64;
+    int32_t pad;
+};
+
+struct EvalArgs {
+    const double* pts;      // n x 3
+    int64_t n;
+    const Segment* segs;    // segments of the chosen split factor
+    const int32_t* split;   // S+1 offsets into segs
+    const uint32_t* rec;    // pair records of the handle's precision
+    const double* nuc;      // nuclei, 4 doubles each (x, y, z, Z)
+    const void* boys;       // Boys table of the handle's precision
+    double* out;            // S == 1: V; S > 1: partial sums [S][n]
+    BoysParams bp;
+};
+
+// Host-side result of the pair-list build.
+struct PairList {
+    int nbf = 0;
+    int n_groups = 0;
+    bool has_cross = false;
+    // pairs in final order (group, L), SoA over pairs
+    std::vector<int32_t> L, group;
+    std::vector<double> center;   // 3 per pair
+    std::vector<double> p;
+    std::vector<double> D;        // 35 per pair (unused tail zero)
+    std::vector<double> nuc;      // 4 per nucleus, grouped
+    std::vector<int32_t> group_nuc_begin, group_nuc_end;  // per group
+    std::vector<int64_t> group_pair_begin;                // per group (+1)
+    int64_t n_unscreened = 0;
+    double screened_bound = 0.0;
+    double electrons = 0.0;
+    double nuclear_charge = 0.0;
+};
+
+// Build the screened, folded primitive-pair list.  Returns ENV_OK or an error.
+env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
+                           const env_shell* shells, int32_t n_shells,
+                           const env_density* P, const env_options& opt, PairList& out);
+
+// Segment table for split factor S: segments (cut where needed) and S+1
+// offsets, balancing the estimated cost of pairs and nuclei.
+void build_segments(const PairList& pl, int S, bool fp64, std::vector<Segment>& segs,
+                    std::vector<int32_t>& split);
+
+// Pack the records of one precision.
+void pack_records(const PairList& pl, bool fp64, std::vector<uint32_t>& rec,
+                  std::vector<int64_t>& rec_off_of_pair_L_start);
+
+// Boys tables (host FP64/long double) and the far-field thresholds.
+void build_boys_tables(std::vector<float>& t32, std::vector<double>& t64, BoysParams& bp);
+
+// Kernel launchers (kernels.hip).
+int launch_potential(const EvalArgs& a, int S, int precision, int np, void* stream);
+int launch_sum_splits(const double* partial, int S, int64_t n, double* out, void* stream);
+
+}  // namespace envpot

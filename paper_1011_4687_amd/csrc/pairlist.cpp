@@ -1,0 +1,604 @@
+// Host-side builder of the screened primitive-pair list (runs once per
+// environment, like the paper's one-time upload of the read-only field data,
+// Sec. III).  For every pair of primitives a in shell I and b in shell J of a
+// nonzero density block it forms the Gaussian product (exponent p = a + b,
+// centre P = (a A + b B)/p) and folds the density-matrix block, the
+// normalisation and the three 1-D Hermite expansion coefficients E^{ij}_t
+// into one Hermite density D_tuv (McMurchie-Davidson), so that the pair's
+// share of the electronic potential at C is
+//     (2 pi / p) sum_{t+u+v <= L} D_tuv R_tuv(p, P - C).
+// D is stored scaled by (pi/p)^{3/2}: then D_000 is the pair's electron
+// count and the far field of the pair is sum_tuv D_tuv d^t d^u d^v (1/R).
+#include <algorithm>
+#include <array>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <thread>
+#include <unordered_map>
+
+#include "envpot_internal.h"
+
+namespace envpot {
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+
+// Cartesian exponents of component c of a shell of angular momentum l,
+// x-major order: p = x, y, z; d = xx, xy, xz, yy, yz, zz.
+void cart(int l, int c, int e[3]) {
+    static const int8_t tab[3][6][3] = {
+        {{0, 0, 0}},
+        {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}},
+        {{2, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2}}};
+    for (int d = 0; d < 3; ++d) e[d] = tab[l][c][d];
+}
+
+double odd_fact(int n) {  // (n)!! for odd n >= -1
+    double r = 1.0;
+    while (n > 1) { r *= n; n -= 2; }
+    return r;
+}
+
+// Normalisation of x^i y^j z^k exp(-a r^2).
+double prim_norm(double a, const int e[3]) {
+    const int l = e[0] + e[1] + e[2];
+    return std::pow(2.0 * a / kPi, 0.75) * std::pow(4.0 * a, 0.5 * l) /
+           std::sqrt(odd_fact(2 * e[0] - 1) * odd_fact(2 * e[1] - 1) * odd_fact(2 * e[2] - 1));
+}
+
+// 1/sqrt(self-overlap) of a contracted component.
+double contraction_scale(int nprim, const double* ex, const double* co, const int e[3]) {
+    double s = 0.0;
+    for (int a = 0; a < nprim; ++a)
+        for (int b = 0; b < nprim; ++b) {
+            const double p = ex[a] + ex[b];
+            double m = std::pow(kPi / p, 1.5);
+            for (int d = 0; d < 3; ++d) m *= odd_fact(2 * e[d] - 1) / std::pow(2.0 * p, e[d]);
+            s += co[a] * co[b] * prim_norm(ex[a], e) * prim_norm(ex[b], e) * m;
+        }
+    return 1.0 / std::sqrt(s);
+}
+
+// Hermite expansion coefficients of one direction:
+//   x_A^i x_B^j exp(-a x_A^2 - b x_B^2) = sum_t E[i][j][t] Lambda_t(x; p, P).
+// First the column i = 0 is raised in j, then every column is raised in i:
+//   E^{i,j+1}_t = E^{ij}_{t-1}/(2p) + X_PB E^{ij}_t + (t+1) E^{ij}_{t+1}
+//   E^{i+1,j}_t = E^{ij}_{t-1}/(2p) + X_PA E^{ij}_t + (t+1) E^{ij}_{t+1}
+struct Ecoef { double v[3][3][5]; };
+
+void hermite_coefs(int li, int lj, double a, double b, double A, double B, Ecoef& E) {
+    std::memset(&E, 0, sizeof(E));
+    const double p = a + b, P = (a * A + b * B) / p;
+    const double xpa = P - A, xpb = P - B, h = 0.5 / p, dab = A - B;
+    E.v[0][0][0] = std::exp(-(a * b / p) * dab * dab);
+    auto get = [&](int i, int j, int t) -> double {
+        return (t < 0 || t > i + j) ? 0.0 : E.v[i][j][t];
+    };
+    for (int j = 0; j < lj; ++j)
+        for (int t = 0; t <= j + 1; ++t)
+            E.v[0][j + 1][t] = h * get(0, j, t - 1) + xpb * get(0, j, t) + (t + 1) * get(0, j, t + 1);
+    for (int i = 0; i < li; ++i)
+        for (int j = 0; j <= lj; ++j)
+            for (int t = 0; t <= i + j + 1; ++t)
+                E.v[i + 1][j][t] = h * get(i, j, t - 1) + xpa * get(i, j, t) + (t + 1) * get(i, j, t + 1);
+}
+
+struct Block {   // one unordered shell pair I <= J with its density block
+    int I, J;
+    double w[6][6];   // P_IJ x contraction scales x (2 if I != J)
+    double maxabs;
+};
+
+struct Bucket {  // pairs of one group and one L, appended in build order
+    std::vector<double> rec;  // per pair: Px, Py, Pz, p, D[ncomp(L)]
+    int64_t n = 0;
+};
+
+struct GroupOut {
+    Bucket b[kLMax + 1];
+    int64_t n_unscreened = 0;
+    double screened_bound = 0.0;
+    double dropped_charge = 0.0;  // electron count of screened-out pairs
+};
+
+bool finite(double x) { return std::isfinite(x); }
+
+}  // namespace
+
+env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
+                           const env_shell* shells, int32_t n_shells,
+                           const env_density* P, const env_options& opt, PairList& out) {
+    out = PairList();
+    if (n_nuclei < 0 || n_shells < 0 || !P) return ENV_E_ARG;
+    if ((n_nuclei > 0 && !nuclei) || (n_shells > 0 && !shells)) return ENV_E_ARG;
+    for (int a = 0; a < n_nuclei; ++a) {
+        const env_nucleus& q = nuclei[a];
+        if (!finite(q.xyz[0]) || !finite(q.xyz[1]) || !finite(q.xyz[2]) || !finite(q.Z))
+            return ENV_E_ARG;
+        if (q.fragment < -1 || q.reserved != 0) return ENV_E_ARG;
+    }
+    std::vector<int> bf0(n_shells + 1, 0);
+    for (int s = 0; s < n_shells; ++s) {
+        const env_shell& sh = shells[s];
+        if (sh.atom < 0 || sh.atom >= n_nuclei || sh.nprim < 1 || sh.reserved != 0 ||
+            !sh.exponents || !sh.coefs || sh.l < 0)
+            return ENV_E_ARG;
+        if (sh.l > 2) return ENV_E_UNSUPPORTED;
+        for (int k = 0; k < sh.nprim; ++k)
+            if (!(sh.exponents[k] > 0.0) || !finite(sh.exponents[k]) || !finite(sh.coefs[k]))
+                return ENV_E_ARG;
+        bf0[s + 1] = bf0[s] + ncart(sh.l);
+    }
+    const int nbf = bf0[n_shells];
+    if (P->nbf != nbf) return ENV_E_ARG;
+    if (P->format != ENV_DENSITY_DENSE && P->format != ENV_DENSITY_CSR) return ENV_E_ARG;
+    if (nbf > 0 && !P->values) return ENV_E_ARG;
+    if (P->format == ENV_DENSITY_CSR && (!P->row_ptr || (nbf > 0 && !P->col))) return ENV_E_ARG;
+    const double thr = opt.screen_threshold;
+    if (!(thr >= 0.0) || !finite(thr)) return ENV_E_ARG;
+    const bool screen = !(opt.flags & ENV_NO_SCREENING) && thr > 0.0;
+    out.nbf = nbf;
+
+    // fragment groups: sorted fragment ids (-1 included), cross group last
+    std::vector<int> ids;
+    for (int a = 0; a < n_nuclei; ++a) ids.push_back(nuclei[a].fragment);
+    std::sort(ids.begin(), ids.end());
+    ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
+    auto group_of_atom = [&](int a) {
+        return int(std::lower_bound(ids.begin(), ids.end(), nuclei[a].fragment) - ids.begin());
+    };
+    const int n_frag_groups = int(ids.size());
+
+    std::vector<int> shell_of_bf(nbf);
+    for (int s = 0; s < n_shells; ++s)
+        for (int k = bf0[s]; k < bf0[s + 1]; ++k) shell_of_bf[k] = s;
+
+    // contraction scales per shell component
+    std::vector<double> cscale(nbf);
+    for (int s = 0; s < n_shells; ++s)
+        for (int c = 0; c < ncart(shells[s].l); ++c) {
+            int e[3];
+            cart(shells[s].l, c, e);
+            cscale[bf0[s] + c] = contraction_scale(shells[s].nprim, shells[s].exponents,
+                                                   shells[s].coefs, e);
+        }
+
+    // density blocks of ordered shell pairs
+    std::unordered_map<uint64_t, int> bidx;
+    std::vector<std::array<double, 36>> raw;
+    std::vector<std::pair<int, int>> rawkey;
+    auto put = [&](int mu, int nu, double v) -> bool {
+        if (!finite(v)) return false;
+        if (v == 0.0) return true;
+        const int I = shell_of_bf[mu], J = shell_of_bf[nu];
+        const uint64_t key = (uint64_t(uint32_t(I)) << 32) | uint32_t(J);
+        auto it = bidx.find(key);
+        int k;
+        if (it == bidx.end()) {
+            k = int(raw.size());
+            bidx.emplace(key, k);
+            raw.emplace_back();
+            raw.back().fill(0.0);
+            rawkey.emplace_back(I, J);
+        } else {
+            k = it->second;
+        }
+        raw[k][(mu - bf0[I]) * 6 + (nu - bf0[J])] += v;
+        return true;
+    };
+    if (P->format == ENV_DENSITY_DENSE) {
+        for (int mu = 0; mu < nbf; ++mu)
+            for (int nu = 0; nu < nbf; ++nu)
+                if (!put(mu, nu, P->values[(size_t)mu * nbf + nu])) return ENV_E_ARG;
+    } else {
+        if (P->row_ptr[0] != 0) return ENV_E_ARG;
+        for (int mu = 0; mu < nbf; ++mu) {
+            if (P->row_ptr[mu + 1] < P->row_ptr[mu]) return ENV_E_ARG;
+            for (int64_t k = P->row_ptr[mu]; k < P->row_ptr[mu + 1]; ++k) {
+                const int nu = P->col[k];
+                if (nu < 0 || nu >= nbf) return ENV_E_ARG;
+                if (!put(mu, nu, P->values[k])) return ENV_E_ARG;
+            }
+        }
+    }
+    // symmetry: block (I,J) must equal the transpose of block (J,I)
+    auto blk = [&](int I, int J) -> const double* {
+        auto it = bidx.find((uint64_t(uint32_t(I)) << 32) | uint32_t(J));
+        return it == bidx.end() ? nullptr : raw[it->second].data();
+    };
+    static const double zero36[36] = {0};
+    std::vector<Block> blocks;
+    std::vector<int> block_group;
+    for (size_t k = 0; k < rawkey.size(); ++k) {
+        const int I = rawkey[k].first, J = rawkey[k].second;
+        const double* a = raw[k].data();
+        const double* b = blk(J, I);
+        if (!b) b = zero36;
+        const int nI = ncart(shells[I].l), nJ = ncart(shells[J].l);
+        for (int x = 0; x < nI; ++x)
+            for (int y = 0; y < nJ; ++y) {
+                const double u = a[x * 6 + y], v = b[y * 6 + x];
+                if (std::fabs(u - v) > 1e-10 * (std::fabs(u) + std::fabs(v))) return ENV_E_ARG;
+            }
+        if (I > J) continue;
+        Block B;
+        B.I = I;
+        B.J = J;
+        B.maxabs = 0.0;
+        std::memset(B.w, 0, sizeof(B.w));
+        const double f = (I == J) ? 1.0 : 2.0;
+        for (int x = 0; x < nI; ++x)
+            for (int y = 0; y < nJ; ++y) {
+                B.w[x][y] = f * a[x * 6 + y] * cscale[bf0[I] + x] * cscale[bf0[J] + y];
+                B.maxabs = std::max(B.maxabs, std::fabs(B.w[x][y]));
+            }
+        const int gI = group_of_atom(shells[I].atom), gJ = group_of_atom(shells[J].atom);
+        blocks.push_back(B);
+        block_group.push_back(gI == gJ ? gI : n_frag_groups);
+        if (gI != gJ) out.has_cross = true;
+    }
+    if (out.has_cross && (opt.flags & ENV_NEUTRALIZE)) return ENV_E_UNSUPPORTED;
+    const int n_groups = n_frag_groups + (out.has_cross ? 1 : 0);
+    out.n_groups = n_groups;
+
+    // blocks of each group in (I, J) order: deterministic pair order
+    std::vector<std::vector<int>> gblocks(n_groups);
+    {
+        std::vector<int> order(blocks.size());
+        for (size_t k = 0; k < order.size(); ++k) order[k] = int(k);
+        std::sort(order.begin(), order.end(), [&](int x, int y) {
+            if (blocks[x].I != blocks[y].I) return blocks[x].I < blocks[y].I;
+            return blocks[x].J < blocks[y].J;
+        });
+        for (int k : order) gblocks[block_group[k]].push_back(k);
+    }
+
+    std::vector<GroupOut> gout(n_groups);
+    const bool neutralize = (opt.flags & ENV_NEUTRALIZE) != 0;
+    auto work = [&](int g) {
+        GroupOut& go = gout[g];
+        Ecoef Ex, Ey, Ez;
+        double D[35];
+        for (int bk : gblocks[g]) {
+            const Block& B = blocks[bk];
+            const env_shell& SI = shells[B.I];
+            const env_shell& SJ = shells[B.J];
+            const double* A = nuclei[SI.atom].xyz;
+            const double* Bc = nuclei[SJ.atom].xyz;
+            const int lI = SI.l, lJ = SJ.l, L = lI + lJ, nc = kNComp[L];
+            const int nI = ncart(lI), nJ = ncart(lJ);
+            const double rab2 = (A[0] - Bc[0]) * (A[0] - Bc[0]) + (A[1] - Bc[1]) * (A[1] - Bc[1]) +
+                                (A[2] - Bc[2]) * (A[2] - Bc[2]);
+            int eI[6][3], eJ[6][3];
+            for (int c = 0; c < nI; ++c) cart(lI, c, eI[c]);
+            for (int c = 0; c < nJ; ++c) cart(lJ, c, eJ[c]);
+            for (int ia = 0; ia < SI.nprim; ++ia) {
+                for (int ib = (B.I == B.J ? ia : 0); ib < SJ.nprim; ++ib) {
+                    const double a = SI.exponents[ia], b = SJ.exponents[ib];
+                    const double ca = SI.coefs[ia], cb = SJ.coefs[ib];
+                    const double p = a + b, mu = a * b / p;
+                    const double w = (B.I == B.J && ia != ib) ? 2.0 : 1.0;
+                    ++go.n_unscreened;
+                    const double bound = std::fabs(ca * cb) * std::pow(4.0 * a * b / (kPi * kPi), 0.75) *
+                                         std::pow(kPi / p, 1.5) * std::exp(-mu * rab2);
+                    const bool drop = screen && bound < thr;
+                    if (drop) go.screened_bound += w * B.maxabs * bound;
+                    if (drop && !neutralize) continue;
+                    hermite_coefs(lI, lJ, a, b, A[0], Bc[0], Ex);
+                    hermite_coefs(lI, lJ, a, b, A[1], Bc[1], Ey);
+                    hermite_coefs(lI, lJ, a, b, A[2], Bc[2], Ez);
+                    if (drop) {  // only its charge: sum P N N c c E_0 E_0 E_0 (pi/p)^{3/2}
+                        double q = 0.0;
+                        for (int x = 0; x < nI; ++x)
+                            for (int y = 0; y < nJ; ++y)
+                                q += B.w[x][y] * prim_norm(a, eI[x]) * prim_norm(b, eJ[y]) *
+                                     Ex.v[eI[x][0]][eJ[y][0]][0] * Ey.v[eI[x][1]][eJ[y][1]][0] *
+                                     Ez.v[eI[x][2]][eJ[y][2]][0];
+                        go.dropped_charge += w * ca * cb * q * std::pow(kPi / p, 1.5);
+                        continue;
+                    }
+                    for (int k = 0; k < nc; ++k) D[k] = 0.0;
+                    for (int x = 0; x < nI; ++x) {
+                        const double na = prim_norm(a, eI[x]);
+                        for (int y = 0; y < nJ; ++y) {
+                            const double pw = B.w[x][y];
+                            if (pw == 0.0) continue;
+                            const double f = w * pw * ca * cb * na * prim_norm(b, eJ[y]);
+                            const int ix = eI[x][0], jx = eJ[y][0], iy = eI[x][1], jy = eJ[y][1],
+                                      iz = eI[x][2], jz = eJ[y][2];
+                            for (int t = 0; t <= ix + jx; ++t) {
+                                const double ft = f * Ex.v[ix][jx][t];
+                                for (int u = 0; u <= iy + jy; ++u) {
+                                    const double fu = ft * Ey.v[iy][jy][u];
+                                    for (int v = 0; v <= iz + jz; ++v)
+                                        D[hermite_index(L, t, u, v)] += fu * Ez.v[iz][jz][v];
+                                }
+                            }
+                        }
+                    }
+                    const double sc = std::pow(kPi / p, 1.5);
+                    Bucket& bu = go.b[L];
+                    bu.rec.push_back((a * A[0] + b * Bc[0]) / p);
+                    bu.rec.push_back((a * A[1] + b * Bc[1]) / p);
+                    bu.rec.push_back((a * A[2] + b * Bc[2]) / p);
+                    bu.rec.push_back(p);
+                    for (int k = 0; k < nc; ++k) bu.rec.push_back(D[k] * sc);
+                    ++bu.n;
+                }
+            }
+        }
+    };
+    {
+        unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        nt = std::min<unsigned>(nt, std::max(1, n_groups));
+        std::vector<std::thread> th;
+        std::atomic<int> next{0};
+        for (unsigned t = 0; t < nt; ++t)
+            th.emplace_back([&]() {
+                for (;;) {
+                    const int g = next.fetch_add(1);
+                    if (g >= n_groups) break;
+                    work(g);
+                }
+            });
+        for (auto& t : th) t.join();
+    }
+
+    // nuclei by group (Z == 0 centres carry basis functions only)
+    std::vector<double> zg(n_groups, 0.0);
+    out.group_nuc_begin.assign(n_groups, 0);
+    out.group_nuc_end.assign(n_groups, 0);
+    for (int g = 0; g < n_frag_groups; ++g) {
+        out.group_nuc_begin[g] = int(out.nuc.size() / 4);
+        for (int a = 0; a < n_nuclei; ++a) {
+            if (group_of_atom(a) != g || nuclei[a].Z == 0.0) continue;
+            out.nuc.push_back(nuclei[a].xyz[0]);
+            out.nuc.push_back(nuclei[a].xyz[1]);
+            out.nuc.push_back(nuclei[a].xyz[2]);
+            out.nuc.push_back(nuclei[a].Z);
+            zg[g] += nuclei[a].Z;
+            out.nuclear_charge += nuclei[a].Z;
+        }
+        out.group_nuc_end[g] = int(out.nuc.size() / 4);
+    }
+    if (out.has_cross) {
+        out.group_nuc_begin[n_frag_groups] = out.group_nuc_end[n_frag_groups] = int(out.nuc.size() / 4);
+    }
+
+    // neutralise: scale the Hermite densities of each group so that its
+    // electron count tr(P_f S_f) (screened-out pairs included) equals its
+    // nuclear charge
+    if (neutralize) {
+        for (int g = 0; g < n_groups; ++g) {
+            double q = gout[g].dropped_charge;
+            for (int L = 0; L <= kLMax; ++L) {
+                const Bucket& bu = gout[g].b[L];
+                const int rw = 4 + kNComp[L];
+                for (int64_t k = 0; k < bu.n; ++k) q += bu.rec[k * rw + 4];
+            }
+            if (q == 0.0) continue;
+            const double s = zg[g] / q;
+            for (int L = 0; L <= kLMax; ++L) {
+                Bucket& bu = gout[g].b[L];
+                const int rw = 4 + kNComp[L];
+                for (int64_t k = 0; k < bu.n; ++k)
+                    for (int c = 0; c < kNComp[L]; ++c) bu.rec[k * rw + 4 + c] *= s;
+            }
+        }
+    }
+
+    // final order: group, then L
+    out.group_pair_begin.assign(n_groups + 1, 0);
+    for (int g = 0; g < n_groups; ++g) {
+        out.group_pair_begin[g] = int64_t(out.L.size());
+        out.n_unscreened += gout[g].n_unscreened;
+        out.screened_bound += gout[g].screened_bound;
+        for (int L = 0; L <= kLMax; ++L) {
+            const Bucket& bu = gout[g].b[L];
+            const int rw = 4 + kNComp[L];
+            for (int64_t k = 0; k < bu.n; ++k) {
+                const double* r = &bu.rec[k * rw];
+                out.L.push_back(L);
+                out.group.push_back(g);
+                out.center.insert(out.center.end(), r, r + 3);
+                out.p.push_back(r[3]);
+                const size_t d0 = out.D.size();
+                out.D.resize(d0 + 35, 0.0);
+                for (int c = 0; c < kNComp[L]; ++c) out.D[d0 + c] = r[4 + c];
+                out.electrons += r[4];
+            }
+        }
+    }
+    out.group_pair_begin[n_groups] = int64_t(out.L.size());
+    return ENV_OK;
+}
+
+// ------------------------------------------------------------- segments
+
+namespace {
+// Estimated relative cost of one point-pair by L and of one point-nucleus.
+const double kCost32[kLMax + 1] = {1.0, 1.5, 2.6, 4.4, 7.5};
+const double kCost64[kLMax + 1] = {1.0, 1.4, 2.3, 3.8, 6.3};
+const double kCostNuc = 0.6;
+}  // namespace
+
+void build_segments(const PairList& pl, int S, bool fp64, std::vector<Segment>& segs,
+                    std::vector<int32_t>& split) {
+    const double* w = fp64 ? kCost64 : kCost32;
+    // base segments: one per (group, L) run, nuclei on the group's first one
+    std::vector<Segment> base;
+    int64_t word = 0;
+    for (int g = 0; g < pl.n_groups; ++g) {
+        const int64_t b = pl.group_pair_begin[g], e = pl.group_pair_begin[g + 1];
+        const size_t first = base.size();
+        int64_t k = b;
+        for (int L = 0; L <= kLMax; ++L) {
+            int64_t m = k;
+            while (m < e && pl.L[m] == L) ++m;
+            if (m > k) {
+                Segment s{};
+                s.L = L;
+                s.n_pairs = int32_t(m - k);
+                s.rec_off = word;
+                word += (m - k) * (fp64 ? rec64_words(L) : rec32_words(L));
+                base.push_back(s);
+            }
+            k = m;
+        }
+        const int nb = pl.group_nuc_begin[g], ne = pl.group_nuc_end[g];
+        if (base.size() == first && ne > nb) {
+            Segment s{};
+            s.L = 0;
+            s.rec_off = word;
+            base.push_back(s);
+        }
+        if (base.size() > first) {
+            base[first].nuc_begin = nb;
+            base[first].nuc_end = ne;
+            base.back().flags |= kSegEndGroup;
+        }
+    }
+    double total = 0.0;
+    for (const Segment& s : base) total += s.n_pairs * w[s.L] + (s.nuc_end - s.nuc_begin) * kCostNuc;
+    segs.clear();
+    split.assign(1, 0);
+    const double target = total / S;
+    double acc = 0.0;
+    int cur = 0;
+    for (Segment rem : base) {
+        double nucc = (rem.nuc_end - rem.nuc_begin) * kCostNuc;
+        for (;;) {
+            const double cost = nucc + rem.n_pairs * w[rem.L];
+            const double boundary = (cur + 1) * target;
+            if (cur < S - 1 && rem.n_pairs > 0 && acc + cost > boundary) {
+                int64_t k = int64_t(std::floor((boundary - acc - nucc) / w[rem.L]));
+                k = std::max<int64_t>(0, std::min<int64_t>(k, rem.n_pairs));
+                if (k > 0 || nucc > 0) {
+                    Segment a = rem;
+                    a.n_pairs = int32_t(k);
+                    a.flags = 0;
+                    segs.push_back(a);
+                }
+                acc += nucc + k * w[rem.L];
+                rem.rec_off += k * (fp64 ? rec64_words(rem.L) : rec32_words(rem.L));
+                rem.n_pairs -= int32_t(k);
+                rem.nuc_begin = rem.nuc_end;
+                nucc = 0.0;
+                split.push_back(int32_t(segs.size()));
+                ++cur;
+                continue;
+            }
+            if (rem.n_pairs > 0 || rem.nuc_end > rem.nuc_begin || (rem.flags & kSegEndGroup))
+                segs.push_back(rem);
+            acc += cost;
+            break;
+        }
+    }
+    while (int(split.size()) < S + 1) split.push_back(int32_t(segs.size()));
+}
+
+void pack_records(const PairList& pl, bool fp64, std::vector<uint32_t>& rec,
+                  std::vector<int64_t>& /*unused*/) {
+    rec.clear();
+    const int64_t n = int64_t(pl.L.size());
+    for (int64_t k = 0; k < n; ++k) {
+        const int L = pl.L[k];
+        const double p = pl.p[k];
+        const double c1 = 2.0 * std::sqrt(p / kPi);
+        const double* D = &pl.D[35 * k];
+        const size_t o = rec.size();
+        if (fp64) {
+            rec.resize(o + rec64_words(L), 0u);
+            double* r = reinterpret_cast<double*>(&rec[o]);
+            r[0] = pl.center[3 * k];
+            r[1] = pl.center[3 * k + 1];
+            r[2] = pl.center[3 * k + 2];
+            r[3] = p;
+            r[4] = c1;
+            for (int c = 0; c < kNComp[L]; ++c) r[5 + c] = D[c];
+        } else {
+            rec.resize(o + rec32_words(L), 0u);
+            double* r = reinterpret_cast<double*>(&rec[o]);
+            r[0] = pl.center[3 * k];
+            r[1] = pl.center[3 * k + 1];
+            r[2] = pl.center[3 * k + 2];
+            float* f = reinterpret_cast<float*>(&rec[o + 6]);
+            f[0] = float(p);
+            f[1] = float(c1);
+            for (int c = 0; c < kNComp[L]; ++c) f[2 + c] = float(D[c]);
+        }
+    }
+}
+
+// ------------------------------------------------------------ Boys tables
+
+namespace {
+
+// F_n(T), n = 0..nmax, in long double: F_N for a high order N by its power
+// series, then the stable downward recursion F_n = (2T F_{n+1} + e^{-T})/(2n+1).
+void boys_ld(int nmax, long double T, long double* F) {
+    const int N = nmax + 30;
+    long double term = 1.0L / (2 * N + 1), sum = term;
+    for (int i = 1; i < 4000; ++i) {
+        term *= 2.0L * T / (2 * N + 2 * i + 1);
+        sum += term;
+        if (term < 1e-22L * sum) break;
+    }
+    const long double e = expl(-T);
+    long double f = e * sum;
+    for (int n = N - 1; n >= 0; --n) {
+        f = (2.0L * T * f + e) / (2 * n + 1);
+        if (n <= nmax) F[n] = f;
+    }
+}
+
+long double boys_asym(int n, long double T) {
+    long double df = 1.0L;
+    for (int k = 2 * n - 1; k > 1; k -= 2) df *= k;
+    return df / powl(2.0L, n + 1) * sqrtl(3.14159265358979323846264338327950288L / powl(T, 2 * n + 1));
+}
+
+// Smallest grid T (multiple of 1/8) beyond which the asymptotic form of
+// F_0..F_L is within eps (relative) of the exact value.
+double far_threshold(int L, long double eps) {
+    long double F[16];
+    int last_bad = 0;
+    for (int k = 1; k <= 8 * 120; ++k) {
+        const long double T = k / 8.0L;
+        boys_ld(L, T, F);
+        for (int n = 0; n <= L; ++n)
+            if (fabsl(F[n] - boys_asym(n, T)) > eps * F[n]) last_bad = k;
+    }
+    return (last_bad + 1) / 8.0;
+}
+
+}  // namespace
+
+void build_boys_tables(std::vector<float>& t32, std::vector<double>& t64, BoysParams& bp) {
+    std::memset(&bp, 0, sizeof(bp));
+    double max32 = 0.0, max64 = 0.0;
+    for (int L = 0; L <= kLMax; ++L) {
+        bp.tfar32[L] = float(far_threshold(L, 0x1p-28L));
+        bp.tfar64[L] = far_threshold(L, 0x1p-56L);
+        max32 = std::max(max32, double(bp.tfar32[L]));
+        max64 = std::max(max64, bp.tfar64[L]);
+    }
+    bp.rows32 = int(max32 * kBoysGridInv) + 2;
+    bp.rows64 = int(max64 * kBoysGridInv) + 2;
+    t32.assign(size_t(bp.rows32) * kBoysRowF32, 0.0f);
+    t64.assign(size_t(bp.rows64) * kBoysRowF64, 0.0);
+    long double F[16];
+    for (int k = 0; k < bp.rows32; ++k) {
+        boys_ld(kLMax + kBoysTaylorF32 - 1, k / (long double)kBoysGridInv, F);
+        for (int n = 0; n < kLMax + kBoysTaylorF32; ++n) t32[size_t(k) * kBoysRowF32 + n] = float(F[n]);
+    }
+    for (int k = 0; k < bp.rows64; ++k) {
+        boys_ld(kLMax + kBoysTaylorF64 - 1, k / (long double)kBoysGridInv, F);
+        for (int n = 0; n < kLMax + kBoysTaylorF64; ++n) t64[size_t(k) * kBoysRowF64 + n] = double(F[n]);
+    }
+}
+
+}  // namespace envpot

@@ -1,0 +1,287 @@
+"""ctypes binding of ``libenvpot.so`` (C ABI in include/env_potential.h).
+
+Argument marshalling only: every step of the potential runs in the library's
+gfx950 kernels.  The binding refuses to work without the built library; there
+is no Python or CPU fallback.
+
+Functions with the C names take raw pointers and sizes; ``Environment`` wraps
+them for numpy inputs and torch device tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int32, c_int64, c_uint32, c_void_p
+from typing import Optional, Sequence
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libenvpot.so")
+
+ENV_OK = 0
+ENV_E_ARG = -1
+ENV_E_UNSUPPORTED = -2
+ENV_E_NOMEM = -3
+ENV_E_DEVICE = -4
+ENV_E_STATE = -5
+
+ENV_PREC_FP64 = 0
+ENV_PREC_FP32C = 1
+
+ENV_BUILD_ONLY = 0x1
+ENV_NEUTRALIZE = 0x2
+ENV_NO_SCREENING = 0x4
+
+ENV_DENSITY_DENSE = 0
+ENV_DENSITY_CSR = 1
+
+PRECISIONS = {"fp64": ENV_PREC_FP64, "fp32c": ENV_PREC_FP32C}
+NCOMP = (1, 4, 10, 20, 35)
+
+
+class env_nucleus(ctypes.Structure):
+    _fields_ = [("xyz", c_double * 3), ("Z", c_double), ("fragment", c_int32),
+                ("reserved", c_int32)]
+
+
+class env_shell(ctypes.Structure):
+    _fields_ = [("atom", c_int32), ("l", c_int32), ("nprim", c_int32), ("reserved", c_int32),
+                ("exponents", POINTER(c_double)), ("coefs", POINTER(c_double))]
+
+
+class env_density(ctypes.Structure):
+    _fields_ = [("nbf", c_int32), ("format", c_int32), ("values", POINTER(c_double)),
+                ("row_ptr", POINTER(c_int64)), ("col", POINTER(c_int32))]
+
+
+class env_options(ctypes.Structure):
+    _fields_ = [("precision", c_int32), ("device", c_int32), ("screen_threshold", c_double),
+                ("flags", c_uint32), ("reserved", c_int32 * 3)]
+
+
+class env_info(ctypes.Structure):
+    _fields_ = [("nbf", c_int32), ("n_nuclei", c_int32), ("n_groups", c_int32),
+                ("n_segments", c_int32), ("n_pairs", c_int64), ("n_pairs_by_L", c_int64 * 5),
+                ("n_pairs_unscreened", c_int64), ("electrons", c_double),
+                ("nuclear_charge", c_double), ("screened_bound", c_double),
+                ("device_bytes", c_int64), ("precision", c_int32),
+                ("built_on_device", c_int32)]
+
+
+class EnvError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {env_status_string(status)} ({status})")
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built: run paper_1011_4687_amd.build.build() "
+                              "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        L.env_options_default.argtypes = [POINTER(env_options)]
+        L.env_options_default.restype = None
+        L.env_status_string.argtypes = [c_int32]
+        L.env_status_string.restype = ctypes.c_char_p
+        L.env_potential_create.argtypes = [POINTER(env_nucleus), c_int32, POINTER(env_shell),
+                                           c_int32, POINTER(env_density), POINTER(env_options),
+                                           POINTER(c_void_p)]
+        L.env_potential_create.restype = c_int32
+        L.env_potential_eval.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]
+        L.env_potential_eval.restype = c_int32
+        L.env_potential_eval_batched.argtypes = [POINTER(c_void_p), c_int32, POINTER(c_void_p),
+                                                 POINTER(c_int64), POINTER(c_void_p), c_void_p]
+        L.env_potential_eval_batched.restype = c_int32
+        L.env_potential_info.argtypes = [c_void_p, POINTER(env_info)]
+        L.env_potential_info.restype = c_int32
+        L.env_potential_export_pairs.argtypes = [c_void_p, c_int64, POINTER(c_int32),
+                                                 POINTER(c_int32), POINTER(c_double),
+                                                 POINTER(c_double), POINTER(c_double)]
+        L.env_potential_export_pairs.restype = c_int32
+        L.env_potential_destroy.argtypes = [c_void_p]
+        L.env_potential_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+# ------------------------------------------------------------ C-named calls
+
+def env_status_string(status: int) -> str:
+    return lib().env_status_string(int(status)).decode()
+
+
+def env_options_default() -> env_options:
+    o = env_options()
+    lib().env_options_default(ctypes.byref(o))
+    return o
+
+
+def env_potential_create(nuclei, n_nuclei, shells, n_shells, density, options) -> int:
+    """Returns the handle (an integer address); raises EnvError on failure."""
+    h = c_void_p()
+    st = lib().env_potential_create(nuclei, int(n_nuclei), shells, int(n_shells),
+                                    ctypes.byref(density), ctypes.byref(options),
+                                    ctypes.byref(h))
+    if st != ENV_OK:
+        raise EnvError(st, "env_potential_create")
+    return h.value
+
+
+def env_potential_eval(handle: int, points_ptr: int, n: int, out_ptr: int,
+                       stream: int = 0) -> None:
+    st = lib().env_potential_eval(c_void_p(handle), c_void_p(points_ptr), int(n),
+                                  c_void_p(out_ptr), c_void_p(stream))
+    if st != ENV_OK:
+        raise EnvError(st, "env_potential_eval")
+
+
+def env_potential_eval_batched(handles: Sequence[int], points_ptrs: Sequence[int],
+                               ns: Sequence[int], out_ptrs: Sequence[int],
+                               stream: int = 0) -> None:
+    k = len(handles)
+    H = (c_void_p * k)(*handles)
+    Pp = (c_void_p * k)(*points_ptrs)
+    N = (c_int64 * k)(*[int(x) for x in ns])
+    O = (c_void_p * k)(*out_ptrs)
+    st = lib().env_potential_eval_batched(H, k, Pp, N, O, c_void_p(stream))
+    if st != ENV_OK:
+        raise EnvError(st, "env_potential_eval_batched")
+
+
+def env_potential_info(handle: int) -> env_info:
+    info = env_info()
+    st = lib().env_potential_info(c_void_p(handle), ctypes.byref(info))
+    if st != ENV_OK:
+        raise EnvError(st, "env_potential_info")
+    return info
+
+
+def env_potential_destroy(handle: int) -> None:
+    if handle:
+        lib().env_potential_destroy(c_void_p(handle))
+
+
+# -------------------------------------------------------------- wrapper
+
+def _dp(a):
+    return a.ctypes.data_as(POINTER(c_double))
+
+
+class Environment:
+    """One environment uploaded to the device (or built on the host only).
+
+    xyz (K,3), Z (K,), fragment (K,) describe the nuclei; shells is a list of
+    (atom, l, exponents, coefs); P is a dense (nbf,nbf) array or a CSR
+    triple (row_ptr, col, values)."""
+
+    def __init__(self, xyz, Z, fragment, shells, P, precision: str = "fp32c",
+                 device: int = -1, screen_threshold: float = 1e-12,
+                 neutralize: bool = False, build_only: bool = False,
+                 screening: bool = True):
+        self.handle = 0
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+        K = xyz.shape[0]
+        Z = np.ascontiguousarray(Z, dtype=np.float64).reshape(K)
+        frag = np.ascontiguousarray(fragment, dtype=np.int32).reshape(K)
+        nuc = (env_nucleus * max(K, 1))()
+        for a in range(K):
+            nuc[a].xyz[0], nuc[a].xyz[1], nuc[a].xyz[2] = xyz[a]
+            nuc[a].Z = Z[a]
+            nuc[a].fragment = int(frag[a])
+        self._keep = []
+        sh = (env_shell * max(len(shells), 1))()
+        for s, (atom, l, ex, co) in enumerate(shells):
+            ex = np.ascontiguousarray(ex, dtype=np.float64)
+            co = np.ascontiguousarray(co, dtype=np.float64)
+            self._keep += [ex, co]
+            sh[s].atom, sh[s].l, sh[s].nprim = int(atom), int(l), int(ex.shape[0])
+            sh[s].exponents, sh[s].coefs = _dp(ex), _dp(co)
+        nbf = int(sum((l + 1) * (l + 2) // 2 for (_, l, _, _) in shells))
+        dens = env_density()
+        dens.nbf = nbf
+        if isinstance(P, tuple):
+            rowp, col, val = P
+            rowp = np.ascontiguousarray(rowp, dtype=np.int64)
+            col = np.ascontiguousarray(col, dtype=np.int32)
+            val = np.ascontiguousarray(val, dtype=np.float64)
+            self._keep += [rowp, col, val]
+            dens.format = ENV_DENSITY_CSR
+            dens.values = _dp(val)
+            dens.row_ptr = rowp.ctypes.data_as(POINTER(c_int64))
+            dens.col = col.ctypes.data_as(POINTER(c_int32))
+        else:
+            Pd = np.ascontiguousarray(P, dtype=np.float64)
+            self._keep.append(Pd)
+            dens.format = ENV_DENSITY_DENSE
+            dens.values = _dp(Pd)
+        opt = env_options_default()
+        opt.precision = PRECISIONS[precision]
+        opt.device = int(device)
+        opt.screen_threshold = float(screen_threshold)
+        opt.flags = ((ENV_NEUTRALIZE if neutralize else 0) | (ENV_BUILD_ONLY if build_only else 0)
+                     | (0 if screening else ENV_NO_SCREENING))
+        self.precision = precision
+        self.handle = env_potential_create(nuc, K, sh, len(shells), dens, opt)
+        self._keep = None
+
+    @classmethod
+    def from_synth(cls, env, scale=None, **kw) -> "Environment":
+        shells = [(s.atom, s.l, s.exponents, s.coefs) for s in env.shells]
+        return cls(env.xyz, env.Z, env.fragment, shells, env.density_csr(scale), **kw)
+
+    def info(self) -> dict:
+        i = env_potential_info(self.handle)
+        d = {f: getattr(i, f) for f, _ in env_info._fields_}
+        d["n_pairs_by_L"] = list(i.n_pairs_by_L)
+        return d
+
+    def export_pairs(self):
+        """(L, group, center[n,3], p, D[n,35]) of a build-only handle."""
+        n = self.info()["n_pairs"]
+        L = np.zeros(max(n, 1), dtype=np.int32)
+        g = np.zeros(max(n, 1), dtype=np.int32)
+        c = np.zeros((max(n, 1), 3))
+        p = np.zeros(max(n, 1))
+        D = np.zeros((max(n, 1), 35))
+        st = lib().env_potential_export_pairs(
+            c_void_p(self.handle), max(n, 1), L.ctypes.data_as(POINTER(c_int32)),
+            g.ctypes.data_as(POINTER(c_int32)), _dp(c), _dp(p), _dp(D))
+        if st != ENV_OK:
+            raise EnvError(st, "env_potential_export_pairs")
+        return L[:n], g[:n], c[:n], p[:n], D[:n]
+
+    def eval(self, points, out=None, stream=None):
+        """V at a (n,3) float64 torch CUDA tensor; returns a (n,) tensor."""
+        import torch
+        if not (isinstance(points, torch.Tensor) and points.is_cuda):
+            raise TypeError("points must be a torch CUDA tensor")
+        if points.dtype != torch.float64 or points.dim() != 2 or points.shape[1] != 3:
+            raise TypeError("points must be float64 of shape (n, 3)")
+        points = points.contiguous()
+        n = points.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=points.device)
+        if out.dtype != torch.float64 or out.numel() != n or not out.is_contiguous():
+            raise TypeError("out must be a contiguous float64 tensor of n elements")
+        if stream is None:
+            stream = torch.cuda.current_stream(points.device)
+        env_potential_eval(self.handle, points.data_ptr(), n, out.data_ptr(),
+                           stream.cuda_stream)
+        return out
+
+    def close(self):
+        if self.handle:
+            env_potential_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

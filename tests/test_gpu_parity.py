@@ -1,0 +1,98 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+FP64 path: |V_gpu - V_oracle(screened)| <= 1e-12 A(r), A(r) = V_nuc + sum|terms|
+FP32C path: |V_gpu - V_oracle(full)| <= 1e-5 hartree (absolute)."""
+import numpy as np
+import pytest
+
+from common import sample_indices, workload_scaled
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+FP64_REL = 1e-12
+
+
+def _env(name, precision, n_points=None, screening=True):
+    from paper_1011_4687_amd.envpot import Environment
+    env, pts, P, _ = workload_scaled(name, n_points)
+    shells = [(s.atom, s.l, s.exponents, s.coefs) for s in env.shells]
+    return Environment(env.xyz, env.Z, env.fragment, shells, P, precision=precision,
+                       screening=screening), env, pts, P
+
+
+def _gpu(E, pts):
+    import torch
+    x = torch.from_numpy(np.ascontiguousarray(pts)).cuda()
+    v = E.eval(x)
+    torch.cuda.synchronize()
+    return v.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_tiny_all_points(precision):
+    from oracle import oracle as O
+    print(f"[parity] tiny {precision}", flush=True)
+    E, env, pts, P = _env("tiny", precision, screening=False)
+    V = _gpu(E, pts)
+    Vo, Vn, Ve, A = O.potential(env, pts, P=P, screen=False)
+    err = np.abs(V - Vo)
+    if precision == "fp64":
+        assert np.all(err <= FP64_REL * A), (err / A).max()
+    else:
+        assert err.max() <= FP32_TOL, err.max()
+    E.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_mid_full_size_sampled(precision):
+    """The mid workload at its full size (131072 points, the benchmark's
+    launch configuration); the oracle checks 40 sampled points."""
+    from oracle import oracle as O
+    print(f"[parity] mid {precision}", flush=True)
+    E, env, pts, P = _env("mid", precision)
+    V = _gpu(E, pts)
+    idx = sample_indices(len(pts), 40)
+    if precision == "fp64":
+        Vo, _, _, A = O.potential(env, pts[idx], P=P, screen=True)
+        assert np.all(np.abs(V[idx] - Vo) <= FP64_REL * A), (np.abs(V[idx] - Vo) / A).max()
+    else:
+        Vo, _, _, A = O.potential(env, pts[idx], P=P, screen=False)
+        assert np.abs(V[idx] - Vo).max() <= FP32_TOL
+    E.close()
+
+
+@pytest.mark.parametrize("n", [1, 63, 255, 257, 1000, 4097])
+def test_ragged_sizes(n):
+    """Point counts that leave ragged tails in the last wave/block and that
+    select different split factors."""
+    from oracle import oracle as O
+    print(f"[parity] ragged n={n}", flush=True)
+    E64, env, pts, P = _env("tiny", "fp64", n_points=n, screening=False)
+    E32, _, _, _ = _env("tiny", "fp32c", n_points=n, screening=False)
+    V64 = _gpu(E64, pts)
+    V32 = _gpu(E32, pts)
+    Vo, _, _, A = O.potential(env, pts, P=P, screen=False)
+    assert np.all(np.abs(V64 - Vo) <= FP64_REL * A)
+    assert np.abs(V32 - Vo).max() <= FP32_TOL
+    E64.close()
+    E32.close()
+
+
+def test_zero_points_and_determinism():
+    import torch
+    E, env, pts, P = _env("tiny", "fp32c", screening=False)
+    x = torch.from_numpy(pts).cuda()
+    out = torch.full((0,), 1.0, dtype=torch.float64, device="cuda")
+    E.eval(x[:0], out=out)
+    a = E.eval(x).cpu().numpy()
+    b = E.eval(x).cpu().numpy()
+    assert np.array_equal(a, b)
+    E.close()
+
+
+def test_point_on_nucleus_is_inf():
+    E, env, pts, P = _env("tiny", "fp64", screening=False)
+    V = _gpu(E, env.xyz[:3])
+    assert np.all(np.isposinf(V))
+    E.close()
