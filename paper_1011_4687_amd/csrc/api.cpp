@@ -181,8 +181,7 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
         return ENV_OK;
     }
     std::vector<uint32_t> rec;
-    std::vector<int64_t> unused;
-    pack_records(pl, fp64, rec, unused);
+    pack_records(pl, fp64, h->bp, rec);
     {
         DeviceGuard g(device);
         hipDeviceProp_t prop;
@@ -217,12 +216,12 @@ env_status env_potential_eval(env_potential* h, const double* points, int64_t n,
     if (!h->on_device) return ENV_E_STATE;
     DeviceGuard g(h->device);
     const bool fp64 = h->precision == ENV_PREC_FP64;
-    int np = env_int("ENVPOT_NP", fp64 ? 1 : 2);
-    if (np != 1 && np != 2 && np != 4) np = fp64 ? 1 : 2;
+    int np = env_int("ENVPOT_NP", fp64 ? 2 : 4);
+    if (np != 1 && np != 2 && np != 4) np = fp64 ? 2 : 4;
     if (fp64 && np == 4) np = 2;
-    // split factor: enough waves for ~4 per SIMD
+    // split factor: enough waves to keep ~24 per SIMD in flight over the run
     const int64_t waves = (n + 64 * np - 1) / (64 * np);
-    const int64_t want = int64_t(h->cu_count) * 16;
+    const int64_t want = int64_t(h->cu_count) * 4 * 24;
     int k = 0;
     while (k < kMaxSplitLog2 && waves * (int64_t(1) << k) < want) ++k;
     const int forced = env_int("ENVPOT_SPLIT_LOG2", -1);

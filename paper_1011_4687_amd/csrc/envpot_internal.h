@@ -37,12 +37,16 @@ constexpr int hermite_index(int L, int t, int u, int v) {
 }
 
 // Pair-record sizes in 4-byte words.
-//  FP32C record: Px, Py, Pz (double), p, c1 = 2 sqrt(p/pi) (float), D[ncomp] (float)
-//  FP64  record: Px, Py, Pz, p, c1 (double), D[ncomp] (double)
-// D is the Hermite density scaled by (pi/p)^{3/2}.  Records are padded to an
-// even number of words so that every double is 8-byte aligned.
-constexpr int rec32_words(int L) { return ((6 + 2 + kNComp[L]) + 1) & ~1; }
-constexpr int rec64_words(int L) { return 2 * (5 + kNComp[L]); }
+//  FP32C record: Px, Py, Pz (double); r2far, p, c1 (float); h[ncomp], D[ncomp] (float)
+//  FP64  record: Px, Py, Pz, r2far, p, c1 (double); h[ncomp], D[ncomp] (double)
+// D is the Hermite density scaled by (pi/p)^{3/2}; c1 = 2 sqrt(p/pi);
+// r2far = tfar[L]/p is the squared distance beyond which the far-field form
+// applies; h are the far-field polynomial coefficients (see far_coefs).
+// Records are padded to an even number of words (8-byte aligned doubles).
+constexpr int rec32_words(int L) { return ((9 + 2 * kNComp[L]) + 1) & ~1; }
+constexpr int rec64_words(int L) { return 2 * (6 + 2 * kNComp[L]); }
+constexpr int kRec32Head = 9;   // words before h in an FP32C record
+constexpr int kRec64Head = 6;   // doubles before h in an FP64 record
 
 // A run of pairs of one L inside one fragment group, plus (on the group's
 // first segment) the group's nuclei.
@@ -106,9 +110,14 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
 void build_segments(const PairList& pl, int S, bool fp64, std::vector<Segment>& segs,
                     std::vector<int32_t>& split);
 
+// Far-field coefficients: for X = P - C with p |X|^2 >= tfar[L],
+//   sum_tuv D_tuv d^t_X d^u_Y d^v_Z (1/|X|) = (1/|X|) sum_abc h_abc x^a y^b z^c,
+//   x = X/|X|^2, y = Y/|X|^2, z = Z/|X|^2   (both in the hermite_index order).
+void far_coefs(int L, const double* D, double* h);
+
 // Pack the records of one precision.
-void pack_records(const PairList& pl, bool fp64, std::vector<uint32_t>& rec,
-                  std::vector<int64_t>& rec_off_of_pair_L_start);
+void pack_records(const PairList& pl, bool fp64, const BoysParams& bp,
+                  std::vector<uint32_t>& rec);
 
 // Boys tables (host FP64/long double) and the far-field thresholds.
 void build_boys_tables(std::vector<float>& t32, std::vector<double>& t64, BoysParams& bp);

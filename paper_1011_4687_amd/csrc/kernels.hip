@@ -12,11 +12,13 @@
 //
 // Per point-pair (FP32C path):
 //   X = (float)(P - C) in FP64 (exact difference, one rounding),
-//   T = p |X|^2,
-//   Boys G_n: far field (T >= tfar[L]) G_n = (-1)^n (2n-1)!! |X|^{-2n-1}
-//   from a refined v_rsq_f32; near field a 6-term Taylor step from the
-//   tabulated F_n(k/8) held in LDS, scaled by 2 sqrt(p/pi) (-2p)^n,
-//   McMurchie-Davidson R_tuv recursion and contraction with the pair's
+//   far field (p |X|^2 >= tfar[L], where the Boys function equals its
+//   asymptote to below 2^-28): the pair is an exact finite multipole,
+//   evaluated as (1/R) sum h_abc x^a y^b z^c with x = X/R^2 (one refined
+//   v_rsq_f32 and a Horner polynomial, hermite_gen.h);
+//   near field: T = p |X|^2, Boys F_n by a 6-term Taylor step from the
+//   tabulated F_n(k/8) held in LDS, G_n = 2 sqrt(p/pi) (-2p)^n F_n, the
+//   McMurchie-Davidson R_tuv recursion and its contraction with the pair's
 //   Hermite density (hermite_gen.h),
 //   FP32 sums over tiles of kTile pairs, promoted to FP64 per tile.
 // The nuclear term and the per-fragment (nuclear - electronic) sums are FP64.
@@ -50,105 +52,214 @@ __device__ __forceinline__ float rsqrt_refined(float x) {
     return __builtin_fmaf(0.5f * e, y, y);
 }
 
+template <int L, typename T>
+__device__ __forceinline__ T far_poly(const T* __restrict__ h, T x, T y, T z) {
+    if constexpr (L == 0) return far_poly_L0<T>(h, x, y, z);
+    else if constexpr (L == 1) return far_poly_L1<T>(h, x, y, z);
+    else if constexpr (L == 2) return far_poly_L2<T>(h, x, y, z);
+    else if constexpr (L == 3) return far_poly_L3<T>(h, x, y, z);
+    else return far_poly_L4<T>(h, x, y, z);
+}
+
+// The part of a record every point needs: centre, far-field radius^2 and
+// far-field coefficients.  The loop below loads pair i+1's head while it
+// computes pair i, so the scalar-load latency overlaps the arithmetic.
+template <int L, typename T>
+struct Head {
+    double px, py, pz;
+    T r2far;
+    T h[kNComp[L]];
+};
+
+template <int L>
+__device__ __forceinline__ void load_head32(const uint32_t* __restrict__ r, Head<L, float>& o) {
+    const double* rd = reinterpret_cast<const double*>(r);
+    const float* rf = reinterpret_cast<const float*>(r + 6);
+    o.px = rd[0];
+    o.py = rd[1];
+    o.pz = rd[2];
+    o.r2far = rf[0];
+#pragma unroll
+    for (int c = 0; c < kNComp[L]; ++c) o.h[c] = rf[3 + c];
+}
+
+template <int L>
+__device__ __forceinline__ void load_head64(const uint32_t* __restrict__ r, Head<L, double>& o) {
+    const double* rd = reinterpret_cast<const double*>(r);
+    o.px = rd[0];
+    o.py = rd[1];
+    o.pz = rd[2];
+    o.r2far = rd[3];
+#pragma unroll
+    for (int c = 0; c < kNComp[L]; ++c) o.h[c] = rd[kRec64Head + c];
+}
+
+// Near field of one point (FP32): Boys values from the LDS table by a 6-term
+// Taylor step, then the Hermite recursion contracted with D.
+template <int L>
+__device__ __forceinline__ float near_f32(const uint32_t* __restrict__ r, float X, float Y, float Z,
+                                          float r2, const float* tab) {
+    const float* rf = reinterpret_cast<const float*>(r + 6);
+    const float p = rf[1], c1 = rf[2];
+    const float* D = rf + 3 + kNComp[L];
+    const float T = p * r2;
+    const int kk = (int)__builtin_fmaf(T, (float)kBoysGridInv, 0.5f);
+    const float d = __builtin_fmaf((float)kk, -1.0f / kBoysGridInv, T);
+    const float* f = tab + kk * kBoysRowF32;
+    const float d2 = 0.5f * d, d3 = d * (1.0f / 3.0f), d4 = 0.25f * d, d5 = 0.2f * d;
+    const float m2p = -2.0f * p;
+    float s = c1;
+    float G[L + 1];
+#pragma unroll
+    for (int n = 0; n <= L; ++n) {
+        float F = __builtin_fmaf(-d5, f[n + 5], f[n + 4]);
+        F = __builtin_fmaf(-d4, F, f[n + 3]);
+        F = __builtin_fmaf(-d3, F, f[n + 2]);
+        F = __builtin_fmaf(-d2, F, f[n + 1]);
+        F = __builtin_fmaf(-d, F, f[n]);
+        G[n] = s * F;
+        s *= m2p;
+    }
+    return hermite_dot<L, float>(G, X, Y, Z, D);
+}
+
+template <int L>
+__device__ __forceinline__ double near_f64(const uint32_t* __restrict__ r, double X, double Y,
+                                           double Z, double r2, const double* __restrict__ tab) {
+    const double* rd = reinterpret_cast<const double*>(r);
+    const double p = rd[4], c1 = rd[5];
+    const double* D = rd + kRec64Head + kNComp[L];
+    const double T = p * r2;
+    const int kk = (int)__builtin_fma(T, (double)kBoysGridInv, 0.5);
+    const double d = __builtin_fma((double)kk, -1.0 / kBoysGridInv, T);
+    const double* f = tab + kk * kBoysRowF64;
+    double dj[kBoysTaylorF64];
+#pragma unroll
+    for (int j = 1; j < kBoysTaylorF64; ++j) dj[j] = d * (1.0 / j);
+    const double m2p = -2.0 * p;
+    double s = c1;
+    double G[L + 1];
+#pragma unroll
+    for (int n = 0; n <= L; ++n) {
+        double F = f[n + kBoysTaylorF64 - 1];
+#pragma unroll
+        for (int j = kBoysTaylorF64 - 1; j >= 1; --j) F = __builtin_fma(-dj[j], F, f[n + j - 1]);
+        G[n] = s * F;
+        s *= m2p;
+    }
+    return hermite_dot<L, double>(G, X, Y, Z, D);
+}
+
+// FP32C pairs of one L.  Record: P (3 doubles), r2far, p, c1, h[nc], D[nc].
 template <int L, int NP>
 __device__ __forceinline__ void pairs_f32(const uint32_t* __restrict__ rec, int npairs,
                                           const double* cx, const double* cy, const double* cz,
-                                          const float* tab, float tfar, double* ele) {
+                                          const float* tab, double* ele) {
     constexpr int RW = rec32_words(L);
-    for (int i0 = 0; i0 < npairs; i0 += kTile) {
-        float tile[NP];
+    if (npairs <= 0) return;
+    float tile[NP];
 #pragma unroll
-        for (int k = 0; k < NP; ++k) tile[k] = 0.0f;
-        const int m = min(kTile, npairs - i0);
-        for (int j = 0; j < m; ++j) {
-            const uint32_t* r = rec + (int64_t)(i0 + j) * RW;
-            const double* rd = reinterpret_cast<const double*>(r);
-            const float* rf = reinterpret_cast<const float*>(r + 6);
-            const double Px = rd[0], Py = rd[1], Pz = rd[2];
-            const float p = rf[0], c1 = rf[1];
-            const float* D = rf + 2;
+    for (int k = 0; k < NP; ++k) tile[k] = 0.0f;
+    Head<L, float> cur;
+    load_head32<L>(rec, cur);
+    for (int i = 0; i < npairs; ++i) {
+        const uint32_t* r = rec + (int64_t)i * RW;
+        Head<L, float> nxt;
+        load_head32<L>(rec + (int64_t)min(i + 1, npairs - 1) * RW, nxt);
+        float X[NP], Y[NP], Z[NP], r2[NP];
+        bool nearp = false;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            X[k] = (float)(cur.px - cx[k]);
+            Y[k] = (float)(cur.py - cy[k]);
+            Z[k] = (float)(cur.pz - cz[k]);
+            r2[k] = __builtin_fmaf(X[k], X[k], __builtin_fmaf(Y[k], Y[k], Z[k] * Z[k]));
+            nearp |= r2[k] < cur.r2far;
+        }
+        if (__builtin_amdgcn_ballot_w64(nearp) == 0) {
+            // every point of the wave is in the far field of this pair:
+            // (1/R) sum h_abc (X/R^2)^a (Y/R^2)^b (Z/R^2)^c
 #pragma unroll
             for (int k = 0; k < NP; ++k) {
-                const float X = (float)(Px - cx[k]);
-                const float Y = (float)(Py - cy[k]);
-                const float Z = (float)(Pz - cz[k]);
-                const float r2 = __builtin_fmaf(X, X, __builtin_fmaf(Y, Y, Z * Z));
-                const float T = p * r2;
-                float G[L + 1];
-                if (T < tfar) {
-                    const int kk = (int)__builtin_fmaf(T, (float)kBoysGridInv, 0.5f);
-                    const float d = __builtin_fmaf((float)kk, -1.0f / kBoysGridInv, T);
-                    const float* f = tab + kk * kBoysRowF32;
-                    const float d2 = 0.5f * d, d3 = d * (1.0f / 3.0f), d4 = 0.25f * d, d5 = 0.2f * d;
-                    const float m2p = -2.0f * p;
-                    float s = c1;
+                const float ri = rsqrt_refined(r2[k]);
+                const float w = ri * ri;
+                tile[k] = __builtin_fmaf(ri, far_poly<L, float>(cur.h, X[k] * w, Y[k] * w, Z[k] * w),
+                                         tile[k]);
+            }
+        } else {
+            // rare: some point inside the near-field radius of this pair
 #pragma unroll
-                    for (int n = 0; n <= L; ++n) {
-                        float F = __builtin_fmaf(-d5, f[n + 5], f[n + 4]);
-                        F = __builtin_fmaf(-d4, F, f[n + 3]);
-                        F = __builtin_fmaf(-d3, F, f[n + 2]);
-                        F = __builtin_fmaf(-d2, F, f[n + 1]);
-                        F = __builtin_fmaf(-d, F, f[n]);
-                        G[n] = s * F;
-                        s *= m2p;
-                    }
+            for (int k = 0; k < NP; ++k) {
+                float v;
+                if (r2[k] < cur.r2far) {
+                    v = near_f32<L>(r, X[k], Y[k], Z[k], r2[k], tab);
                 } else {
-                    const float ri = rsqrt_refined(r2);
-                    const float ri2 = ri * ri;
-                    G[0] = ri;
-#pragma unroll
-                    for (int n = 1; n <= L; ++n) G[n] = (G[n - 1] * ri2) * (float)(1 - 2 * n);
+                    const float ri = rsqrt_refined(r2[k]);
+                    const float w = ri * ri;
+                    v = ri * far_poly<L, float>(cur.h, X[k] * w, Y[k] * w, Z[k] * w);
                 }
-                tile[k] += hermite_dot<L, float>(G, X, Y, Z, D);
+                tile[k] += v;
             }
         }
+        if ((i & (kTile - 1)) == kTile - 1) {
 #pragma unroll
-        for (int k = 0; k < NP; ++k) ele[k] += (double)tile[k];
+            for (int k = 0; k < NP; ++k) {
+                ele[k] += (double)tile[k];
+                tile[k] = 0.0f;
+            }
+        }
+        cur = nxt;
     }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) ele[k] += (double)tile[k];
 }
 
+// FP64 pairs of one L.  Record: P, r2far, p, c1 (doubles), h[nc], D[nc].
 template <int L, int NP>
 __device__ __forceinline__ void pairs_f64(const uint32_t* __restrict__ rec, int npairs,
                                           const double* cx, const double* cy, const double* cz,
-                                          const double* __restrict__ tab, double tfar,
-                                          double* ele) {
+                                          const double* __restrict__ tab, double* ele) {
     constexpr int RW = rec64_words(L);
+    if (npairs <= 0) return;
+    Head<L, double> cur;
+    load_head64<L>(rec, cur);
     for (int i = 0; i < npairs; ++i) {
-        const double* rd = reinterpret_cast<const double*>(rec + (int64_t)i * RW);
-        const double Px = rd[0], Py = rd[1], Pz = rd[2], p = rd[3], c1 = rd[4];
-        const double* D = rd + 5;
+        const uint32_t* r = rec + (int64_t)i * RW;
+        Head<L, double> nxt;
+        load_head64<L>(rec + (int64_t)min(i + 1, npairs - 1) * RW, nxt);
+        double X[NP], Y[NP], Z[NP], r2[NP];
+        bool nearp = false;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
-            const double X = Px - cx[k], Y = Py - cy[k], Z = Pz - cz[k];
-            const double r2 = __builtin_fma(X, X, __builtin_fma(Y, Y, Z * Z));
-            const double T = p * r2;
-            double G[L + 1];
-            if (T < tfar) {
-                const int kk = (int)__builtin_fma(T, (double)kBoysGridInv, 0.5);
-                const double d = __builtin_fma((double)kk, -1.0 / kBoysGridInv, T);
-                const double* f = tab + kk * kBoysRowF64;
-                double dj[kBoysTaylorF64];
-#pragma unroll
-                for (int j = 1; j < kBoysTaylorF64; ++j) dj[j] = d * (1.0 / j);
-                const double m2p = -2.0 * p;
-                double s = c1;
-#pragma unroll
-                for (int n = 0; n <= L; ++n) {
-                    double F = f[n + kBoysTaylorF64 - 1];
-#pragma unroll
-                    for (int j = kBoysTaylorF64 - 1; j >= 1; --j) F = __builtin_fma(-dj[j], F, f[n + j - 1]);
-                    G[n] = s * F;
-                    s *= m2p;
-                }
-            } else {
-                const double ri = rsqrt(r2);
-                const double ri2 = ri * ri;
-                G[0] = ri;
-#pragma unroll
-                for (int n = 1; n <= L; ++n) G[n] = (G[n - 1] * ri2) * (double)(1 - 2 * n);
-            }
-            ele[k] += hermite_dot<L, double>(G, X, Y, Z, D);
+            X[k] = cur.px - cx[k];
+            Y[k] = cur.py - cy[k];
+            Z[k] = cur.pz - cz[k];
+            r2[k] = __builtin_fma(X[k], X[k], __builtin_fma(Y[k], Y[k], Z[k] * Z[k]));
+            nearp |= r2[k] < cur.r2far;
         }
+        if (__builtin_amdgcn_ballot_w64(nearp) == 0) {
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                const double ri = rsqrt(r2[k]);
+                const double w = ri * ri;
+                ele[k] = __builtin_fma(ri, far_poly<L, double>(cur.h, X[k] * w, Y[k] * w, Z[k] * w),
+                                       ele[k]);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                double v;
+                if (r2[k] < cur.r2far) {
+                    v = near_f64<L>(r, X[k], Y[k], Z[k], r2[k], tab);
+                } else {
+                    const double ri = rsqrt(r2[k]);
+                    const double w = ri * ri;
+                    v = ri * far_poly<L, double>(cur.h, X[k] * w, Y[k] * w, Z[k] * w);
+                }
+                ele[k] += v;
+            }
+        }
+        cur = nxt;
     }
 }
 
@@ -188,19 +299,19 @@ __global__ __launch_bounds__(kBlock) void k_potential(EvalArgs a) {
         if constexpr (F64) {
             const double* tab = static_cast<const double*>(a.boys);
             switch (sg.L) {
-                case 0: pairs_f64<0, NP>(rec, sg.n_pairs, cx, cy, cz, tab, a.bp.tfar64[0], ve); break;
-                case 1: pairs_f64<1, NP>(rec, sg.n_pairs, cx, cy, cz, tab, a.bp.tfar64[1], ve); break;
-                case 2: pairs_f64<2, NP>(rec, sg.n_pairs, cx, cy, cz, tab, a.bp.tfar64[2], ve); break;
-                case 3: pairs_f64<3, NP>(rec, sg.n_pairs, cx, cy, cz, tab, a.bp.tfar64[3], ve); break;
-                default: pairs_f64<4, NP>(rec, sg.n_pairs, cx, cy, cz, tab, a.bp.tfar64[4], ve); break;
+                case 0: pairs_f64<0, NP>(rec, sg.n_pairs, cx, cy, cz, tab, ve); break;
+                case 1: pairs_f64<1, NP>(rec, sg.n_pairs, cx, cy, cz, tab, ve); break;
+                case 2: pairs_f64<2, NP>(rec, sg.n_pairs, cx, cy, cz, tab, ve); break;
+                case 3: pairs_f64<3, NP>(rec, sg.n_pairs, cx, cy, cz, tab, ve); break;
+                default: pairs_f64<4, NP>(rec, sg.n_pairs, cx, cy, cz, tab, ve); break;
             }
         } else {
             switch (sg.L) {
-                case 0: pairs_f32<0, NP>(rec, sg.n_pairs, cx, cy, cz, tab32, a.bp.tfar32[0], ve); break;
-                case 1: pairs_f32<1, NP>(rec, sg.n_pairs, cx, cy, cz, tab32, a.bp.tfar32[1], ve); break;
-                case 2: pairs_f32<2, NP>(rec, sg.n_pairs, cx, cy, cz, tab32, a.bp.tfar32[2], ve); break;
-                case 3: pairs_f32<3, NP>(rec, sg.n_pairs, cx, cy, cz, tab32, a.bp.tfar32[3], ve); break;
-                default: pairs_f32<4, NP>(rec, sg.n_pairs, cx, cy, cz, tab32, a.bp.tfar32[4], ve); break;
+                case 0: pairs_f32<0, NP>(rec, sg.n_pairs, cx, cy, cz, tab32, ve); break;
+                case 1: pairs_f32<1, NP>(rec, sg.n_pairs, cx, cy, cz, tab32, ve); break;
+                case 2: pairs_f32<2, NP>(rec, sg.n_pairs, cx, cy, cz, tab32, ve); break;
+                case 3: pairs_f32<3, NP>(rec, sg.n_pairs, cx, cy, cz, tab32, ve); break;
+                default: pairs_f32<4, NP>(rec, sg.n_pairs, cx, cy, cz, tab32, ve); break;
             }
         }
         if (sg.flags & kSegEndGroup) {

@@ -500,15 +500,86 @@ void build_segments(const PairList& pl, int S, bool fp64, std::vector<Segment>& 
     while (int(split.size()) < S + 1) split.push_back(int32_t(segs.size()));
 }
 
-void pack_records(const PairList& pl, bool fp64, std::vector<uint32_t>& rec,
-                  std::vector<int64_t>& /*unused*/) {
+namespace {
+
+// Coefficients of the homogeneous polynomials P_tuv with
+//   d^t_X d^u_Y d^v_Z (1/R) = P_tuv(X, Y, Z) / R^{2k+1},  k = t + u + v,
+// built by P_{t+1,u,v} = R^2 dP/dX - (2k+1) X P (likewise for Y and Z).
+// Polynomials are dense arrays over exponents [a][b][c], a, b, c <= 4.
+struct Poly { double c[5][5][5]; };
+struct PolyTable { Poly t[5][5][5]; };
+
+PolyTable make_poly_table() {
+    PolyTable T;
+    std::memset(&T, 0, sizeof(T));
+    T.t[0][0][0].c[0][0][0] = 1.0;
+    for (int k = 1; k <= kLMax; ++k)
+        for (int tt = 0; tt <= k; ++tt)
+            for (int uu = 0; uu <= k - tt; ++uu) {
+                const int vv = k - tt - uu;
+                int dir, pt = tt, pu = uu, pv = vv;
+                if (tt > 0) { dir = 0; --pt; }
+                else if (uu > 0) { dir = 1; --pu; }
+                else { dir = 2; --pv; }
+                const Poly& P = T.t[pt][pu][pv];
+                Poly& Q = T.t[tt][uu][vv];
+                for (int a = 0; a <= 4; ++a)
+                    for (int b = 0; b <= 4 - a; ++b)
+                        for (int c = 0; c <= 4 - a - b; ++c) {
+                            const double co = P.c[a][b][c];
+                            if (co == 0.0) continue;
+                            const int e[3] = {a, b, c};
+                            if (e[dir] > 0) {  // R^2 dP/d(dir)
+                                for (int s = 0; s < 3; ++s) {
+                                    int f[3] = {a, b, c};
+                                    f[dir] -= 1;
+                                    f[s] += 2;
+                                    if (f[0] + f[1] + f[2] <= 4) Q.c[f[0]][f[1]][f[2]] += e[dir] * co;
+                                }
+                            }
+                            int f[3] = {a, b, c};  // -(2k-1) X_dir P
+                            f[dir] += 1;
+                            if (f[0] + f[1] + f[2] <= 4) Q.c[f[0]][f[1]][f[2]] -= (2 * k - 1) * co;
+                        }
+            }
+    return T;
+}
+
+const Poly& derivative_poly(int t, int u, int v) {
+    static const PolyTable table = make_poly_table();  // thread-safe one-time init
+    return table.t[t][u][v];
+}
+
+}  // namespace
+
+void far_coefs(int L, const double* D, double* h) {
+    for (int k = 0; k < kNComp[L]; ++k) h[k] = 0.0;
+    for (int t = 0; t <= L; ++t)
+        for (int u = 0; u <= L - t; ++u)
+            for (int v = 0; v <= L - t - u; ++v) {
+                const double d = D[hermite_index(L, t, u, v)];
+                if (d == 0.0) continue;
+                const Poly& P = derivative_poly(t, u, v);
+                const int k = t + u + v;
+                for (int a = 0; a <= k; ++a)
+                    for (int b = 0; b <= k - a; ++b) {
+                        const int c = k - a - b;
+                        h[hermite_index(L, a, b, c)] += d * P.c[a][b][c];
+                    }
+            }
+}
+
+void pack_records(const PairList& pl, bool fp64, const BoysParams& bp,
+                  std::vector<uint32_t>& rec) {
     rec.clear();
     const int64_t n = int64_t(pl.L.size());
+    double h[35];
     for (int64_t k = 0; k < n; ++k) {
-        const int L = pl.L[k];
+        const int L = pl.L[k], nc = kNComp[L];
         const double p = pl.p[k];
         const double c1 = 2.0 * std::sqrt(p / kPi);
         const double* D = &pl.D[35 * k];
+        far_coefs(L, D, h);
         const size_t o = rec.size();
         if (fp64) {
             rec.resize(o + rec64_words(L), 0u);
@@ -516,9 +587,11 @@ void pack_records(const PairList& pl, bool fp64, std::vector<uint32_t>& rec,
             r[0] = pl.center[3 * k];
             r[1] = pl.center[3 * k + 1];
             r[2] = pl.center[3 * k + 2];
-            r[3] = p;
-            r[4] = c1;
-            for (int c = 0; c < kNComp[L]; ++c) r[5 + c] = D[c];
+            r[3] = bp.tfar64[L] / p;
+            r[4] = p;
+            r[5] = c1;
+            for (int c = 0; c < nc; ++c) r[kRec64Head + c] = h[c];
+            for (int c = 0; c < nc; ++c) r[kRec64Head + nc + c] = D[c];
         } else {
             rec.resize(o + rec32_words(L), 0u);
             double* r = reinterpret_cast<double*>(&rec[o]);
@@ -526,9 +599,11 @@ void pack_records(const PairList& pl, bool fp64, std::vector<uint32_t>& rec,
             r[1] = pl.center[3 * k + 1];
             r[2] = pl.center[3 * k + 2];
             float* f = reinterpret_cast<float*>(&rec[o + 6]);
-            f[0] = float(p);
-            f[1] = float(c1);
-            for (int c = 0; c < kNComp[L]; ++c) f[2 + c] = float(D[c]);
+            f[0] = float(double(bp.tfar32[L]) / p);
+            f[1] = float(p);
+            f[2] = float(c1);
+            for (int c = 0; c < nc; ++c) f[3 + c] = float(h[c]);
+            for (int c = 0; c < nc; ++c) f[3 + nc + c] = float(D[c]);
         }
     }
 }
