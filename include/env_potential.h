@@ -156,14 +156,56 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
 env_status env_potential_eval(env_potential* h, const double* points, int64_t n,
                               double* out, void* stream);
 
-/* Several independent evaluations in one persistent launch: instance i
- * evaluates handle hs[i] at points[i] (n[i] x 3) into out[i] (n[i]).
- * All handles must share the device and precision of hs[0].  Work items
- * (instance, point block, pair range) are balanced by cost across the chip.
- * Same pointer/stream rules and errors as env_potential_eval. */
+/* Several independent evaluations in one persistent launch (convenience
+ * form of the env_batch calls below): instance i evaluates handle hs[i] at
+ * points[i] (n[i] x 3) into out[i] (n[i]).  All handles must be on the same
+ * device with the same precision.  Unlike env_potential_eval this call
+ * synchronises the stream before it returns (it owns temporary buffers).
+ * Errors: as env_potential_eval; ENV_E_ARG for mixed devices/precisions. */
 env_status env_potential_eval_batched(env_potential* const* hs, int32_t n_inst,
                                       const double* const* points, const int64_t* n,
                                       double* const* out, void* stream);
+
+/* A reusable plan for repeated batched evaluation (many walkers and many
+ * uneven QM/MM instances per QMC step; the paper's outlook of sharing one GPU
+ * among several processes, Sec. I and Sec. V).  Work items (instance, point
+ * block, pair range) are sorted by decreasing cost and drained by one
+ * persistent kernel through a global work counter; split-pair partials are
+ * reduced in fixed order, so a plan gives bitwise-identical results for the
+ * same inputs on every call.  While the caller passes the same pointers and counts
+ * on a non-NULL stream, env_batch_eval replays a captured HIP graph; a new
+ * pointer set or count synchronises the stream once, uploads the new tables
+ * and captures again.  The handles must outlive the plan. */
+typedef struct env_batch env_batch;
+
+typedef struct {
+    int64_t n_items;          /* work items of the current shape */
+    int32_t grid;             /* workgroups of the persistent launch */
+    int32_t reserved;
+    int64_t launches;         /* direct launches */
+    int64_t captures;         /* graph captures */
+    int64_t graph_launches;   /* graph replays */
+} env_batch_stats;
+
+/* Errors: ENV_E_ARG (NULL, n_inst <= 0, mixed device/precision), ENV_E_STATE
+ * (a build-only handle), ENV_E_NOMEM. */
+env_status env_batch_create(env_potential* const* hs, int32_t n_inst, env_batch** out);
+
+/* points[i]: device n[i] x 3 float64; out[i]: device n[i] float64.
+ * Asynchronous on `stream` except when the pointers or counts changed. */
+env_status env_batch_eval(env_batch* b, const double* const* points, const int64_t* n,
+                          double* const* out, void* stream);
+
+env_status env_batch_get_stats(const env_batch* b, env_batch_stats* stats);
+
+void env_batch_destroy(env_batch* b);
+
+/* Times the candidate launch shapes (points per lane, pair-split factor) of
+ * h at the n device points `points` on `stream` (synchronous) and keeps the
+ * fastest for evaluations of h at a point count within a factor 2 of n.
+ * Must not run concurrently with other calls on the same handle.
+ * Errors: ENV_E_ARG, ENV_E_STATE, ENV_E_NOMEM, ENV_E_DEVICE. */
+env_status env_potential_autotune(env_potential* h, const double* points, int64_t n, void* stream);
 
 /* Statistics of the built pair list. */
 env_status env_potential_info(const env_potential* h, env_info* info);

@@ -2,48 +2,18 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
 #include <vector>
 
-#include "envpot_internal.h"
+#include "handle.h"
 
 using namespace envpot;
 
-struct env_potential {
-    int device = -1;
-    int precision = ENV_PREC_FP32C;
-    bool on_device = false;
-    int cu_count = 256;
-    env_info info{};
-    PairList host;                      // kept only for ENV_BUILD_ONLY handles
-    BoysParams bp{};
-    // device buffers
-    uint32_t* d_rec = nullptr;
-    Segment* d_segs = nullptr;
-    int32_t* d_split = nullptr;
-    double* d_nuc = nullptr;
-    void* d_boys = nullptr;
-    int64_t seg_off[kMaxSplitLog2 + 1] = {};    // per split factor 2^k: first segment
-    int64_t split_off[kMaxSplitLog2 + 1] = {};  // per split factor 2^k: first offset
-    int64_t device_bytes = 0;
-};
-
 namespace {
-
-struct DeviceGuard {  // restores the caller's current device
-    int prev = -1;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (dev >= 0 && dev != prev) (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
 
 template <typename T>
 env_status upload(const std::vector<T>& v, T** dst, int64_t& bytes) {
@@ -78,6 +48,52 @@ int env_int(const char* name, int dflt) {
 }
 
 }  // namespace
+
+namespace envpot {
+
+void choose_shape(const env_potential* h, int64_t n, int* np_out, int* k_out) {
+    const bool fp64 = h->precision == ENV_PREC_FP64;
+    // a tuned shape for a point count within a factor 2 of n wins
+    const env_potential::Tuned* best = nullptr;
+    double bestd = 1e300;
+    for (const auto& t : h->tuned) {
+        const double d = std::fabs(std::log(double(t.n) / double(n)));
+        if (d < bestd) { bestd = d; best = &t; }
+    }
+    int np, k = 0;
+    if (best && bestd <= std::log(2.0)) {
+        np = best->np;
+        k = best->klog;
+    } else {
+        np = fp64 ? 2 : 4;
+        // split factor: enough waves to keep ~24 per SIMD in flight over the run
+        const int64_t waves = (n + 64 * np - 1) / (64 * np);
+        const int64_t want = int64_t(h->cu_count) * 4 * 24;
+        while (k < kMaxSplitLog2 && waves * (int64_t(1) << k) < want) ++k;
+    }
+    const int fnp = env_int("ENVPOT_NP", -1);
+    if (fnp == 1 || fnp == 2 || (fnp == 4 && !fp64)) np = fnp;
+    const int fk = env_int("ENVPOT_SPLIT_LOG2", -1);
+    if (fk >= 0 && fk <= kMaxSplitLog2) k = fk;
+    *np_out = np;
+    *k_out = k;
+}
+
+EvalArgs make_args(const env_potential* h, const double* points, int64_t n, double* out, int k) {
+    EvalArgs a;
+    a.pts = points;
+    a.n = n;
+    a.segs = h->d_segs + h->seg_off[k];
+    a.split = h->d_split + h->split_off[k];
+    a.rec = h->d_rec;
+    a.nuc = h->d_nuc;
+    a.boys = h->d_boys;
+    a.out = out;
+    a.bp = h->bp;
+    return a;
+}
+
+}  // namespace envpot
 
 extern "C" {
 
@@ -215,60 +231,76 @@ env_status env_potential_eval(env_potential* h, const double* points, int64_t n,
     if (!points || !out) return ENV_E_ARG;
     if (!h->on_device) return ENV_E_STATE;
     DeviceGuard g(h->device);
-    const bool fp64 = h->precision == ENV_PREC_FP64;
-    int np = env_int("ENVPOT_NP", fp64 ? 2 : 4);
-    if (np != 1 && np != 2 && np != 4) np = fp64 ? 2 : 4;
-    if (fp64 && np == 4) np = 2;
-    // split factor: enough waves to keep ~24 per SIMD in flight over the run
-    const int64_t waves = (n + 64 * np - 1) / (64 * np);
-    const int64_t want = int64_t(h->cu_count) * 4 * 24;
-    int k = 0;
-    while (k < kMaxSplitLog2 && waves * (int64_t(1) << k) < want) ++k;
-    const int forced = env_int("ENVPOT_SPLIT_LOG2", -1);
-    if (forced >= 0 && forced <= kMaxSplitLog2) k = forced;
+    int np, k;
+    choose_shape(h, n, &np, &k);
     const int S = 1 << k;
-
-    EvalArgs a;
-    a.pts = points;
-    a.n = n;
-    a.segs = h->d_segs + h->seg_off[k];
-    a.split = h->d_split + h->split_off[k];
-    a.rec = h->d_rec;
-    a.nuc = h->d_nuc;
-    a.boys = h->d_boys;
-    a.bp = h->bp;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (S == 1) {
-        a.out = out;
+        const EvalArgs a = make_args(h, points, n, out, 0);
         return launch_potential(a, 1, h->precision, np, stream) == 0 ? ENV_OK : ENV_E_DEVICE;
     }
     double* part = nullptr;
     if (hipMallocAsync(reinterpret_cast<void**>(&part), size_t(S) * size_t(n) * sizeof(double), st) !=
         hipSuccess)
         return ENV_E_NOMEM;
-    a.out = part;
+    const EvalArgs a = make_args(h, points, n, part, k);
     int rc = launch_potential(a, S, h->precision, np, stream);
     if (rc == 0) rc = launch_sum_splits(part, S, n, out, stream);
     (void)hipFreeAsync(part, st);
     return rc == 0 ? ENV_OK : ENV_E_DEVICE;
 }
 
-env_status env_potential_eval_batched(env_potential* const* hs, int32_t n_inst,
-                                      const double* const* points, const int64_t* n,
-                                      double* const* out, void* stream) {
-    if (n_inst < 0) return ENV_E_ARG;
-    if (n_inst == 0) return ENV_OK;
-    if (!hs || !points || !n || !out) return ENV_E_ARG;
-    for (int i = 0; i < n_inst; ++i) {
-        if (!hs[i] || n[i] < 0) return ENV_E_ARG;
-        if (hs[i]->device != hs[0]->device || hs[i]->precision != hs[0]->precision)
-            return ENV_E_ARG;
+env_status env_potential_autotune(env_potential* h, const double* points, int64_t n, void* stream) {
+    if (!h || n <= 0 || !points) return ENV_E_ARG;
+    if (!h->on_device) return ENV_E_STATE;
+    DeviceGuard g(h->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double* out = nullptr;
+    if (hipMalloc(reinterpret_cast<void**>(&out), size_t(n) * sizeof(double)) != hipSuccess)
+        return ENV_E_NOMEM;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        (void)hipFree(out);
+        return ENV_E_DEVICE;
     }
-    for (int i = 0; i < n_inst; ++i) {
-        const env_status s = env_potential_eval(hs[i], points[i], n[i], out[i], stream);
-        if (s != ENV_OK) return s;
+    const bool fp64 = h->precision == ENV_PREC_FP64;
+    const int nps32[] = {2, 4}, nps64[] = {1, 2};
+    const int* nps = fp64 ? nps64 : nps32;
+    float best = 1e30f;
+    env_potential::Tuned bestc{n, fp64 ? 2 : 4, 0};
+    env_status rc = ENV_OK;
+    // drop an earlier entry for this size, then time every candidate shape
+    h->tuned.erase(std::remove_if(h->tuned.begin(), h->tuned.end(),
+                                  [&](const env_potential::Tuned& t) { return t.n == n; }),
+                   h->tuned.end());
+    for (int a = 0; a < 2 && rc == ENV_OK; ++a) {
+        for (int k = 0; k <= kMaxSplitLog2 && rc == ENV_OK; ++k) {
+            const int64_t waves = ((n + 64 * nps[a] - 1) / (64 * nps[a])) << k;
+            if (waves < int64_t(h->cu_count) * 4 || (k > 0 && waves > int64_t(h->cu_count) * 4 * 96))
+                continue;
+            h->tuned.push_back({n, nps[a], k});
+            float ms = 0.0f;
+            for (int rep = 0; rep < 3 && rc == ENV_OK; ++rep) {  // first run warms up
+                if (hipEventRecord(e0, st) != hipSuccess) rc = ENV_E_DEVICE;
+                if (rc == ENV_OK) rc = env_potential_eval(h, points, n, out, stream);
+                if (rc == ENV_OK && hipEventRecord(e1, st) != hipSuccess) rc = ENV_E_DEVICE;
+                if (rc == ENV_OK && hipEventSynchronize(e1) != hipSuccess) rc = ENV_E_DEVICE;
+                float t = 0.0f;
+                if (rc == ENV_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = ENV_E_DEVICE;
+                if (rep > 0) ms += t;
+            }
+            h->tuned.pop_back();
+            if (rc == ENV_OK && ms < best) {
+                best = ms;
+                bestc = {n, nps[a], k};
+            }
+        }
     }
-    return ENV_OK;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(out);
+    if (rc == ENV_OK) h->tuned.push_back(bestc);
+    return rc;
 }
 
 env_status env_potential_info(const env_potential* h, env_info* info) {

@@ -81,6 +81,31 @@ struct EvalArgs {
     BoysParams bp;
 };
 
+// One work item of the persistent batched kernel.
+struct BatchItem {
+    int32_t inst;     // instance (index into BatchArgs::args)
+    int32_t split;    // pair split of that instance
+    int64_t pblock;   // point block of that instance
+};
+
+struct BatchArgs {
+    const EvalArgs* args;         // per instance (out = its partial buffer when S > 1)
+    const BatchItem* items;       // sorted by decreasing cost
+    int64_t n_items;
+    unsigned long long* counter;  // queue head, zeroed by a kernel before each launch
+    const void* boys;             // Boys table of the common precision
+    int32_t rows32;
+    int32_t pad;
+};
+
+struct SumDesc {                  // fixed-order sum of S partials of one instance
+    const double* part;
+    double* out;
+    int64_t n;
+    int32_t S;
+    int32_t pad;
+};
+
 // Host-side result of the pair-list build.
 struct PairList {
     int nbf = 0;
@@ -125,5 +150,8 @@ void build_boys_tables(std::vector<float>& t32, std::vector<double>& t64, BoysPa
 // Kernel launchers (kernels.hip).
 int launch_potential(const EvalArgs& a, int S, int precision, int np, void* stream);
 int launch_sum_splits(const double* partial, int S, int64_t n, double* out, void* stream);
+int launch_persistent(const BatchArgs& b, int grid, int precision, int np, void* stream);
+int launch_sum_multi(const SumDesc* d, int n_desc, int64_t max_n, void* stream);
+int persistent_grid(int precision, int np, int cu_count);
 
 }  // namespace envpot

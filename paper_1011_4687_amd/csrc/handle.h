@@ -1,0 +1,50 @@
+// The opaque handle of the C ABI and helpers shared by the ABI files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "envpot_internal.h"
+
+struct env_potential {
+    int device = -1;
+    int precision = ENV_PREC_FP32C;
+    bool on_device = false;
+    int cu_count = 256;
+    env_info info{};
+    envpot::PairList host;              // kept only for ENV_BUILD_ONLY handles
+    envpot::BoysParams bp{};
+    // device buffers
+    uint32_t* d_rec = nullptr;
+    envpot::Segment* d_segs = nullptr;
+    int32_t* d_split = nullptr;
+    double* d_nuc = nullptr;
+    void* d_boys = nullptr;
+    int64_t seg_off[envpot::kMaxSplitLog2 + 1] = {};    // per split factor 2^k: first segment
+    int64_t split_off[envpot::kMaxSplitLog2 + 1] = {};  // per split factor 2^k: first offset
+    int64_t device_bytes = 0;
+    // tuned launch shapes: (point count, points per lane, split log2)
+    struct Tuned { int64_t n; int np; int klog; };
+    std::vector<Tuned> tuned;
+};
+
+namespace envpot {
+
+struct DeviceGuard {  // restores the caller's current device
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (dev >= 0 && dev != prev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// Launch shape of a single evaluation of h at n points.
+void choose_shape(const env_potential* h, int64_t n, int* np, int* klog);
+
+// Arguments of one evaluation (out = V when S == 1, partials otherwise).
+EvalArgs make_args(const env_potential* h, const double* points, int64_t n, double* out, int klog);
+
+}  // namespace envpot

@@ -263,15 +263,12 @@ __device__ __forceinline__ void pairs_f64(const uint32_t* __restrict__ rec, int 
     }
 }
 
+// One workgroup's share: points of point block `pblock` against the pair
+// range of split `s` (all of it when S == 1).
 template <int NP, bool F64>
-__global__ __launch_bounds__(kBlock) void k_potential(EvalArgs a) {
-    __shared__ float tab32[F64 ? 1 : kBoysMaxRowsF32 * kBoysRowF32];
-    if constexpr (!F64) {
-        const float* g = static_cast<const float*>(a.boys);
-        for (int i = threadIdx.x; i < a.bp.rows32 * kBoysRowF32; i += kBlock) tab32[i] = g[i];
-        __syncthreads();
-    }
-    const int64_t base = (int64_t)blockIdx.x * (kBlock * NP) + threadIdx.x;
+__device__ __forceinline__ void block_work(const EvalArgs& a, int64_t pblock, int s,
+                                           const float* tab32) {
+    const int64_t base = pblock * (kBlock * NP) + threadIdx.x;
     double cx[NP], cy[NP], cz[NP], acc[NP], vn[NP], ve[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
@@ -282,7 +279,6 @@ __global__ __launch_bounds__(kBlock) void k_potential(EvalArgs a) {
         cz[k] = a.pts[3 * ic + 2];
         acc[k] = vn[k] = ve[k] = 0.0;
     }
-    const int s = blockIdx.y;
     const int sb = a.split[s], se = a.split[s + 1];
     for (int g = sb; g < se; ++g) {
         const Segment sg = a.segs[g];
@@ -330,6 +326,62 @@ __global__ __launch_bounds__(kBlock) void k_potential(EvalArgs a) {
     }
 }
 
+template <bool F64>
+__device__ __forceinline__ void load_boys_lds(const void* boys, int rows32, float* tab32) {
+    if constexpr (!F64) {
+        const float* g = static_cast<const float*>(boys);
+        for (int i = threadIdx.x; i < rows32 * kBoysRowF32; i += kBlock) tab32[i] = g[i];
+        __syncthreads();
+    }
+}
+
+template <int NP, bool F64>
+__global__ __launch_bounds__(kBlock) void k_potential(EvalArgs a) {
+    __shared__ float tab32[F64 ? 1 : kBoysMaxRowsF32 * kBoysRowF32];
+    load_boys_lds<F64>(a.boys, a.bp.rows32, tab32);
+    block_work<NP, F64>(a, blockIdx.x, blockIdx.y, tab32);
+}
+
+// Persistent batched kernel: every workgroup takes work items (instance,
+// point block, pair split) from a global counter until the queue is empty.
+// Items are sorted by decreasing estimated cost, so the long ones start
+// first.  Every workgroup reaches the exit test once the counter passes
+// n_items, so the grid always drains.
+template <int NP, bool F64>
+__global__ __launch_bounds__(kBlock) void k_potential_persistent(BatchArgs b) {
+    __shared__ float tab32[F64 ? 1 : kBoysMaxRowsF32 * kBoysRowF32];
+    __shared__ unsigned long long item_sh;
+    load_boys_lds<F64>(b.boys, b.rows32, tab32);
+    for (;;) {
+        if (threadIdx.x == 0) item_sh = atomicAdd(b.counter, 1ull);
+        __syncthreads();
+        const unsigned long long it_v = item_sh;
+        __syncthreads();
+        // wave-uniform copy, so the item and its instance are read with scalar loads
+        const int64_t it = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(it_v >> 32)) << 32) |
+                                     (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)it_v));
+        if (it >= b.n_items) break;
+        const BatchItem w = b.items[it];
+        const EvalArgs a = b.args[w.inst];
+        block_work<NP, F64>(a, w.pblock, w.split, tab32);
+    }
+}
+
+__global__ void k_reset_counter(unsigned long long* c) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0ull;
+}
+
+// Fixed-order sum of the split partials of several instances: grid.y is the
+// instance, grid.x covers its points.
+__global__ __launch_bounds__(kBlock) void k_sum_splits_multi(const SumDesc* __restrict__ d) {
+    const SumDesc q = d[blockIdx.y];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= q.n) return;
+    double s = 0.0;
+    for (int k = 0; k < q.S; ++k) s += q.part[(int64_t)k * q.n + i];
+    q.out[i] = s;
+}
+
 __global__ __launch_bounds__(kBlock) void k_sum_splits(const double* __restrict__ part, int S,
                                                        int64_t n, double* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -354,6 +406,41 @@ int launch_potential(const EvalArgs& a, int S, int precision, int np, void* stre
         else if (np == 4) hipLaunchKernelGGL((k_potential<4, false>), grid, block, 0, st, a);
         else hipLaunchKernelGGL((k_potential<2, false>), grid, block, 0, st, a);
     }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_persistent(const BatchArgs& b, int grid, int precision, int np, void* stream) {
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, b.counter);
+    if (precision == ENV_PREC_FP64) {
+        if (np == 2) hipLaunchKernelGGL((k_potential_persistent<2, true>), dim3(grid), dim3(kBlock), 0, st, b);
+        else hipLaunchKernelGGL((k_potential_persistent<1, true>), dim3(grid), dim3(kBlock), 0, st, b);
+    } else {
+        if (np == 1) hipLaunchKernelGGL((k_potential_persistent<1, false>), dim3(grid), dim3(kBlock), 0, st, b);
+        else if (np == 2) hipLaunchKernelGGL((k_potential_persistent<2, false>), dim3(grid), dim3(kBlock), 0, st, b);
+        else hipLaunchKernelGGL((k_potential_persistent<4, false>), dim3(grid), dim3(kBlock), 0, st, b);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int persistent_grid(int precision, int np, int cu_count) {
+    int per_cu = 0;
+    hipError_t e;
+    if (precision == ENV_PREC_FP64)
+        e = np == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_potential_persistent<2, true>, kBlock, 0)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_potential_persistent<1, true>, kBlock, 0);
+    else
+        e = np == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_potential_persistent<1, false>, kBlock, 0)
+          : np == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_potential_persistent<2, false>, kBlock, 0)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_potential_persistent<4, false>, kBlock, 0);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    return per_cu * cu_count;
+}
+
+int launch_sum_multi(const SumDesc* d, int n_desc, int64_t max_n, void* stream) {
+    if (n_desc <= 0) return 0;
+    const dim3 grid((unsigned)((max_n + kBlock - 1) / kBlock), (unsigned)n_desc);
+    hipLaunchKernelGGL(k_sum_splits_multi, grid, dim3(kBlock), 0, static_cast<hipStream_t>(stream), d);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -68,6 +68,11 @@ class env_info(ctypes.Structure):
                 ("built_on_device", c_int32)]
 
 
+class env_batch_stats(ctypes.Structure):
+    _fields_ = [("n_items", c_int64), ("grid", c_int32), ("reserved", c_int32),
+                ("launches", c_int64), ("captures", c_int64), ("graph_launches", c_int64)]
+
+
 class EnvError(RuntimeError):
     def __init__(self, status: int, what: str = ""):
         self.status = status
@@ -106,6 +111,17 @@ def lib():
         L.env_potential_export_pairs.restype = c_int32
         L.env_potential_destroy.argtypes = [c_void_p]
         L.env_potential_destroy.restype = None
+        L.env_potential_autotune.argtypes = [c_void_p, c_void_p, c_int64, c_void_p]
+        L.env_potential_autotune.restype = c_int32
+        L.env_batch_create.argtypes = [POINTER(c_void_p), c_int32, POINTER(c_void_p)]
+        L.env_batch_create.restype = c_int32
+        L.env_batch_eval.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_int64),
+                                     POINTER(c_void_p), c_void_p]
+        L.env_batch_eval.restype = c_int32
+        L.env_batch_get_stats.argtypes = [c_void_p, POINTER(env_batch_stats)]
+        L.env_batch_get_stats.restype = c_int32
+        L.env_batch_destroy.argtypes = [c_void_p]
+        L.env_batch_destroy.restype = None
         _lib = L
     return _lib
 
@@ -152,6 +168,47 @@ def env_potential_eval_batched(handles: Sequence[int], points_ptrs: Sequence[int
     st = lib().env_potential_eval_batched(H, k, Pp, N, O, c_void_p(stream))
     if st != ENV_OK:
         raise EnvError(st, "env_potential_eval_batched")
+
+
+def env_potential_autotune(handle: int, points_ptr: int, n: int, stream: int = 0) -> None:
+    st = lib().env_potential_autotune(c_void_p(handle), c_void_p(points_ptr), int(n),
+                                      c_void_p(stream))
+    if st != ENV_OK:
+        raise EnvError(st, "env_potential_autotune")
+
+
+def env_batch_create(handles: Sequence[int]) -> int:
+    k = len(handles)
+    H = (c_void_p * k)(*handles)
+    b = c_void_p()
+    st = lib().env_batch_create(H, k, ctypes.byref(b))
+    if st != ENV_OK:
+        raise EnvError(st, "env_batch_create")
+    return b.value
+
+
+def env_batch_eval(batch: int, points_ptrs: Sequence[int], ns: Sequence[int],
+                   out_ptrs: Sequence[int], stream: int = 0) -> None:
+    k = len(points_ptrs)
+    Pp = (c_void_p * k)(*points_ptrs)
+    N = (c_int64 * k)(*[int(x) for x in ns])
+    O = (c_void_p * k)(*out_ptrs)
+    st = lib().env_batch_eval(c_void_p(batch), Pp, N, O, c_void_p(stream))
+    if st != ENV_OK:
+        raise EnvError(st, "env_batch_eval")
+
+
+def env_batch_get_stats(batch: int) -> dict:
+    s = env_batch_stats()
+    st = lib().env_batch_get_stats(c_void_p(batch), ctypes.byref(s))
+    if st != ENV_OK:
+        raise EnvError(st, "env_batch_get_stats")
+    return {f: getattr(s, f) for f, _ in env_batch_stats._fields_}
+
+
+def env_batch_destroy(batch: int) -> None:
+    if batch:
+        lib().env_batch_destroy(c_void_p(batch))
 
 
 def env_potential_info(handle: int) -> env_info:
@@ -275,9 +332,54 @@ class Environment:
                            stream.cuda_stream)
         return out
 
+    def autotune(self, points, stream=None):
+        """Time the launch shapes at these (n,3) device points; keep the best."""
+        import torch
+        points = points.contiguous()
+        if stream is None:
+            stream = torch.cuda.current_stream(points.device)
+        env_potential_autotune(self.handle, points.data_ptr(), points.shape[0], stream.cuda_stream)
+
     def close(self):
         if self.handle:
             env_potential_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """A persistent-launch plan over several Environments (same precision)."""
+
+    def __init__(self, envs: Sequence[Environment]):
+        self.envs = list(envs)
+        self.handle = env_batch_create([e.handle for e in self.envs])
+
+    def eval(self, points: Sequence, outs: Optional[Sequence] = None, stream=None):
+        import torch
+        if outs is None:
+            outs = [torch.empty(p.shape[0], dtype=torch.float64, device=p.device) for p in points]
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        for p, o in zip(points, outs):
+            if p.dtype != torch.float64 or not p.is_contiguous() or p.dim() != 2 or p.shape[1] != 3:
+                raise TypeError("points must be contiguous float64 (n, 3) tensors")
+            if o.dtype != torch.float64 or not o.is_contiguous() or o.numel() != p.shape[0]:
+                raise TypeError("out must be contiguous float64 tensors of n elements")
+        env_batch_eval(self.handle, [p.data_ptr() for p in points], [p.shape[0] for p in points],
+                       [o.data_ptr() for o in outs], stream.cuda_stream)
+        return outs
+
+    def stats(self) -> dict:
+        return env_batch_get_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            env_batch_destroy(self.handle)
             self.handle = 0
 
     def __del__(self):

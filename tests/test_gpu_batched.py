@@ -1,0 +1,156 @@
+"""Batched persistent launch (env_batch_*) and the autotuner, against the
+oracle and against single evaluations; graph replays are checked one by one
+with eager work and synchronisation between them."""
+import numpy as np
+import pytest
+
+from paper_1011_4687_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+_inst = {}
+
+
+def instances():
+    """Six uneven instances: the tiny environment and five fragmented ones."""
+    if not _inst:
+        from oracle import oracle as O
+        specs = [("tiny", None, 1), ("frag", 50, 300), ("frag", 80, 2000), ("frag", 60, 777),
+                 ("frag", 100, 5000), ("frag", 50, 64)]
+        out = []
+        for k, (kind, na, npts) in enumerate(specs):
+            rng = np.random.Generator(np.random.PCG64(5000 + k))
+            env = synth.make_tiny(rng) if kind == "tiny" else synth.make_fragmented(na, rng)
+            pts = synth.points_in_ball(rng, npts, env.r_qm)
+            sc = O.neutral_scales(env)
+            out.append((env, pts, env.density_csr(sc)))
+        _inst["v"] = out
+    return _inst["v"]
+
+
+def handles(precision):
+    from paper_1011_4687_amd.envpot import Environment
+    hs = []
+    for env, pts, P in instances():
+        shells = [(s.atom, s.l, s.exponents, s.coefs) for s in env.shells]
+        hs.append(Environment(env.xyz, env.Z, env.fragment, shells, P, precision=precision))
+    return hs
+
+
+def oracle_ref(k, idx):
+    from oracle import oracle as O
+    env, pts, P = instances()[k]
+    return O.potential(env, pts[idx], P=P, screen=True)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_batch_matches_oracle_and_single(precision):
+    import torch
+    from paper_1011_4687_amd.envpot import Batch
+    print(f"[batched] {precision}", flush=True)
+    hs = handles(precision)
+    pts = [torch.from_numpy(p).cuda() for _, p, _ in instances()]
+    B = Batch(hs)
+    outs = B.eval(pts)
+    torch.cuda.synchronize()
+    for k, (h, x, o) in enumerate(zip(hs, pts, outs)):
+        single = h.eval(x).cpu().numpy()
+        got = o.cpu().numpy()
+        n = len(got)
+        idx = np.unique(np.linspace(0, n - 1, min(n, 12)).astype(int))
+        Vo, _, _, A = oracle_ref(k, idx)
+        if precision == "fp64":
+            assert np.all(np.abs(got[idx] - Vo) <= 1e-12 * A)
+            assert np.all(np.abs(got - single) <= 1e-12 * np.abs(single).max())
+        else:
+            assert np.abs(got[idx] - Vo).max() <= 1e-5
+            assert np.abs(got - single).max() <= 2e-6
+    st = B.stats()
+    assert st["n_items"] > 0 and st["grid"] > 0
+    B.close()
+
+
+def test_graph_replay_with_eager_work_between():
+    import torch
+    from paper_1011_4687_amd.envpot import Batch
+    hs = handles("fp32c")
+    pts = [torch.from_numpy(p).cuda() for _, p, _ in instances()]
+    outs = [torch.zeros(p.shape[0], dtype=torch.float64, device="cuda") for p in pts]
+    s = torch.cuda.Stream()
+    B = Batch(hs)
+    with torch.cuda.stream(s):
+        B.eval(pts, outs, stream=s)
+    s.synchronize()
+    ref = [o.clone() for o in outs]
+    for rep in range(4):
+        for o in outs:
+            o.fill_(float("nan"))            # eager work between replays
+        junk = torch.randn(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            B.eval(pts, outs, stream=s)
+        s.synchronize()
+        for o, r in zip(outs, ref):
+            assert torch.equal(o, r), rep
+        del junk
+    st = B.stats()
+    assert st["captures"] == 1 and st["graph_launches"] == 5
+    # the captured graph reads the current contents of the same buffers
+    moved = [p * 0.9 for p in pts]
+    for p, m in zip(pts, moved):
+        p.copy_(m)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        B.eval(pts, outs, stream=s)
+    s.synchronize()
+    for h, p, o in zip(hs, pts, outs):
+        single = h.eval(p)
+        torch.cuda.synchronize()
+        assert (o - single).abs().max().item() <= 2e-6
+    # new buffers: one more capture
+    pts2 = [p.clone() for p in pts]
+    with torch.cuda.stream(s):
+        outs2 = B.eval(pts2, stream=s)
+    s.synchronize()
+    assert B.stats()["captures"] == 2
+    for a, b in zip(outs, outs2):
+        assert torch.equal(a, b)
+    B.close()
+
+
+def test_eval_batched_one_shot_equals_plan():
+    import torch
+    from paper_1011_4687_amd import envpot as E
+    hs = handles("fp64")
+    pts = [torch.from_numpy(p).cuda() for _, p, _ in instances()]
+    outs = [torch.empty(p.shape[0], dtype=torch.float64, device="cuda") for p in pts]
+    E.env_potential_eval_batched([h.handle for h in hs], [p.data_ptr() for p in pts],
+                                 [p.shape[0] for p in pts], [o.data_ptr() for o in outs],
+                                 torch.cuda.current_stream().cuda_stream)
+    B = E.Batch(hs)
+    outs2 = B.eval(pts)
+    torch.cuda.synchronize()
+    for a, b in zip(outs, outs2):
+        assert torch.equal(a, b)
+    B.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_autotune_keeps_results(precision):
+    import torch
+    from paper_1011_4687_amd.envpot import Environment
+    from common import workload_scaled
+    from oracle import oracle as O
+    env, pts, P, _ = workload_scaled("mid", n_points=20000)
+    shells = [(s.atom, s.l, s.exponents, s.coefs) for s in env.shells]
+    E = Environment(env.xyz, env.Z, env.fragment, shells, P, precision=precision)
+    x = torch.from_numpy(pts).cuda()
+    E.autotune(x)
+    V = E.eval(x).cpu().numpy()
+    idx = np.array([0, 777, 12345, 19999])
+    Vo, _, _, A = O.potential(env, pts[idx], P=P, screen=True)
+    if precision == "fp64":
+        assert np.all(np.abs(V[idx] - Vo) <= 1e-12 * A)
+    else:
+        assert np.abs(V[idx] - Vo).max() <= 1e-5
+    E.close()
