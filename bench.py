@@ -34,6 +34,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per dispatch of the FP32C kernel from the committed counter
+    runs, or None when the kernel sources changed since they were taken."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", "k_potential_mid_traffic.json")
+    try:
+        rec = json.load(open(path))
+        h = hashlib.sha256()
+        for s in rec["kernel_sources"]:
+            h.update(open(os.path.join(root, s), "rb").read())
+        if h.hexdigest() != rec["kernel_source_sha256"]:
+            return None
+        return rec["traffic_bytes_per_dispatch"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def time_path(E, x, out, steps, warmup, torch):
     for _ in range(warmup):
         E.eval(x, out=out)
@@ -63,6 +81,8 @@ def main():
                     help="points of the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--paths", default="fp32c,fp64")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -105,6 +125,15 @@ def main():
         log(f"[bench] {prec}: {ms:.3f} ms/step, {paths[prec]['point_pairs_per_s']:.4g} pp/s")
         E.close()
 
+    if args.copy_calibration:
+        # plain copy of known size: 256 MiB read + 256 MiB written per launch
+        a = torch.ones(256 << 18, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] copy calibration: 3 x 256 MiB device copies")
+
     head = "fp32c" if "fp32c" in paths else list(paths)[0]
     flops = eval_flops(n, info["n_pairs_by_L"], info["n_nuclei"])
     ms = paths[head]["ms_per_step"]
@@ -140,7 +169,7 @@ def main():
             "peak": peak / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": measured_traffic() if (head == "fp32c" and args.workload == "mid") else None,
         },
         "paths": paths,
     }

@@ -1,0 +1,511 @@
+// gfx950 kernels of the coordinate-MLP surrogate of V(r) inside the QM region.
+//
+// Network: gamma(r) = [cos 2 pi B r, sin 2 pi B r] (BF16) -> 4 x (Linear 128 x 128
+// in BF16 on the matrix cores with FP32 accumulation, bias, SiLU, BF16) ->
+// Linear 128 -> 1 in FP32; V_hat = poly(r/R) + sigma * y.  Training: MSE,
+// straight-through BF16 rounding, Adam on FP32 master weights.
+//
+// All matrix products are one NT kernel: C[M x N] = A[M x K] * Bt[N x K]^T with
+// BF16 row-major operands (K contiguous) and v_mfma_f32_32x32x16_bf16; each
+// wave owns a 32 x 32 tile of C and gridDim.z splits K (partials summed in
+// fixed order by k_reduce_rows).  Operand layout of the instruction (verified
+// on the device): lane l, g = l / 32, r = l % 32 holds A[r][g*8 .. g*8+7] and
+// Bt[r][g*8 .. g*8+7]; result register i holds C[(i/4)*8 + g*4 + i%4][r].
+#include <hip/hip_runtime.h>
+
+#include "surrogate_internal.h"
+
+namespace envpot {
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+__device__ __forceinline__ uint16_t to_bf16(float x) {  // round to nearest even
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+
+__device__ __forceinline__ float dsilu(float z) {
+    const float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+__global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A, int lda,
+                                                 const uint16_t* __restrict__ Bt, int ldb,
+                                                 float* __restrict__ C, int ldc, int M, int N, int K,
+                                                 int kchunk, int64_t cstride) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 5, r = lane & 31;
+    const int tm = (blockIdx.y * 2 + (wave >> 1)) * 32;
+    const int tn = (blockIdx.x * 2 + (wave & 1)) * 32;
+    if (tm >= M || tn >= N) return;  // wave-uniform
+    const int k0 = blockIdx.z * kchunk;
+    const int k1 = min(K, k0 + kchunk);
+    f32x16 acc = {};
+    const uint16_t* a = A + (int64_t)(tm + r) * lda + g * 8;
+    const uint16_t* b = Bt + (int64_t)(tn + r) * ldb + g * 8;
+    for (int k = k0; k < k1; k += 16) {
+        const uint4 av = *reinterpret_cast<const uint4*>(a + k);
+        const uint4 bv = *reinterpret_cast<const uint4*>(b + k);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av),
+                                                      __builtin_bit_cast(bf16x8, bv), acc, 0, 0, 0);
+    }
+    float* c = C + blockIdx.z * cstride;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) c[(int64_t)(tm + (i >> 2) * 8 + g * 4 + (i & 3)) * ldc + tn + r] = acc[i];
+}
+
+// out[j] = sum_{p < P} part[p * L + j], fixed order, FP64 accumulation.
+__global__ __launch_bounds__(256) void k_reduce_rows(const float* __restrict__ part, int P, int64_t L,
+                                                     float* __restrict__ out) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= L) return;
+    double s = 0.0;
+    for (int p = 0; p < P; ++p) s += part[(int64_t)p * L + j];
+    out[j] = (float)s;
+}
+
+// Fourier features of rows < n (zeros in the padding rows), BF16, row-major
+// [Np x 2F] and optionally transposed [2F x ldT].
+__global__ __launch_bounds__(256) void k_features(const double* __restrict__ pts, int64_t n,
+                                                  int64_t Np, const double* __restrict__ B, int F,
+                                                  uint16_t* __restrict__ H, uint16_t* __restrict__ HT,
+                                                  int64_t ldT) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= Np * F) return;
+    const int64_t row = idx / F;
+    const int k = (int)(idx % F);
+    uint16_t c = 0, s = 0;
+    if (row < n) {
+        const double ph = kTwoPi * (B[3 * k] * pts[3 * row] + B[3 * k + 1] * pts[3 * row + 1] +
+                                    B[3 * k + 2] * pts[3 * row + 2]);
+        double sv, cv;
+        sincos(ph, &sv, &cv);
+        c = to_bf16((float)cv);
+        s = to_bf16((float)sv);
+    }
+    H[row * (2 * F) + k] = c;
+    H[row * (2 * F) + F + k] = s;
+    if (HT) {
+        HT[(int64_t)k * ldT + row] = c;
+        HT[(int64_t)(F + k) * ldT + row] = s;
+    }
+}
+
+// Z += bias (kept for the backward pass); H = bf16(silu(Z)), optional H^T.
+__global__ __launch_bounds__(256) void k_bias_silu(float* __restrict__ Z, const float* __restrict__ bias,
+                                                   uint16_t* __restrict__ H, uint16_t* __restrict__ HT,
+                                                   int64_t Np, int64_t ldT) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= Np * kHidden) return;
+    const int64_t row = idx / kHidden;
+    const int col = (int)(idx % kHidden);
+    const float z = Z[idx] + bias[col];
+    Z[idx] = z;
+    const uint16_t h = to_bf16(silu(z));
+    H[idx] = h;
+    if (HT) HT[(int64_t)col * ldT + row] = h;
+}
+
+// y = H . w_out + b_out (FP32, fixed order).
+__global__ __launch_bounds__(256) void k_out_fwd(const uint16_t* __restrict__ H, const float* __restrict__ w,
+                                                 const float* __restrict__ b, int64_t Np, float* __restrict__ y) {
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (row >= Np) return;
+    float s = 0.0f;
+    const uint16_t* h = H + row * kHidden;
+    for (int j = 0; j < kHidden; ++j) s = __builtin_fmaf(__uint_as_float((uint32_t)h[j] << 16), w[j], s);
+    y[row] = s + b[0];
+}
+
+// dy = 2 (y - t)/n on rows < n, 0 on padding; per-block partial of sum (y-t)^2.
+__global__ __launch_bounds__(256) void k_loss(const float* __restrict__ y, const float* __restrict__ t,
+                                              int64_t n, int64_t Np, float* __restrict__ dy,
+                                              double* __restrict__ part) {
+    __shared__ double sh[256];
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double e2 = 0.0;
+    if (row < Np) {
+        float d = 0.0f;
+        if (row < n) {
+            const float e = y[row] - t[row];
+            d = 2.0f * e / (float)n;
+            e2 = (double)e * (double)e;
+        }
+        dy[row] = d;
+    }
+    sh[threadIdx.x] = e2;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// Backward through SiLU for one layer.  dH = dy (x) w_out for the top layer
+// (dH == nullptr), else the given FP32 dH.  Writes bf16(dZ) [Np x 128] and
+// its transpose [128 x ldT], the per-block column sums of dZ (bias
+// gradient) and, for the top layer, the per-block column sums of dy * H
+// (output-weight gradient).  Block: 128 threads (one column), kRowsPerBlock rows.
+__global__ __launch_bounds__(128) void k_dsilu(const float* __restrict__ dH, const float* __restrict__ dy,
+                                               const float* __restrict__ w_out, const float* __restrict__ Z,
+                                               const uint16_t* __restrict__ Htop, int64_t Np,
+                                               uint16_t* __restrict__ dZb, uint16_t* __restrict__ dZT,
+                                               int64_t ldT, float* __restrict__ colsum,
+                                               float* __restrict__ colsum_out) {
+    const int col = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * kRowsPerBlock;
+    const int64_t r1 = min(Np, r0 + kRowsPerBlock);
+    float cs = 0.0f, co = 0.0f;
+    for (int64_t row = r0; row < r1; ++row) {
+        const int64_t idx = row * kHidden + col;
+        float g;
+        if (dH) {
+            g = dH[idx];
+        } else {
+            g = dy[row] * w_out[col];
+            co = __builtin_fmaf(dy[row], __uint_as_float((uint32_t)Htop[idx] << 16), co);
+        }
+        const float dz = g * dsilu(Z[idx]);
+        cs += dz;
+        const uint16_t b = to_bf16(dz);
+        dZb[idx] = b;
+        dZT[(int64_t)col * ldT + row] = b;
+    }
+    colsum[(int64_t)blockIdx.x * kHidden + col] = cs;
+    if (!dH) colsum_out[(int64_t)blockIdx.x * kHidden + col] = co;
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v, int64_t n,
+                                              float lr, float b1, float b2, float eps, float bc1, float bc2) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// BF16 copies of the four hidden weight matrices, as stored (out x in) and transposed.
+__global__ __launch_bounds__(256) void k_pack(const float* __restrict__ params, uint16_t* __restrict__ W,
+                                              uint16_t* __restrict__ WT) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)kLayers * kHidden * kHidden) return;
+    const int l = (int)(idx / (kHidden * kHidden));
+    const int e = (int)(idx % (kHidden * kHidden));
+    const int o = e / kHidden, i = e % kHidden;
+    const uint16_t b = to_bf16(params[(int64_t)l * kLayerStride + e]);
+    W[idx] = b;
+    WT[(int64_t)l * kHidden * kHidden + i * kHidden + o] = b;
+}
+
+// V = poly(r/R) + sigma * y (FP64).
+__global__ __launch_bounds__(256) void k_finish(const double* __restrict__ pts, const float* __restrict__ y,
+                                                int64_t n, const double* __restrict__ coef,
+                                                const int8_t* __restrict__ mono, int nmono, double inv_r,
+                                                double sigma, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double px[kMaxPolyDegree + 1], py[kMaxPolyDegree + 1], pz[kMaxPolyDegree + 1];
+    const double ux = pts[3 * i] * inv_r, uy = pts[3 * i + 1] * inv_r, uz = pts[3 * i + 2] * inv_r;
+    px[0] = py[0] = pz[0] = 1.0;
+    for (int d = 1; d <= kMaxPolyDegree; ++d) {
+        px[d] = px[d - 1] * ux;
+        py[d] = py[d - 1] * uy;
+        pz[d] = pz[d - 1] * uz;
+    }
+    double v = 0.0;
+    for (int k = 0; k < nmono; ++k) v += coef[k] * px[mono[3 * k]] * py[mono[3 * k + 1]] * pz[mono[3 * k + 2]];
+    out[i] = v + sigma * (double)y[i];
+}
+
+// Residual targets t = (V - poly(r/R)) / sigma.
+__global__ __launch_bounds__(256) void k_residual(const double* __restrict__ pts, const double* __restrict__ V,
+                                                  int64_t n, const double* __restrict__ coef,
+                                                  const int8_t* __restrict__ mono, int nmono, double inv_r,
+                                                  double inv_sigma, float* __restrict__ t) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double px[kMaxPolyDegree + 1], py[kMaxPolyDegree + 1], pz[kMaxPolyDegree + 1];
+    const double ux = pts[3 * i] * inv_r, uy = pts[3 * i + 1] * inv_r, uz = pts[3 * i + 2] * inv_r;
+    px[0] = py[0] = pz[0] = 1.0;
+    for (int d = 1; d <= kMaxPolyDegree; ++d) {
+        px[d] = px[d - 1] * ux;
+        py[d] = py[d - 1] * uy;
+        pz[d] = pz[d - 1] * uz;
+    }
+    double v = 0.0;
+    for (int k = 0; k < nmono; ++k) v += coef[k] * px[mono[3 * k]] * py[mono[3 * k + 1]] * pz[mono[3 * k + 2]];
+    t[i] = (float)((V[i] - v) * inv_sigma);
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014): the counter-based generator of the
+// training and gate sample points.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+__device__ __forceinline__ double unif(uint64_t seed, uint64_t ctr) {
+    return (double)(splitmix64(seed ^ splitmix64(ctr)) >> 11) * 0x1.0p-53;
+}
+
+// n points uniform in the ball of radius R, point i from counters 3i..3i+2.
+__global__ __launch_bounds__(256) void k_sample_ball(uint64_t seed, int64_t n, double R, double* __restrict__ pts) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double u0 = unif(seed, 3 * (uint64_t)i), u1 = unif(seed, 3 * (uint64_t)i + 1),
+                 u2 = unif(seed, 3 * (uint64_t)i + 2);
+    const double r = R * cbrt(u0), ct = 2.0 * u1 - 1.0, st = sqrt(fmax(0.0, 1.0 - ct * ct));
+    const double ph = kTwoPi * u2;
+    pts[3 * i] = r * st * cos(ph);
+    pts[3 * i + 1] = r * st * sin(ph);
+    pts[3 * i + 2] = r * ct;
+}
+
+// Gate validation points: per voxel v (of the G^3 grid over [-R, R]^3) m
+// points uniform in the voxel, pulled radially into the ball when outside it.
+__global__ __launch_bounds__(256) void k_sample_voxels(uint64_t seed, int G, int m, double R,
+                                                       double* __restrict__ pts) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t nv = (int64_t)G * G * G;
+    if (i >= nv * m) return;
+    const int64_t v = i / m;
+    const int vx = (int)(v % G), vy = (int)((v / G) % G), vz = (int)(v / ((int64_t)G * G));
+    const double h = 2.0 * R / G;
+    double x = -R + h * (vx + unif(seed, 3 * (uint64_t)i));
+    double y = -R + h * (vy + unif(seed, 3 * (uint64_t)i + 1));
+    double z = -R + h * (vz + unif(seed, 3 * (uint64_t)i + 2));
+    const double rr = sqrt(x * x + y * y + z * z);
+    if (rr > R) {
+        const double s = R * (1.0 - 1e-12) / rr;
+        x *= s;
+        y *= s;
+        z *= s;
+    }
+    pts[3 * i] = x;
+    pts[3 * i + 1] = y;
+    pts[3 * i + 2] = z;
+}
+
+__global__ __launch_bounds__(256) void k_gather(const double* __restrict__ pts, const float* __restrict__ t,
+                                                const int32_t* __restrict__ perm, int64_t start, int64_t bs,
+                                                double* __restrict__ pb, float* __restrict__ tb) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= bs) return;
+    const int64_t j = perm[start + i];
+    pb[3 * i] = pts[3 * j];
+    pb[3 * i + 1] = pts[3 * j + 1];
+    pb[3 * i + 2] = pts[3 * j + 2];
+    tb[i] = t[j];
+}
+
+// Gate: flag[i] = 1 when point i must use the exact kernel (outside the
+// ball or in a voxel that failed validation); per-block counts of flags.
+__global__ __launch_bounds__(256) void k_gate_flags(const double* __restrict__ pts, int64_t n,
+                                                    const uint8_t* __restrict__ pass, int G, double R,
+                                                    uint8_t* __restrict__ flag, int32_t* __restrict__ counts) {
+    __shared__ int32_t sh[256];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int f = 0;
+    if (i < n) {
+        const double x = pts[3 * i], y = pts[3 * i + 1], z = pts[3 * i + 2];
+        f = 1;
+        if (x * x + y * y + z * z <= R * R) {
+            const double h = 2.0 * R / G;
+            const int vx = min(G - 1, max(0, (int)floor((x + R) / h)));
+            const int vy = min(G - 1, max(0, (int)floor((y + R) / h)));
+            const int vz = min(G - 1, max(0, (int)floor((z + R) / h)));
+            f = pass[((int64_t)vz * G + vy) * G + vx] ? 0 : 1;
+        }
+        flag[i] = (uint8_t)f;
+    }
+    sh[threadIdx.x] = f;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) counts[blockIdx.x] = sh[0];
+}
+
+// Exclusive scan of the block counts (one workgroup, sequential chunks).
+__global__ __launch_bounds__(256) void k_scan_counts(const int32_t* __restrict__ counts, int nb,
+                                                     int64_t* __restrict__ offsets, int64_t* __restrict__ total) {
+    __shared__ int64_t sh[256];
+    int64_t carry = 0;
+    for (int base = 0; base < nb; base += 256) {
+        const int i = base + threadIdx.x;
+        const int64_t v = i < nb ? counts[i] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int s = 1; s < 256; s <<= 1) {  // inclusive Hillis-Steele scan
+            const int64_t a = threadIdx.x >= s ? sh[threadIdx.x - s] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += a;
+            __syncthreads();
+        }
+        if (i < nb) offsets[i] = carry + sh[threadIdx.x] - v;
+        const int64_t last = sh[255];
+        __syncthreads();
+        carry += last;
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+// Stable compaction of the flagged points (order of the input kept).
+__global__ __launch_bounds__(256) void k_compact(const double* __restrict__ pts, int64_t n,
+                                                 const uint8_t* __restrict__ flag,
+                                                 const int64_t* __restrict__ offsets,
+                                                 int64_t* __restrict__ idx, double* __restrict__ cpts) {
+    __shared__ int32_t sh[256];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int f = (i < n) ? flag[i] : 0;
+    sh[threadIdx.x] = f;
+    __syncthreads();
+    for (int s = 1; s < 256; s <<= 1) {
+        const int32_t a = threadIdx.x >= s ? sh[threadIdx.x - s] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += a;
+        __syncthreads();
+    }
+    if (f) {
+        const int64_t o = offsets[blockIdx.x] + sh[threadIdx.x] - 1;
+        idx[o] = i;
+        cpts[3 * o] = pts[3 * i];
+        cpts[3 * o + 1] = pts[3 * i + 1];
+        cpts[3 * o + 2] = pts[3 * i + 2];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scatter(const double* __restrict__ vals, const int64_t* __restrict__ idx,
+                                                 int64_t m, double* __restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k < m) out[idx[k]] = vals[k];
+}
+
+// max |a - b| per voxel (m consecutive samples per voxel), FP64.
+__global__ __launch_bounds__(256) void k_voxel_maxerr(const double* __restrict__ a, const double* __restrict__ b,
+                                                      int64_t nv, int m, double* __restrict__ err) {
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (v >= nv) return;
+    double e = 0.0;
+    for (int k = 0; k < m; ++k) e = fmax(e, fabs(a[v * m + k] - b[v * m + k]));
+    err[v] = e;
+}
+
+inline unsigned blocks(int64_t n, int per = 256) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+#define SG_LAUNCH(k, g, b, st, ...) hipLaunchKernelGGL(k, g, b, 0, static_cast<hipStream_t>(st), __VA_ARGS__)
+
+int sg_gemm_nt(const uint16_t* A, int lda, const uint16_t* Bt, int ldb, float* C, int ldc, int M, int N,
+               int K, int ksplit, void* st) {
+    if (M % 32 || N % 32 || K % 16 || lda % 8 || ldb % 8 || ksplit < 1) return -1;
+    int kchunk = (K + ksplit - 1) / ksplit;
+    kchunk = (kchunk + 15) / 16 * 16;
+    const int nz = (K + kchunk - 1) / kchunk;
+    const dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64), (unsigned)nz);
+    SG_LAUNCH(k_gemm_nt, grid, dim3(256), st, A, lda, Bt, ldb, C, ldc, M, N, K, kchunk,
+              (int64_t)M * ldc);
+    return nz;
+}
+
+void sg_reduce_rows(const float* part, int P, int64_t L, float* out, void* st) {
+    SG_LAUNCH(k_reduce_rows, dim3(blocks(L)), dim3(256), st, part, P, L, out);
+}
+
+void sg_features(const double* pts, int64_t n, int64_t Np, const double* B, int F, uint16_t* H,
+                 uint16_t* HT, int64_t ldT, void* st) {
+    SG_LAUNCH(k_features, dim3(blocks(Np * F)), dim3(256), st, pts, n, Np, B, F, H, HT, ldT);
+}
+
+void sg_bias_silu(float* Z, const float* bias, uint16_t* H, uint16_t* HT, int64_t Np, int64_t ldT, void* st) {
+    SG_LAUNCH(k_bias_silu, dim3(blocks(Np * kHidden)), dim3(256), st, Z, bias, H, HT, Np, ldT);
+}
+
+void sg_out_fwd(const uint16_t* H, const float* w, const float* b, int64_t Np, float* y, void* st) {
+    SG_LAUNCH(k_out_fwd, dim3(blocks(Np)), dim3(256), st, H, w, b, Np, y);
+}
+
+void sg_loss(const float* y, const float* t, int64_t n, int64_t Np, float* dy, double* part, void* st) {
+    SG_LAUNCH(k_loss, dim3(blocks(Np)), dim3(256), st, y, t, n, Np, dy, part);
+}
+
+void sg_dsilu(const float* dH, const float* dy, const float* w_out, const float* Z, const uint16_t* Htop,
+              int64_t Np, uint16_t* dZb, uint16_t* dZT, int64_t ldT, float* colsum, float* colsum_out,
+              void* st) {
+    SG_LAUNCH(k_dsilu, dim3(blocks(Np, kRowsPerBlock)), dim3(kHidden), st, dH, dy, w_out, Z, Htop, Np, dZb,
+              dZT, ldT, colsum, colsum_out);
+}
+
+void sg_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
+             float bc1, float bc2, void* st) {
+    SG_LAUNCH(k_adam, dim3(blocks(n)), dim3(256), st, p, g, m, v, n, lr, b1, b2, eps, bc1, bc2);
+}
+
+void sg_pack(const float* params, uint16_t* W, uint16_t* WT, void* st) {
+    SG_LAUNCH(k_pack, dim3(blocks((int64_t)kLayers * kHidden * kHidden)), dim3(256), st, params, W, WT);
+}
+
+void sg_finish(const double* pts, const float* y, int64_t n, const double* coef, const int8_t* mono, int nmono,
+               double inv_r, double sigma, double* out, void* st) {
+    SG_LAUNCH(k_finish, dim3(blocks(n)), dim3(256), st, pts, y, n, coef, mono, nmono, inv_r, sigma, out);
+}
+
+void sg_residual(const double* pts, const double* V, int64_t n, const double* coef, const int8_t* mono,
+                 int nmono, double inv_r, double inv_sigma, float* t, void* st) {
+    SG_LAUNCH(k_residual, dim3(blocks(n)), dim3(256), st, pts, V, n, coef, mono, nmono, inv_r, inv_sigma, t);
+}
+
+void sg_sample_ball(uint64_t seed, int64_t n, double R, double* pts, void* st) {
+    SG_LAUNCH(k_sample_ball, dim3(blocks(n)), dim3(256), st, seed, n, R, pts);
+}
+
+void sg_sample_voxels(uint64_t seed, int G, int m, double R, double* pts, void* st) {
+    SG_LAUNCH(k_sample_voxels, dim3(blocks((int64_t)G * G * G * m)), dim3(256), st, seed, G, m, R, pts);
+}
+
+void sg_gather(const double* pts, const float* t, const int32_t* perm, int64_t start, int64_t bs, double* pb,
+               float* tb, void* st) {
+    SG_LAUNCH(k_gather, dim3(blocks(bs)), dim3(256), st, pts, t, perm, start, bs, pb, tb);
+}
+
+int sg_gate_flags(const double* pts, int64_t n, const uint8_t* pass, int G, double R, uint8_t* flag,
+                  int32_t* counts, void* st) {
+    SG_LAUNCH(k_gate_flags, dim3(blocks(n)), dim3(256), st, pts, n, pass, G, R, flag, counts);
+    return (int)blocks(n);
+}
+
+void sg_scan_counts(const int32_t* counts, int nb, int64_t* offsets, int64_t* total, void* st) {
+    SG_LAUNCH(k_scan_counts, dim3(1), dim3(256), st, counts, nb, offsets, total);
+}
+
+void sg_compact(const double* pts, int64_t n, const uint8_t* flag, const int64_t* offsets, int64_t* idx,
+                double* cpts, void* st) {
+    SG_LAUNCH(k_compact, dim3(blocks(n)), dim3(256), st, pts, n, flag, offsets, idx, cpts);
+}
+
+void sg_scatter(const double* vals, const int64_t* idx, int64_t m, double* out, void* st) {
+    SG_LAUNCH(k_scatter, dim3(blocks(m)), dim3(256), st, vals, idx, m, out);
+}
+
+void sg_voxel_maxerr(const double* a, const double* b, int64_t nv, int m, double* err, void* st) {
+    SG_LAUNCH(k_voxel_maxerr, dim3(blocks(nv)), dim3(256), st, a, b, nv, m, err);
+}
+
+int sg_last_error() { return hipGetLastError() == hipSuccess ? 0 : -1; }
+
+}  // namespace envpot
