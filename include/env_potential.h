@@ -222,6 +222,109 @@ env_status env_potential_export_pairs(const env_potential* h, int64_t cap, int32
                                       int32_t* group, double* center, double* p,
                                       double* D);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate of V inside the QM region (not in the paper: an addition
+ * of this library).  A coordinate MLP with Fourier-feature input,
+ *     gamma(r) = [cos(2 pi B r), sin(2 pi B r)]   (B: 64 x 3, 1/bohr)
+ *     4 hidden layers of 128 SiLU units, BF16 weights on the matrix cores with
+ *     FP32 accumulation, an FP32 output layer 128 -> 1,
+ *     V_hat(r) = poly(r/R) + sigma * y(r),
+ * where poly is a least-squares polynomial baseline (monomials u_x^a u_y^b
+ * u_z^c, a+b+c <= degree, ordered by total degree, then a descending, then b
+ * descending).  It is trained on the GPU on samples of an exact handle; a
+ * voxel gate validated against that handle decides, per point, whether the
+ * network is used or the exact fallback handle is evaluated instead.
+ *
+ * Parameter vector (float32, 66,177 values): W1 (128 x 128, out x in), b1,
+ * W2, b2, W3, b3, W4, b4, w_out (128), b_out.  Network inputs 0..63 are the
+ * cosines, 64..127 the sines.
+ * ------------------------------------------------------------------------ */
+typedef struct env_surrogate env_surrogate;
+
+typedef struct {
+    int32_t n_freq;          /* must be 64 */
+    int32_t hidden;          /* must be 128 */
+    int32_t layers;          /* must be 4 */
+    int32_t poly_degree;     /* 0..8 */
+    double radius;           /* R: the region the surrogate covers is |r| <= R (bohr) */
+    const double* B;         /* n_freq x 3 frequencies (1/bohr), host, copied */
+    const float* params;     /* initial parameters (layout above), host, copied */
+    const double* poly;      /* baseline coefficients (NULL allowed when poly_degree == 0) */
+    double sigma;            /* output scale (<= 0 means 1) */
+    int32_t reserved[4];
+} env_surrogate_spec;
+
+typedef struct {
+    int64_t n_train;         /* samples uniform in the ball (default 2,000,000) */
+    int32_t epochs;          /* default 20 */
+    int32_t batch;           /* multiple of 32, default 8192 */
+    double lr, lr_final;     /* Adam, cosine decay from lr to lr_final */
+    uint64_t seed;           /* SplitMix64 seed of samples and shuffles */
+    int32_t gate_grid;       /* G: voxels per axis over [-R, R]^3 (default 24) */
+    int32_t gate_samples;    /* validation points per voxel (default 8) */
+    double gate_tol;         /* a voxel passes if its max |V_hat - V| <= gate_tol (default 5e-6 Ha) */
+    int64_t n_fit;           /* samples used for the baseline fit (default 131,072) */
+    int32_t poly_degree;     /* baseline degree (default 6) */
+    int32_t reserved[3];
+} env_train_opts;
+
+typedef struct {
+    int64_t n_params;
+    int32_t n_freq, hidden, layers, poly_degree;
+    double radius, sigma, baseline_rms;
+    int64_t train_steps;
+    double final_loss;               /* last minibatch, normalised targets */
+    double epoch_loss[64];           /* last minibatch of each epoch */
+    double teacher_seconds, train_seconds, gate_seconds;
+    int32_t gate_grid, reserved0;
+    int64_t gate_voxels_in_ball, gate_voxels_pass;
+    double gate_pass_volume_fraction; /* share of the ball's volume served by the network */
+    double gate_max_err_passed;       /* largest validation error of a passing voxel */
+    double gate_tol;
+    int64_t last_eval_n, last_eval_fallback;
+} env_surrogate_info;
+
+void env_train_opts_default(env_train_opts* opts);
+
+/* fallback: the exact handle evaluated for gated-out points (FP32C or FP64).
+ * Errors: ENV_E_ARG, ENV_E_STATE (build-only fallback), ENV_E_UNSUPPORTED
+ * (other sizes), ENV_E_NOMEM, ENV_E_DEVICE.  Synchronises the device once. */
+env_status env_surrogate_create(env_potential* fallback, const env_surrogate_spec* spec,
+                                env_surrogate** out);
+
+/* Trains on opts->n_train points drawn uniformly in the ball with values from
+ * `teacher`, fits the baseline, runs Adam, then validates the voxel gate
+ * against `teacher`.  Synchronous.  Must not overlap other calls on s. */
+env_status env_surrogate_train(env_surrogate* s, env_potential* teacher, const env_train_opts* opts,
+                               void* stream);
+
+/* Network + baseline at n device points (no gate): device out[n] float64. */
+env_status env_surrogate_predict(env_surrogate* s, const double* points, int64_t n, double* out,
+                                 void* stream);
+
+/* Gated evaluation: points outside the ball or in a failed voxel are
+ * evaluated by the exact fallback handle (the same values env_potential_eval
+ * gives for the compacted list of those points); used_fallback (device, n
+ * bytes, may be NULL) receives 1 for them.  Synchronises the stream once (to
+ * size the fallback launch).  ENV_E_STATE before training. */
+env_status env_surrogate_eval(env_surrogate* s, const double* points, int64_t n, double* out,
+                              uint8_t* used_fallback, void* stream);
+
+/* Diagnostic: loss mean((y - t)^2) and its gradient (host, 66,177 floats) for
+ * the current parameters at n device points with device targets t (float32,
+ * normalised).  Synchronous. */
+env_status env_surrogate_loss_grad(env_surrogate* s, const double* points, const float* targets,
+                                   int64_t n, float* grad_host, double* loss, void* stream);
+
+/* Current parameters (host, 66,177 floats), baseline coefficients and sigma;
+ * any pointer may be NULL. */
+env_status env_surrogate_get_params(const env_surrogate* s, float* params, double* poly,
+                                    double* sigma);
+
+env_status env_surrogate_get_info(const env_surrogate* s, env_surrogate_info* info);
+
+void env_surrogate_destroy(env_surrogate* s);
+
 void env_potential_destroy(env_potential* h);
 
 const char* env_status_string(env_status s);

@@ -1,0 +1,641 @@
+// Host driver of the coordinate-MLP surrogate (env_surrogate_*): training on
+// samples of the exact kernel, a validated voxel gate, and gated evaluation
+// that sends every point outside the gate to the exact kernel.  The learned
+// model is this build's addition; the paper has none.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <random>
+#include <vector>
+
+#include "handle.h"
+#include "surrogate_internal.h"
+
+using namespace envpot;
+
+namespace {
+
+struct Workspace {
+    int64_t cap = 0;    // rows (multiple of 32)
+    bool train = false;
+    uint16_t* H[kLayers + 1] = {};
+    uint16_t* HT[kLayers + 1] = {};
+    float* Z[kLayers] = {};
+    float* y = nullptr;
+    float* dy = nullptr;
+    uint16_t* dZb = nullptr;
+    uint16_t* dZT = nullptr;
+    float* dH = nullptr;
+    float* gpart = nullptr;     // split-K partials of dW: kSplitK x 128 x 128
+    float* colb = nullptr;      // per-block column sums (bias gradient)
+    float* colo = nullptr;      // per-block column sums (output weights)
+    double* losspart = nullptr;
+};
+
+constexpr int kSplitK = 16;
+
+template <typename T>
+bool dalloc(T** p, size_t n) {
+    return hipMalloc(reinterpret_cast<void**>(p), std::max<size_t>(n, 1) * sizeof(T)) == hipSuccess;
+}
+
+void ws_free(Workspace& w) {
+    for (int l = 0; l <= kLayers; ++l) {
+        (void)hipFree(w.H[l]);
+        (void)hipFree(w.HT[l]);
+        w.H[l] = w.HT[l] = nullptr;
+    }
+    for (int l = 0; l < kLayers; ++l) {
+        (void)hipFree(w.Z[l]);
+        w.Z[l] = nullptr;
+    }
+    (void)hipFree(w.y);
+    (void)hipFree(w.dy);
+    (void)hipFree(w.dZb);
+    (void)hipFree(w.dZT);
+    (void)hipFree(w.dH);
+    (void)hipFree(w.gpart);
+    (void)hipFree(w.colb);
+    (void)hipFree(w.colo);
+    (void)hipFree(w.losspart);
+    w = Workspace();
+}
+
+bool ws_ensure(Workspace& w, int64_t rows, bool train) {
+    if (w.cap >= rows && (w.train || !train)) return true;
+    const int64_t cap = std::max(rows, w.cap);
+    ws_free(w);
+    w.cap = cap;
+    w.train = train;
+    bool ok = true;
+    for (int l = 0; l <= kLayers; ++l) {
+        ok = ok && dalloc(&w.H[l], size_t(cap) * kHidden);
+        if (train) ok = ok && dalloc(&w.HT[l], size_t(cap) * kHidden);
+    }
+    for (int l = 0; l < kLayers; ++l) ok = ok && dalloc(&w.Z[l], size_t(cap) * kHidden);
+    ok = ok && dalloc(&w.y, cap);
+    if (train) {
+        const int64_t nb = (cap + kRowsPerBlock - 1) / kRowsPerBlock;
+        ok = ok && dalloc(&w.dy, cap) && dalloc(&w.dZb, size_t(cap) * kHidden) &&
+             dalloc(&w.dZT, size_t(cap) * kHidden) && dalloc(&w.dH, size_t(cap) * kHidden) &&
+             dalloc(&w.gpart, size_t(kSplitK) * kHidden * kHidden) && dalloc(&w.colb, size_t(nb) * kHidden) &&
+             dalloc(&w.colo, size_t(nb) * kHidden) && dalloc(&w.losspart, size_t((cap + 255) / 256));
+    }
+    if (!ok) ws_free(w);
+    return ok;
+}
+
+std::vector<int8_t> monomials(int degree) {
+    std::vector<int8_t> m;
+    for (int k = 0; k <= degree; ++k)
+        for (int a = k; a >= 0; --a)
+            for (int b = k - a; b >= 0; --b) {
+                m.push_back(int8_t(a));
+                m.push_back(int8_t(b));
+                m.push_back(int8_t(k - a - b));
+            }
+    return m;
+}
+
+int64_t round32(int64_t n) { return std::max<int64_t>(32, (n + 31) / 32 * 32); }
+
+}  // namespace
+
+struct env_surrogate {
+    env_potential* fallback = nullptr;
+    int device = -1;
+    double radius = 6.0;
+    int degree = 0;
+    std::vector<int8_t> mono;
+    std::vector<double> coef;
+    double sigma = 1.0;
+    // device
+    double* d_B = nullptr;
+    float* d_params = nullptr;
+    float* d_grad = nullptr;
+    float* d_m = nullptr;
+    float* d_v = nullptr;
+    uint16_t* d_W = nullptr;
+    uint16_t* d_WT = nullptr;
+    double* d_coef = nullptr;
+    int8_t* d_mono = nullptr;
+    uint8_t* d_pass = nullptr;
+    int G = 0;
+    int64_t step = 0;
+    Workspace ws;
+    env_surrogate_info info{};
+};
+
+namespace {
+
+env_status upload_baseline(env_surrogate* s) {
+    (void)hipFree(s->d_coef);
+    (void)hipFree(s->d_mono);
+    s->d_coef = nullptr;
+    s->d_mono = nullptr;
+    if (!dalloc(&s->d_coef, s->coef.size()) || !dalloc(&s->d_mono, s->mono.size())) return ENV_E_NOMEM;
+    if (hipMemcpy(s->d_coef, s->coef.data(), s->coef.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(s->d_mono, s->mono.data(), s->mono.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return ENV_E_DEVICE;
+    return ENV_OK;
+}
+
+// Forward pass of rows [0, Np) whose first n are real points; y in ws.y.
+void forward(env_surrogate* s, const double* pts, int64_t n, int64_t Np, bool train, void* st) {
+    Workspace& w = s->ws;
+    sg_features(pts, n, Np, s->d_B, kFreq, w.H[0], train ? w.HT[0] : nullptr, Np, st);
+    for (int l = 0; l < kLayers; ++l) {
+        sg_gemm_nt(w.H[l], kHidden, s->d_W + size_t(l) * kHidden * kHidden, kHidden, w.Z[l], kHidden, int(Np),
+                   kHidden, kHidden, 1, st);
+        sg_bias_silu(w.Z[l], s->d_params + size_t(l) * kLayerStride + kHidden * kHidden, w.H[l + 1],
+                     train ? w.HT[l + 1] : nullptr, Np, Np, st);
+    }
+    sg_out_fwd(w.H[kLayers], s->d_params + kOutOffset, s->d_params + kOutOffset + kHidden, Np, w.y, st);
+}
+
+// Loss partials and the full gradient into d_grad (forward must have run with train = true).
+void backward(env_surrogate* s, const float* t, int64_t n, int64_t Np, void* st) {
+    Workspace& w = s->ws;
+    sg_loss(w.y, t, n, Np, w.dy, w.losspart, st);
+    const int nb = int((Np + kRowsPerBlock - 1) / kRowsPerBlock);
+    for (int l = kLayers - 1; l >= 0; --l) {
+        const bool top = l == kLayers - 1;
+        sg_dsilu(top ? nullptr : w.dH, w.dy, s->d_params + kOutOffset, w.Z[l], w.H[kLayers], Np, w.dZb, w.dZT,
+                 Np, w.colb, w.colo, st);
+        float* gl = s->d_grad + size_t(l) * kLayerStride;
+        sg_reduce_rows(w.colb, nb, kHidden, gl + kHidden * kHidden, st);
+        if (top) {
+            sg_reduce_rows(w.colo, nb, kHidden, s->d_grad + kOutOffset, st);
+            sg_reduce_rows(w.dy, int(Np), 1, s->d_grad + kOutOffset + kHidden, st);
+        }
+        const int nz = sg_gemm_nt(w.dZT, int(Np), w.HT[l], int(Np), w.gpart, kHidden, kHidden, kHidden, int(Np),
+                                  kSplitK, st);
+        sg_reduce_rows(w.gpart, nz, int64_t(kHidden) * kHidden, gl, st);
+        if (l > 0)
+            sg_gemm_nt(w.dZb, kHidden, s->d_WT + size_t(l) * kHidden * kHidden, kHidden, w.dH, kHidden, int(Np),
+                       kHidden, kHidden, 1, st);
+    }
+}
+
+// Surrogate values (baseline + network) at n points, in chunks.
+env_status predict(env_surrogate* s, const double* pts, int64_t n, double* out, void* st) {
+    const int64_t chunk = 65536;
+    if (!ws_ensure(s->ws, std::min(round32(n), chunk), s->ws.train)) return ENV_E_NOMEM;
+    for (int64_t o = 0; o < n; o += chunk) {
+        const int64_t m = std::min(chunk, n - o);
+        const int64_t Np = round32(m);
+        forward(s, pts + 3 * o, m, Np, false, st);
+        sg_finish(pts + 3 * o, s->ws.y, m, s->d_coef, s->d_mono, int(s->mono.size() / 3), 1.0 / s->radius,
+                  s->sigma, out + o, st);
+    }
+    return sg_last_error() == 0 ? ENV_OK : ENV_E_DEVICE;
+}
+
+// Least-squares fit of the polynomial baseline (normal equations, Cholesky, FP64).
+bool fit_baseline(const std::vector<double>& P, const std::vector<double>& V, const std::vector<int8_t>& mono,
+                  double R, std::vector<double>& coef, double& rms) {
+    const size_t m = mono.size() / 3, n = V.size();
+    std::vector<double> A(m * m, 0.0), b(m, 0.0), row(m);
+    for (size_t i = 0; i < n; ++i) {
+        const double u[3] = {P[3 * i] / R, P[3 * i + 1] / R, P[3 * i + 2] / R};
+        for (size_t k = 0; k < m; ++k)
+            row[k] = std::pow(u[0], mono[3 * k]) * std::pow(u[1], mono[3 * k + 1]) * std::pow(u[2], mono[3 * k + 2]);
+        for (size_t a = 0; a < m; ++a) {
+            b[a] += row[a] * V[i];
+            for (size_t c = 0; c <= a; ++c) A[a * m + c] += row[a] * row[c];
+        }
+    }
+    for (size_t a = 0; a < m; ++a) {  // Cholesky A = L L^T in place (lower)
+        for (size_t c = 0; c <= a; ++c) {
+            double sum = A[a * m + c];
+            for (size_t k = 0; k < c; ++k) sum -= A[a * m + k] * A[c * m + k];
+            if (a == c) {
+                if (!(sum > 0.0)) return false;
+                A[a * m + a] = std::sqrt(sum);
+            } else {
+                A[a * m + c] = sum / A[c * m + c];
+            }
+        }
+    }
+    coef.assign(m, 0.0);
+    std::vector<double> z(m);
+    for (size_t a = 0; a < m; ++a) {
+        double sum = b[a];
+        for (size_t k = 0; k < a; ++k) sum -= A[a * m + k] * z[k];
+        z[a] = sum / A[a * m + a];
+    }
+    for (size_t a = m; a-- > 0;) {
+        double sum = z[a];
+        for (size_t k = a + 1; k < m; ++k) sum -= A[k * m + a] * coef[k];
+        coef[a] = sum / A[a * m + a];
+    }
+    double ss = 0.0;
+    for (size_t i = 0; i < n; ++i) {
+        const double u[3] = {P[3 * i] / R, P[3 * i + 1] / R, P[3 * i + 2] / R};
+        double v = 0.0;
+        for (size_t k = 0; k < m; ++k)
+            v += coef[k] * std::pow(u[0], mono[3 * k]) * std::pow(u[1], mono[3 * k + 1]) *
+                 std::pow(u[2], mono[3 * k + 2]);
+        ss += (V[i] - v) * (V[i] - v);
+    }
+    rms = std::sqrt(ss / std::max<size_t>(n, 1));
+    return true;
+}
+
+void destroy(env_surrogate* s) {
+    DeviceGuard g(s->device);
+    ws_free(s->ws);
+    (void)hipFree(s->d_B);
+    (void)hipFree(s->d_params);
+    (void)hipFree(s->d_grad);
+    (void)hipFree(s->d_m);
+    (void)hipFree(s->d_v);
+    (void)hipFree(s->d_W);
+    (void)hipFree(s->d_WT);
+    (void)hipFree(s->d_coef);
+    (void)hipFree(s->d_mono);
+    (void)hipFree(s->d_pass);
+    delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+void env_train_opts_default(env_train_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->n_train = 2000000;
+    o->epochs = 20;
+    o->batch = 8192;
+    o->lr = 2e-3;
+    o->lr_final = 2e-5;
+    o->seed = 12345;
+    o->gate_grid = 24;
+    o->gate_samples = 8;
+    o->gate_tol = 5e-6;
+    o->n_fit = 131072;
+    o->poly_degree = 6;
+}
+
+env_status env_surrogate_create(env_potential* fallback, const env_surrogate_spec* spec, env_surrogate** out) {
+    if (!out) return ENV_E_ARG;
+    *out = nullptr;
+    if (!fallback || !spec || !spec->B || !spec->params) return ENV_E_ARG;
+    if (!fallback->on_device) return ENV_E_STATE;
+    if (spec->n_freq != kFreq || spec->hidden != kHidden || spec->layers != kLayers) return ENV_E_UNSUPPORTED;
+    if (!(spec->radius > 0.0) || spec->poly_degree < 0 || spec->poly_degree > kMaxPolyDegree) return ENV_E_ARG;
+    if (spec->poly_degree > 0 && !spec->poly) return ENV_E_ARG;
+    env_surrogate* s = new (std::nothrow) env_surrogate();
+    if (!s) return ENV_E_NOMEM;
+    s->fallback = fallback;
+    s->device = fallback->device;
+    s->radius = spec->radius;
+    s->degree = spec->poly_degree;
+    s->mono = monomials(s->degree);
+    s->coef.assign(s->mono.size() / 3, 0.0);
+    if (spec->poly) std::copy(spec->poly, spec->poly + s->coef.size(), s->coef.begin());
+    s->sigma = spec->sigma > 0.0 ? spec->sigma : 1.0;
+    DeviceGuard g(s->device);
+    bool ok = dalloc(&s->d_B, 3 * kFreq) && dalloc(&s->d_params, kNParams) && dalloc(&s->d_grad, kNParams) &&
+              dalloc(&s->d_m, kNParams) && dalloc(&s->d_v, kNParams) &&
+              dalloc(&s->d_W, size_t(kLayers) * kHidden * kHidden) &&
+              dalloc(&s->d_WT, size_t(kLayers) * kHidden * kHidden);
+    if (!ok) {
+        destroy(s);
+        return ENV_E_NOMEM;
+    }
+    if (hipMemcpy(s->d_B, spec->B, 3 * kFreq * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(s->d_params, spec->params, kNParams * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(s->d_m, 0, kNParams * sizeof(float)) != hipSuccess ||
+        hipMemset(s->d_v, 0, kNParams * sizeof(float)) != hipSuccess) {
+        destroy(s);
+        return ENV_E_DEVICE;
+    }
+    env_status st = upload_baseline(s);
+    if (st != ENV_OK) {
+        destroy(s);
+        return st;
+    }
+    sg_pack(s->d_params, s->d_W, s->d_WT, nullptr);
+    if (sg_last_error() != 0 || hipDeviceSynchronize() != hipSuccess) {
+        destroy(s);
+        return ENV_E_DEVICE;
+    }
+    s->info.n_params = kNParams;
+    s->info.n_freq = kFreq;
+    s->info.hidden = kHidden;
+    s->info.layers = kLayers;
+    s->info.poly_degree = s->degree;
+    s->info.radius = s->radius;
+    s->info.sigma = s->sigma;
+    *out = s;
+    return ENV_OK;
+}
+
+env_status env_surrogate_predict(env_surrogate* s, const double* points, int64_t n, double* out, void* stream) {
+    if (!s || n < 0) return ENV_E_ARG;
+    if (n == 0) return ENV_OK;
+    if (!points || !out) return ENV_E_ARG;
+    DeviceGuard g(s->device);
+    return predict(s, points, n, out, stream);
+}
+
+env_status env_surrogate_loss_grad(env_surrogate* s, const double* points, const float* targets, int64_t n,
+                                   float* grad_host, double* loss, void* stream) {
+    if (!s || n <= 0 || !points || !targets) return ENV_E_ARG;
+    DeviceGuard g(s->device);
+    const int64_t Np = round32(n);
+    if (!ws_ensure(s->ws, Np, true)) return ENV_E_NOMEM;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    forward(s, points, n, Np, true, stream);
+    backward(s, targets, n, Np, stream);
+    if (sg_last_error() != 0) return ENV_E_DEVICE;
+    std::vector<double> lp((Np + 255) / 256);
+    if (hipMemcpyAsync(lp.data(), s->ws.losspart, lp.size() * sizeof(double), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        (grad_host && hipMemcpyAsync(grad_host, s->d_grad, kNParams * sizeof(float), hipMemcpyDeviceToHost, st) !=
+                          hipSuccess) ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return ENV_E_DEVICE;
+    double L = 0.0;
+    for (double v : lp) L += v;
+    if (loss) *loss = L / double(n);
+    return ENV_OK;
+}
+
+env_status env_surrogate_train(env_surrogate* s, env_potential* teacher, const env_train_opts* opts, void* stream) {
+    if (!s || !teacher) return ENV_E_ARG;
+    if (!teacher->on_device) return ENV_E_STATE;
+    env_train_opts o;
+    if (opts) o = *opts;
+    else env_train_opts_default(&o);
+    if (o.n_train < 1024 || o.batch < 32 || o.batch % 32 || o.epochs < 1 || !(o.lr > 0.0) ||
+        o.gate_grid < 1 || o.gate_samples < 1 || o.poly_degree < 0 || o.poly_degree > kMaxPolyDegree ||
+        o.n_fit < 1)
+        return ENV_E_ARG;
+    DeviceGuard g(s->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = o.n_train;
+    double* d_pts = nullptr;
+    double* d_V = nullptr;
+    float* d_t = nullptr;
+    int32_t* d_perm = nullptr;
+    double* d_pb = nullptr;
+    float* d_tb = nullptr;
+    env_status rc = ENV_OK;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(d_pts);
+        (void)hipFree(d_V);
+        (void)hipFree(d_t);
+        (void)hipFree(d_perm);
+        (void)hipFree(d_pb);
+        (void)hipFree(d_tb);
+    };
+    if (!dalloc(&d_pts, 3 * size_t(n)) || !dalloc(&d_V, n) || !dalloc(&d_t, n) || !dalloc(&d_perm, n) ||
+        !dalloc(&d_pb, 3 * size_t(o.batch)) || !dalloc(&d_tb, o.batch) || !ws_ensure(s->ws, o.batch, true)) {
+        cleanup();
+        return ENV_E_NOMEM;
+    }
+    // 1. training samples and their exact values
+    sg_sample_ball(o.seed, n, s->radius, d_pts, stream);
+    rc = env_potential_eval(teacher, d_pts, n, d_V, stream);
+    if (rc != ENV_OK) {
+        cleanup();
+        return rc;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) {
+        cleanup();
+        return ENV_E_DEVICE;
+    }
+    const auto t1 = std::chrono::steady_clock::now();
+    // 2. polynomial baseline on a subsample, residual targets
+    const int64_t nf = std::min(n, o.n_fit);
+    std::vector<double> hp(3 * size_t(nf)), hv(nf);
+    if (hipMemcpy(hp.data(), d_pts, hp.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(hv.data(), d_V, hv.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+        cleanup();
+        return ENV_E_DEVICE;
+    }
+    s->degree = o.poly_degree;
+    s->mono = monomials(s->degree);
+    double rms = 0.0;
+    if (!fit_baseline(hp, hv, s->mono, s->radius, s->coef, rms)) {
+        cleanup();
+        return ENV_E_ARG;
+    }
+    s->sigma = rms > 0.0 ? rms : 1.0;
+    rc = upload_baseline(s);
+    if (rc != ENV_OK) {
+        cleanup();
+        return rc;
+    }
+    sg_residual(d_pts, d_V, n, s->d_coef, s->d_mono, int(s->mono.size() / 3), 1.0 / s->radius, 1.0 / s->sigma,
+                d_t, stream);
+    // 3. Adam on minibatches, cosine learning-rate decay
+    const int64_t steps_per_epoch = n / o.batch;
+    const int64_t total = steps_per_epoch * o.epochs;
+    std::mt19937_64 gen(o.seed ^ 0x5DEECE66Dull);
+    std::vector<int32_t> perm(n);
+    double last_loss = 0.0;
+    for (int ep = 0; ep < o.epochs && rc == ENV_OK; ++ep) {
+        for (int64_t i = 0; i < n; ++i) perm[i] = int32_t(i);
+        std::shuffle(perm.begin(), perm.end(), gen);
+        if (hipMemcpyAsync(d_perm, perm.data(), size_t(n) * sizeof(int32_t), hipMemcpyHostToDevice, st) !=
+            hipSuccess) {
+            rc = ENV_E_DEVICE;
+            break;
+        }
+        for (int64_t k = 0; k < steps_per_epoch; ++k) {
+            sg_gather(d_pts, d_t, d_perm, k * o.batch, o.batch, d_pb, d_tb, stream);
+            forward(s, d_pb, o.batch, o.batch, true, stream);
+            backward(s, d_tb, o.batch, o.batch, stream);
+            ++s->step;
+            const double frac = double(s->step) / double(std::max<int64_t>(total, 1));
+            const double lr = o.lr_final + 0.5 * (o.lr - o.lr_final) * (1.0 + std::cos(M_PI * std::min(1.0, frac)));
+            const float bc1 = float(1.0 - std::pow(0.9, double(s->step)));
+            const float bc2 = float(1.0 - std::pow(0.999, double(s->step)));
+            sg_adam(s->d_params, s->d_grad, s->d_m, s->d_v, kNParams, float(lr), 0.9f, 0.999f, 1e-8f, bc1, bc2,
+                    stream);
+            sg_pack(s->d_params, s->d_W, s->d_WT, stream);
+        }
+        // loss of the last minibatch of the epoch
+        std::vector<double> lp((o.batch + 255) / 256);
+        if (sg_last_error() != 0 ||
+            hipMemcpyAsync(lp.data(), s->ws.losspart, lp.size() * sizeof(double), hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            rc = ENV_E_DEVICE;
+            break;
+        }
+        last_loss = 0.0;
+        for (double v : lp) last_loss += v;
+        last_loss /= double(o.batch);
+        if (ep < int(sizeof(s->info.epoch_loss) / sizeof(double))) s->info.epoch_loss[ep] = last_loss;
+    }
+    const auto t2 = std::chrono::steady_clock::now();
+    // 4. gate: m validation points per voxel of a G^3 grid over the ball
+    if (rc == ENV_OK) {
+        const int G = o.gate_grid, m = o.gate_samples;
+        const int64_t nv = int64_t(G) * G * G, nvp = nv * m;
+        double *d_vp = nullptr, *d_ve = nullptr, *d_vs = nullptr, *d_err = nullptr;
+        if (!dalloc(&d_vp, 3 * size_t(nvp)) || !dalloc(&d_ve, nvp) || !dalloc(&d_vs, nvp) || !dalloc(&d_err, nv)) {
+            rc = ENV_E_NOMEM;
+        } else {
+            sg_sample_voxels(o.seed ^ 0xA5A5A5A5ull, G, m, s->radius, d_vp, stream);
+            rc = env_potential_eval(teacher, d_vp, nvp, d_ve, stream);
+            if (rc == ENV_OK) rc = predict(s, d_vp, nvp, d_vs, stream);
+            if (rc == ENV_OK) sg_voxel_maxerr(d_ve, d_vs, nv, m, d_err, stream);
+            std::vector<double> err(nv);
+            if (rc == ENV_OK &&
+                (hipMemcpyAsync(err.data(), d_err, nv * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+                 hipStreamSynchronize(st) != hipSuccess))
+                rc = ENV_E_DEVICE;
+            if (rc == ENV_OK) {
+                std::vector<uint8_t> pass(nv, 0);
+                const double h = 2.0 * s->radius / G, R = s->radius;
+                int64_t in_ball = 0, passed = 0;
+                double vol_in = 0.0, vol_pass = 0.0, maxpass = 0.0;
+                for (int64_t v = 0; v < nv; ++v) {
+                    const int vx = int(v % G), vy = int((v / G) % G), vz = int(v / (int64_t(G) * G));
+                    // nearest point of the voxel to the centre: does it touch the ball?
+                    auto nearest = [&](int i) {
+                        const double lo = -R + h * i, hi = lo + h;
+                        return lo > 0 ? lo : (hi < 0 ? hi : 0.0);
+                    };
+                    const double dx = nearest(vx), dy = nearest(vy), dz = nearest(vz);
+                    if (dx * dx + dy * dy + dz * dz > R * R) continue;
+                    ++in_ball;
+                    // volume weight: fraction of the voxel's corners inside the ball
+                    int inside = 0;
+                    for (int c = 0; c < 8; ++c) {
+                        const double cx = -R + h * (vx + (c & 1)), cy = -R + h * (vy + ((c >> 1) & 1)),
+                                     cz = -R + h * (vz + ((c >> 2) & 1));
+                        inside += (cx * cx + cy * cy + cz * cz <= R * R);
+                    }
+                    const double wv = (inside + 1) / 9.0;
+                    vol_in += wv;
+                    if (err[v] <= o.gate_tol) {
+                        pass[v] = 1;
+                        ++passed;
+                        vol_pass += wv;
+                        maxpass = std::max(maxpass, err[v]);
+                    }
+                }
+                (void)hipFree(s->d_pass);
+                s->d_pass = nullptr;
+                if (!dalloc(&s->d_pass, nv) ||
+                    hipMemcpy(s->d_pass, pass.data(), nv, hipMemcpyHostToDevice) != hipSuccess) {
+                    rc = ENV_E_DEVICE;
+                } else {
+                    s->G = G;
+                    s->info.gate_grid = G;
+                    s->info.gate_voxels_in_ball = in_ball;
+                    s->info.gate_voxels_pass = passed;
+                    s->info.gate_pass_volume_fraction = vol_in > 0 ? vol_pass / vol_in : 0.0;
+                    s->info.gate_max_err_passed = maxpass;
+                    s->info.gate_tol = o.gate_tol;
+                }
+            }
+        }
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(d_vp);
+        (void)hipFree(d_ve);
+        (void)hipFree(d_vs);
+        (void)hipFree(d_err);
+    }
+    const auto t3 = std::chrono::steady_clock::now();
+    cleanup();
+    if (rc != ENV_OK) return rc;
+    s->info.sigma = s->sigma;
+    s->info.poly_degree = s->degree;
+    s->info.baseline_rms = rms;
+    s->info.train_steps = s->step;
+    s->info.final_loss = last_loss;
+    s->info.teacher_seconds = std::chrono::duration<double>(t1 - t0).count();
+    s->info.train_seconds = std::chrono::duration<double>(t2 - t1).count();
+    s->info.gate_seconds = std::chrono::duration<double>(t3 - t2).count();
+    return ENV_OK;
+}
+
+env_status env_surrogate_eval(env_surrogate* s, const double* points, int64_t n, double* out,
+                              uint8_t* used_fallback, void* stream) {
+    if (!s || n < 0) return ENV_E_ARG;
+    if (n == 0) return ENV_OK;
+    if (!points || !out) return ENV_E_ARG;
+    if (!s->d_pass) return ENV_E_STATE;  // no gate before training
+    DeviceGuard g(s->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int nb = int((n + 255) / 256);
+    uint8_t* flag = nullptr;
+    int32_t* counts = nullptr;
+    int64_t *offs = nullptr, *total = nullptr, *idx = nullptr;
+    double *cpts = nullptr, *vals = nullptr;
+    bool ok = hipMallocAsync(reinterpret_cast<void**>(&flag), size_t(n), st) == hipSuccess &&
+              hipMallocAsync(reinterpret_cast<void**>(&counts), size_t(nb) * 4, st) == hipSuccess &&
+              hipMallocAsync(reinterpret_cast<void**>(&offs), size_t(nb) * 8, st) == hipSuccess &&
+              hipMallocAsync(reinterpret_cast<void**>(&total), 8, st) == hipSuccess;
+    env_status rc = ok ? ENV_OK : ENV_E_NOMEM;
+    int64_t m = 0;
+    if (rc == ENV_OK) {
+        sg_gate_flags(points, n, s->d_pass, s->G, s->radius, flag, counts, stream);
+        sg_scan_counts(counts, nb, offs, total, stream);
+        if (hipMemcpyAsync(&m, total, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            rc = ENV_E_DEVICE;
+    }
+    if (rc == ENV_OK) rc = predict(s, points, n, out, stream);
+    if (rc == ENV_OK && m > 0) {
+        if (hipMallocAsync(reinterpret_cast<void**>(&idx), size_t(m) * 8, st) != hipSuccess ||
+            hipMallocAsync(reinterpret_cast<void**>(&cpts), size_t(m) * 24, st) != hipSuccess ||
+            hipMallocAsync(reinterpret_cast<void**>(&vals), size_t(m) * 8, st) != hipSuccess) {
+            rc = ENV_E_NOMEM;
+        } else {
+            sg_compact(points, n, flag, offs, idx, cpts, stream);
+            rc = env_potential_eval(s->fallback, cpts, m, vals, stream);
+            if (rc == ENV_OK) sg_scatter(vals, idx, m, out, stream);
+        }
+    }
+    if (rc == ENV_OK && used_fallback &&
+        hipMemcpyAsync(used_fallback, flag, size_t(n), hipMemcpyDeviceToDevice, st) != hipSuccess)
+        rc = ENV_E_DEVICE;
+    if (rc == ENV_OK && sg_last_error() != 0) rc = ENV_E_DEVICE;
+    (void)hipFreeAsync(flag, st);
+    (void)hipFreeAsync(counts, st);
+    (void)hipFreeAsync(offs, st);
+    (void)hipFreeAsync(total, st);
+    if (idx) (void)hipFreeAsync(idx, st);
+    if (cpts) (void)hipFreeAsync(cpts, st);
+    if (vals) (void)hipFreeAsync(vals, st);
+    s->info.last_eval_n = n;
+    s->info.last_eval_fallback = m;
+    return rc;
+}
+
+env_status env_surrogate_get_params(const env_surrogate* s, float* params, double* poly, double* sigma) {
+    if (!s) return ENV_E_ARG;
+    DeviceGuard g(s->device);
+    if (params && hipMemcpy(params, s->d_params, kNParams * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+        return ENV_E_DEVICE;
+    if (poly) std::copy(s->coef.begin(), s->coef.end(), poly);
+    if (sigma) *sigma = s->sigma;
+    return ENV_OK;
+}
+
+env_status env_surrogate_get_info(const env_surrogate* s, env_surrogate_info* info) {
+    if (!s || !info) return ENV_E_ARG;
+    *info = s->info;
+    return ENV_OK;
+}
+
+void env_surrogate_destroy(env_surrogate* s) {
+    if (s) destroy(s);
+}
+
+}  // extern "C"

@@ -73,6 +73,32 @@ class env_batch_stats(ctypes.Structure):
                 ("launches", c_int64), ("captures", c_int64), ("graph_launches", c_int64)]
 
 
+class env_surrogate_spec(ctypes.Structure):
+    _fields_ = [("n_freq", c_int32), ("hidden", c_int32), ("layers", c_int32),
+                ("poly_degree", c_int32), ("radius", c_double), ("B", POINTER(c_double)),
+                ("params", POINTER(ctypes.c_float)), ("poly", POINTER(c_double)),
+                ("sigma", c_double), ("reserved", c_int32 * 4)]
+
+
+class env_train_opts(ctypes.Structure):
+    _fields_ = [("n_train", c_int64), ("epochs", c_int32), ("batch", c_int32), ("lr", c_double),
+                ("lr_final", c_double), ("seed", ctypes.c_uint64), ("gate_grid", c_int32),
+                ("gate_samples", c_int32), ("gate_tol", c_double), ("n_fit", c_int64),
+                ("poly_degree", c_int32), ("reserved", c_int32 * 3)]
+
+
+class env_surrogate_info(ctypes.Structure):
+    _fields_ = [("n_params", c_int64), ("n_freq", c_int32), ("hidden", c_int32),
+                ("layers", c_int32), ("poly_degree", c_int32), ("radius", c_double),
+                ("sigma", c_double), ("baseline_rms", c_double), ("train_steps", c_int64),
+                ("final_loss", c_double), ("epoch_loss", c_double * 64),
+                ("teacher_seconds", c_double), ("train_seconds", c_double),
+                ("gate_seconds", c_double), ("gate_grid", c_int32), ("reserved0", c_int32),
+                ("gate_voxels_in_ball", c_int64), ("gate_voxels_pass", c_int64),
+                ("gate_pass_volume_fraction", c_double), ("gate_max_err_passed", c_double),
+                ("gate_tol", c_double), ("last_eval_n", c_int64), ("last_eval_fallback", c_int64)]
+
+
 class EnvError(RuntimeError):
     def __init__(self, status: int, what: str = ""):
         self.status = status
@@ -122,6 +148,26 @@ def lib():
         L.env_batch_get_stats.restype = c_int32
         L.env_batch_destroy.argtypes = [c_void_p]
         L.env_batch_destroy.restype = None
+        L.env_train_opts_default.argtypes = [POINTER(env_train_opts)]
+        L.env_train_opts_default.restype = None
+        L.env_surrogate_create.argtypes = [c_void_p, POINTER(env_surrogate_spec), POINTER(c_void_p)]
+        L.env_surrogate_create.restype = c_int32
+        L.env_surrogate_train.argtypes = [c_void_p, c_void_p, POINTER(env_train_opts), c_void_p]
+        L.env_surrogate_train.restype = c_int32
+        L.env_surrogate_predict.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]
+        L.env_surrogate_predict.restype = c_int32
+        L.env_surrogate_eval.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]
+        L.env_surrogate_eval.restype = c_int32
+        L.env_surrogate_loss_grad.argtypes = [c_void_p, c_void_p, c_void_p, c_int64,
+                                              POINTER(ctypes.c_float), POINTER(c_double), c_void_p]
+        L.env_surrogate_loss_grad.restype = c_int32
+        L.env_surrogate_get_params.argtypes = [c_void_p, POINTER(ctypes.c_float), POINTER(c_double),
+                                               POINTER(c_double)]
+        L.env_surrogate_get_params.restype = c_int32
+        L.env_surrogate_get_info.argtypes = [c_void_p, POINTER(env_surrogate_info)]
+        L.env_surrogate_get_info.restype = c_int32
+        L.env_surrogate_destroy.argtypes = [c_void_p]
+        L.env_surrogate_destroy.restype = None
         _lib = L
     return _lib
 
@@ -387,3 +433,139 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+N_SURROGATE_PARAMS = 4 * (128 * 128 + 128) + 128 + 1
+
+
+def _check(st, what):
+    if st != ENV_OK:
+        raise EnvError(st, what)
+
+
+class Surrogate:
+    """Coordinate-MLP surrogate with a validated voxel gate (env_surrogate_*).
+
+    fallback: Environment evaluated for gated-out points; B: (64, 3)
+    frequencies; params: initial parameter vector (66,177 float32)."""
+
+    def __init__(self, fallback: Environment, B, params, radius: float = 6.0,
+                 poly_degree: int = 0, poly=None, sigma: float = 1.0):
+        self.fallback = fallback
+        self._B = np.ascontiguousarray(B, dtype=np.float64).reshape(64, 3)
+        self._p = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+        if self._p.shape[0] != N_SURROGATE_PARAMS:
+            raise ValueError("params must hold 66,177 values")
+        spec = env_surrogate_spec()
+        spec.n_freq, spec.hidden, spec.layers, spec.poly_degree = 64, 128, 4, int(poly_degree)
+        spec.radius = float(radius)
+        spec.B = _dp(self._B)
+        spec.params = self._p.ctypes.data_as(POINTER(ctypes.c_float))
+        if poly is not None:
+            self._poly = np.ascontiguousarray(poly, dtype=np.float64)
+            spec.poly = _dp(self._poly)
+        spec.sigma = float(sigma)
+        h = c_void_p()
+        _check(lib().env_surrogate_create(c_void_p(fallback.handle), ctypes.byref(spec),
+                                          ctypes.byref(h)), "env_surrogate_create")
+        self.handle = h.value
+        self.radius = radius
+
+    @staticmethod
+    def default_opts(**kw) -> env_train_opts:
+        o = env_train_opts()
+        lib().env_train_opts_default(ctypes.byref(o))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    def train(self, teacher: Environment, stream=None, **kw):
+        import torch
+        o = self.default_opts(**kw)
+        st = (stream or torch.cuda.current_stream()).cuda_stream
+        _check(lib().env_surrogate_train(c_void_p(self.handle), c_void_p(teacher.handle),
+                                         ctypes.byref(o), c_void_p(st)), "env_surrogate_train")
+
+    def predict(self, points, stream=None):
+        import torch
+        points = points.contiguous()
+        out = torch.empty(points.shape[0], dtype=torch.float64, device=points.device)
+        st = (stream or torch.cuda.current_stream()).cuda_stream
+        _check(lib().env_surrogate_predict(c_void_p(self.handle), c_void_p(points.data_ptr()),
+                                           points.shape[0], c_void_p(out.data_ptr()), c_void_p(st)),
+               "env_surrogate_predict")
+        return out
+
+    def eval(self, points, stream=None):
+        """(V, used_fallback) at (n,3) float64 device points."""
+        import torch
+        points = points.contiguous()
+        n = points.shape[0]
+        out = torch.empty(n, dtype=torch.float64, device=points.device)
+        fb = torch.empty(n, dtype=torch.uint8, device=points.device)
+        st = (stream or torch.cuda.current_stream()).cuda_stream
+        _check(lib().env_surrogate_eval(c_void_p(self.handle), c_void_p(points.data_ptr()), n,
+                                        c_void_p(out.data_ptr()), c_void_p(fb.data_ptr()),
+                                        c_void_p(st)), "env_surrogate_eval")
+        return out, fb
+
+    def loss_grad(self, points, targets, stream=None):
+        import torch
+        points = points.contiguous()
+        targets = targets.to(torch.float32).contiguous()
+        g = np.zeros(N_SURROGATE_PARAMS, dtype=np.float32)
+        loss = c_double()
+        st = (stream or torch.cuda.current_stream()).cuda_stream
+        _check(lib().env_surrogate_loss_grad(c_void_p(self.handle), c_void_p(points.data_ptr()),
+                                             c_void_p(targets.data_ptr()), points.shape[0],
+                                             g.ctypes.data_as(POINTER(ctypes.c_float)),
+                                             ctypes.byref(loss), c_void_p(st)),
+               "env_surrogate_loss_grad")
+        return loss.value, g
+
+    def params(self):
+        p = np.zeros(N_SURROGATE_PARAMS, dtype=np.float32)
+        poly = np.zeros(165)
+        sig = c_double()
+        _check(lib().env_surrogate_get_params(c_void_p(self.handle),
+                                              p.ctypes.data_as(POINTER(ctypes.c_float)),
+                                              _dp(poly), ctypes.byref(sig)),
+               "env_surrogate_get_params")
+        return p, poly, sig.value
+
+    def info(self) -> dict:
+        i = env_surrogate_info()
+        _check(lib().env_surrogate_get_info(c_void_p(self.handle), ctypes.byref(i)),
+               "env_surrogate_get_info")
+        d = {f: getattr(i, f) for f, _ in env_surrogate_info._fields_}
+        d["epoch_loss"] = list(i.epoch_loss)
+        return d
+
+    def close(self):
+        if self.handle:
+            lib().env_surrogate_destroy(c_void_p(self.handle))
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def init_params(seed: int = 0, scale: float = 1.0) -> np.ndarray:
+    """He-style initial parameters (numpy Generator(PCG64(seed)))."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for _ in range(4):
+        parts.append(rng.standard_normal(128 * 128) * scale * np.sqrt(2.0 / 128))
+        parts.append(np.zeros(128))
+    parts.append(rng.standard_normal(128) * np.sqrt(1.0 / 128))
+    parts.append(np.zeros(1))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def fourier_matrix(seed: int = 0, sigma: float = 1.0) -> np.ndarray:
+    """64 frequency vectors b ~ N(0, sigma^2 I) (1/bohr)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.standard_normal((64, 3)) * sigma
