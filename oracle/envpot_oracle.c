@@ -479,31 +479,53 @@ int oracle_density_overlap_rows(int K, const double* xyz, int S, const int32_t* 
     prepared pr;
     prepare(&e, &pr);
     for (int mu = 0; mu < nbf; ++mu) out[mu] = 0.0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
     for (int k = 0; k < pr.n; ++k) {
+        double Sx[(ORACLE_LMAX + 1) * (ORACLE_LMAX + 1)], Sy[(ORACLE_LMAX + 1) * (ORACLE_LMAX + 1)],
+            Sz[(ORACLE_LMAX + 1) * (ORACLE_LMAX + 1)];
         const shellpair* q = &pr.sp[k];
         int I = q->I, J = q->J, nI = ncart(l[I]), nJ = ncart(l[J]);
         const double* A = xyz + 3 * atom[I];
         const double* B = xyz + 3 * atom[J];
+        double* acc = (double*)calloc((size_t)nI * nJ, sizeof(double));
+        int eI[ORACLE_NMAXCART][3], eJ[ORACLE_NMAXCART][3];
+        for (int ci = 0; ci < nI; ++ci) cart_exps(l[I], ci, eI[ci]);
+        for (int cj = 0; cj < nJ; ++cj) cart_exps(l[J], cj, eJ[cj]);
+        for (int pa = 0; pa < nprim[I]; ++pa)
+            for (int pb = 0; pb < nprim[J]; ++pb) {
+                double a = ex[poff[I] + pa], b = ex[poff[J] + pb];
+                double Na[ORACLE_NMAXCART], Nb[ORACLE_NMAXCART];
+                for (int ci = 0; ci < nI; ++ci) Na[ci] = oracle_prim_norm(a, eI[ci][0], eI[ci][1], eI[ci][2]);
+                for (int cj = 0; cj < nJ; ++cj) Nb[cj] = oracle_prim_norm(b, eJ[cj][0], eJ[cj][1], eJ[cj][2]);
+                /* the 1-D overlaps of this primitive pair, for every exponent pair */
+                for (int i = 0; i <= l[I]; ++i)
+                    for (int j = 0; j <= l[J]; ++j) {
+                        Sx[i * (ORACLE_LMAX + 1) + j] = oracle_overlap1d(i, j, a, b, A[0], B[0]);
+                        Sy[i * (ORACLE_LMAX + 1) + j] = oracle_overlap1d(i, j, a, b, A[1], B[1]);
+                        Sz[i * (ORACLE_LMAX + 1) + j] = oracle_overlap1d(i, j, a, b, A[2], B[2]);
+                    }
+                for (int ci = 0; ci < nI; ++ci)
+                    for (int cj = 0; cj < nJ; ++cj) {
+                        if (q->Pblk[ci * nJ + cj] == 0.0) continue;
+                        const int* ei = eI[ci];
+                        const int* ej = eJ[cj];
+                        acc[ci * nJ + cj] += co[poff[I] + pa] * co[poff[J] + pb] * Na[ci] * Nb[cj] *
+                                             Sx[ei[0] * (ORACLE_LMAX + 1) + ej[0]] *
+                                             Sy[ei[1] * (ORACLE_LMAX + 1) + ej[1]] *
+                                             Sz[ei[2] * (ORACLE_LMAX + 1) + ej[2]];
+                    }
+            }
         for (int ci = 0; ci < nI; ++ci)
             for (int cj = 0; cj < nJ; ++cj) {
-                double Pmn = q->Pblk[ci * nJ + cj];
-                if (Pmn == 0.0) continue;
-                int ei[3], ej[3];
-                cart_exps(l[I], ci, ei);
-                cart_exps(l[J], cj, ej);
-                double s = 0.0;
-                for (int pa = 0; pa < nprim[I]; ++pa)
-                    for (int pb = 0; pb < nprim[J]; ++pb) {
-                        double a = ex[poff[I] + pa], b = ex[poff[J] + pb];
-                        s += co[poff[I] + pa] * co[poff[J] + pb] *
-                             oracle_prim_norm(a, ei[0], ei[1], ei[2]) *
-                             oracle_prim_norm(b, ej[0], ej[1], ej[2]) *
-                             oracle_overlap1d(ei[0], ej[0], a, b, A[0], B[0]) *
-                             oracle_overlap1d(ei[1], ej[1], a, b, A[1], B[1]) *
-                             oracle_overlap1d(ei[2], ej[2], a, b, A[2], B[2]);
-                    }
-                out[pr.bf0[I] + ci] += Pmn * s; /* Pblk already holds the scales */
+                const double v = q->Pblk[ci * nJ + cj] * acc[ci * nJ + cj];  /* Pblk holds the scales */
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+                out[pr.bf0[I] + ci] += v;
             }
+        free(acc);
     }
     release(&e, &pr);
     return 0;

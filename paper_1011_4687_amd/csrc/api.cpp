@@ -320,7 +320,11 @@ env_status env_potential_export_pairs(const env_potential* h, int64_t cap, int32
     if (group) std::copy(pl.group.begin(), pl.group.end(), group);
     if (center) std::copy(pl.center.begin(), pl.center.end(), center);
     if (p) std::copy(pl.p.begin(), pl.p.end(), p);
-    if (D) std::copy(pl.D.begin(), pl.D.end(), D);
+    if (D) {
+        std::fill(D, D + 35 * n, 0.0);
+        for (int64_t k = 0; k < n; ++k)
+            std::copy(pl.D.begin() + pl.d_off[k], pl.D.begin() + pl.d_off[k + 1], D + 35 * k);
+    }
     return ENV_OK;
 }
 

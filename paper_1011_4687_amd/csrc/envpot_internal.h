@@ -115,7 +115,8 @@ struct PairList {
     std::vector<int32_t> L, group;
     std::vector<double> center;   // 3 per pair
     std::vector<double> p;
-    std::vector<double> D;        // 35 per pair (unused tail zero)
+    std::vector<double> D;        // ncomp(L) per pair, pair k starts at d_off[k]
+    std::vector<int64_t> d_off;   // n_pairs + 1
     std::vector<double> nuc;      // 4 per nucleus, grouped
     std::vector<int32_t> group_nuc_begin, group_nuc_end;  // per group
     std::vector<int64_t> group_pair_begin;                // per group (+1)

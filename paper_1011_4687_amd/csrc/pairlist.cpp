@@ -11,11 +11,15 @@
 // count and the far field of the pair is sum_tuv D_tuv d^t d^u d^v (1/R).
 #include <algorithm>
 #include <array>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <atomic>
 #include <cmath>
 #include <cstring>
 #include <thread>
 #include <unordered_map>
+#include <xmmintrin.h>
 
 #include "envpot_internal.h"
 
@@ -106,11 +110,36 @@ struct GroupOut {
 
 bool finite(double x) { return std::isfinite(x); }
 
+// hermite_index as a lookup table for the hot loops.
+struct HIndex {
+    int8_t v[kLMax + 1][kLMax + 1][kLMax + 1][kLMax + 1];
+    HIndex() {
+        for (int L = 0; L <= kLMax; ++L)
+            for (int t = 0; t <= kLMax; ++t)
+                for (int u = 0; u <= kLMax; ++u)
+                    for (int w = 0; w <= kLMax; ++w) v[L][t][u][w] = int8_t(hermite_index(L, t, u, w));
+    }
+};
+const HIndex& hidx() {
+    static const HIndex h;
+    return h;
+}
+
 }  // namespace
 
 env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
                            const env_shell* shells, int32_t n_shells,
                            const env_density* P, const env_options& opt, PairList& out) {
+    const char* tenv = std::getenv("ENVPOT_TIMING");
+    const bool timing = tenv && *tenv && *tenv != '0';
+    auto tlast = std::chrono::steady_clock::now();
+    auto lap = [&](const char* what) {
+        if (!timing) return;
+        const auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[envpot build] %-22s %8.3f s\n", what,
+                     std::chrono::duration<double>(now - tlast).count());
+        tlast = now;
+    };
     out = PairList();
     if (n_nuclei < 0 || n_shells < 0 || !P) return ENV_E_ARG;
     if ((n_nuclei > 0 && !nuclei) || (n_shells > 0 && !shells)) return ENV_E_ARG;
@@ -166,6 +195,28 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
                                                    shells[s].coefs, e);
         }
 
+    // per shell: coefficient x primitive normalisation of every component, and
+    // the s-type normalisation (2a/pi)^{3/4} used by the screening bound
+    std::vector<int64_t> noff(n_shells + 1, 0);
+    for (int s = 0; s < n_shells; ++s) noff[s + 1] = noff[s] + int64_t(shells[s].nprim) * ncart(shells[s].l);
+    std::vector<double> cnorm(noff[n_shells]);
+    std::vector<int64_t> poff(n_shells + 1, 0);
+    for (int s = 0; s < n_shells; ++s) poff[s + 1] = poff[s] + shells[s].nprim;
+    std::vector<double> n0(poff[n_shells]);
+    for (int s = 0; s < n_shells; ++s) {
+        const int nc = ncart(shells[s].l);
+        for (int k = 0; k < shells[s].nprim; ++k) {
+            const double a = shells[s].exponents[k];
+            n0[poff[s] + k] = std::pow(2.0 * a / kPi, 0.75);
+            for (int c = 0; c < nc; ++c) {
+                int e[3];
+                cart(shells[s].l, c, e);
+                cnorm[noff[s] + int64_t(k) * nc + c] = shells[s].coefs[k] * prim_norm(a, e);
+            }
+        }
+    }
+
+    lap("validate, norms");
     // density blocks of ordered shell pairs
     std::unordered_map<uint64_t, int> bidx;
     std::vector<std::array<double, 36>> raw;
@@ -204,6 +255,7 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
             }
         }
     }
+    lap("density blocks");
     // symmetry: block (I,J) must equal the transpose of block (J,I)
     auto blk = [&](int I, int J) -> const double* {
         auto it = bidx.find((uint64_t(uint32_t(I)) << 32) | uint32_t(J));
@@ -256,8 +308,10 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
         for (int k : order) gblocks[block_group[k]].push_back(k);
     }
 
+    lap("symmetry, grouping");
     std::vector<GroupOut> gout(n_groups);
     const bool neutralize = (opt.flags & ENV_NEUTRALIZE) != 0;
+    const HIndex& HX = hidx();
     auto work = [&](int g) {
         GroupOut& go = gout[g];
         Ecoef Ex, Ey, Ez;
@@ -281,45 +335,46 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
                     const double ca = SI.coefs[ia], cb = SJ.coefs[ib];
                     const double p = a + b, mu = a * b / p;
                     const double w = (B.I == B.J && ia != ib) ? 2.0 : 1.0;
+                    const double pp = kPi / p, pp32 = pp * std::sqrt(pp);
+                    const double* na_c = &cnorm[noff[B.I] + int64_t(ia) * nI];  // c_a N_a per component
+                    const double* nb_c = &cnorm[noff[B.J] + int64_t(ib) * nJ];
                     ++go.n_unscreened;
-                    const double bound = std::fabs(ca * cb) * std::pow(4.0 * a * b / (kPi * kPi), 0.75) *
-                                         std::pow(kPi / p, 1.5) * std::exp(-mu * rab2);
+                    const double bound = std::fabs(ca * cb) * n0[poff[B.I] + ia] * n0[poff[B.J] + ib] * pp32 *
+                                         std::exp(-mu * rab2);
                     const bool drop = screen && bound < thr;
                     if (drop) go.screened_bound += w * B.maxabs * bound;
                     if (drop && !neutralize) continue;
                     hermite_coefs(lI, lJ, a, b, A[0], Bc[0], Ex);
                     hermite_coefs(lI, lJ, a, b, A[1], Bc[1], Ey);
                     hermite_coefs(lI, lJ, a, b, A[2], Bc[2], Ez);
-                    if (drop) {  // only its charge: sum P N N c c E_0 E_0 E_0 (pi/p)^{3/2}
+                    if (drop) {  // only its charge: sum P c N c N E_0 E_0 E_0 (pi/p)^{3/2}
                         double q = 0.0;
                         for (int x = 0; x < nI; ++x)
                             for (int y = 0; y < nJ; ++y)
-                                q += B.w[x][y] * prim_norm(a, eI[x]) * prim_norm(b, eJ[y]) *
-                                     Ex.v[eI[x][0]][eJ[y][0]][0] * Ey.v[eI[x][1]][eJ[y][1]][0] *
-                                     Ez.v[eI[x][2]][eJ[y][2]][0];
-                        go.dropped_charge += w * ca * cb * q * std::pow(kPi / p, 1.5);
+                                q += B.w[x][y] * na_c[x] * nb_c[y] * Ex.v[eI[x][0]][eJ[y][0]][0] *
+                                     Ey.v[eI[x][1]][eJ[y][1]][0] * Ez.v[eI[x][2]][eJ[y][2]][0];
+                        go.dropped_charge += w * q * pp32;
                         continue;
                     }
                     for (int k = 0; k < nc; ++k) D[k] = 0.0;
                     for (int x = 0; x < nI; ++x) {
-                        const double na = prim_norm(a, eI[x]);
                         for (int y = 0; y < nJ; ++y) {
                             const double pw = B.w[x][y];
                             if (pw == 0.0) continue;
-                            const double f = w * pw * ca * cb * na * prim_norm(b, eJ[y]);
+                            const double f = w * pw * na_c[x] * nb_c[y];
                             const int ix = eI[x][0], jx = eJ[y][0], iy = eI[x][1], jy = eJ[y][1],
                                       iz = eI[x][2], jz = eJ[y][2];
                             for (int t = 0; t <= ix + jx; ++t) {
                                 const double ft = f * Ex.v[ix][jx][t];
                                 for (int u = 0; u <= iy + jy; ++u) {
                                     const double fu = ft * Ey.v[iy][jy][u];
-                                    for (int v = 0; v <= iz + jz; ++v)
-                                        D[hermite_index(L, t, u, v)] += fu * Ez.v[iz][jz][v];
+                                    const int8_t* hx = HX.v[L][t][u];
+                                    for (int v = 0; v <= iz + jz; ++v) D[hx[v]] += fu * Ez.v[iz][jz][v];
                                 }
                             }
                         }
                     }
-                    const double sc = std::pow(kPi / p, 1.5);
+                    const double sc = pp32;
                     Bucket& bu = go.b[L];
                     bu.rec.push_back((a * A[0] + b * Bc[0]) / p);
                     bu.rec.push_back((a * A[1] + b * Bc[1]) / p);
@@ -338,6 +393,9 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
         std::atomic<int> next{0};
         for (unsigned t = 0; t < nt; ++t)
             th.emplace_back([&]() {
+                // flush denormals to zero: products of vanishing Gaussian overlaps
+                // (exp(-mu R^2) ~ 1e-300) otherwise take the slow denormal path
+                _mm_setcsr(_mm_getcsr() | 0x8040);
                 for (;;) {
                     const int g = next.fetch_add(1);
                     if (g >= n_groups) break;
@@ -347,6 +405,7 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
         for (auto& t : th) t.join();
     }
 
+    lap("primitive pairs");
     // nuclei by group (Z == 0 centres carry basis functions only)
     std::vector<double> zg(n_groups, 0.0);
     out.group_nuc_begin.assign(n_groups, 0);
@@ -368,6 +427,7 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
         out.group_nuc_begin[n_frag_groups] = out.group_nuc_end[n_frag_groups] = int(out.nuc.size() / 4);
     }
 
+    lap("nuclei");
     // neutralise: scale the Hermite densities of each group so that its
     // electron count tr(P_f S_f) (screened-out pairs included) equals its
     // nuclear charge
@@ -390,29 +450,68 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
         }
     }
 
-    // final order: group, then L
+    lap("neutralise");
+    // final order: group, then L; every output sized once, groups filled in parallel
     out.group_pair_begin.assign(n_groups + 1, 0);
+    std::vector<int64_t> gd(n_groups + 1, 0);  // first D word of each group
     for (int g = 0; g < n_groups; ++g) {
-        out.group_pair_begin[g] = int64_t(out.L.size());
+        int64_t np = 0, nd = 0;
+        for (int L = 0; L <= kLMax; ++L) {
+            np += gout[g].b[L].n;
+            nd += gout[g].b[L].n * kNComp[L];
+        }
+        out.group_pair_begin[g + 1] = out.group_pair_begin[g] + np;
+        gd[g + 1] = gd[g] + nd;
         out.n_unscreened += gout[g].n_unscreened;
         out.screened_bound += gout[g].screened_bound;
-        for (int L = 0; L <= kLMax; ++L) {
-            const Bucket& bu = gout[g].b[L];
-            const int rw = 4 + kNComp[L];
-            for (int64_t k = 0; k < bu.n; ++k) {
-                const double* r = &bu.rec[k * rw];
-                out.L.push_back(L);
-                out.group.push_back(g);
-                out.center.insert(out.center.end(), r, r + 3);
-                out.p.push_back(r[3]);
-                const size_t d0 = out.D.size();
-                out.D.resize(d0 + 35, 0.0);
-                for (int c = 0; c < kNComp[L]; ++c) out.D[d0 + c] = r[4 + c];
-                out.electrons += r[4];
-            }
-        }
     }
-    out.group_pair_begin[n_groups] = int64_t(out.L.size());
+    const int64_t npairs = out.group_pair_begin[n_groups];
+    lap("count");
+    out.L.resize(npairs);
+    out.group.resize(npairs);
+    out.center.resize(3 * size_t(npairs));
+    out.p.resize(npairs);
+    out.d_off.resize(npairs + 1);
+    out.D.resize(gd[n_groups]);
+    out.d_off[npairs] = gd[n_groups];
+    std::vector<double> qg(n_groups, 0.0);
+    lap("allocate");
+    {
+        std::atomic<int> next{0};
+        std::vector<std::thread> th;
+        const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        for (unsigned t = 0; t < nt; ++t)
+            th.emplace_back([&]() {
+                for (;;) {
+                    const int g = next.fetch_add(1);
+                    if (g >= n_groups) break;
+                    int64_t k = out.group_pair_begin[g], d = gd[g];
+                    double q = 0.0;
+                    for (int L = 0; L <= kLMax; ++L) {
+                        Bucket& bu = gout[g].b[L];
+                        const int rw = 4 + kNComp[L];
+                        for (int64_t j = 0; j < bu.n; ++j, ++k) {
+                            const double* r = &bu.rec[j * rw];
+                            out.L[k] = L;
+                            out.group[k] = g;
+                            out.center[3 * k] = r[0];
+                            out.center[3 * k + 1] = r[1];
+                            out.center[3 * k + 2] = r[2];
+                            out.p[k] = r[3];
+                            out.d_off[k] = d;
+                            for (int c = 0; c < kNComp[L]; ++c) out.D[d + c] = r[4 + c];
+                            d += kNComp[L];
+                            q += r[4];
+                        }
+                        std::vector<double>().swap(bu.rec);
+                    }
+                    qg[g] = q;
+                }
+            });
+        for (auto& t : th) t.join();
+    }
+    for (int g = 0; g < n_groups; ++g) out.electrons += qg[g];
+    lap("order");
     return ENV_OK;
 }
 
@@ -553,18 +652,19 @@ const Poly& derivative_poly(int t, int u, int v) {
 }  // namespace
 
 void far_coefs(int L, const double* D, double* h) {
+    const HIndex& HX = hidx();
     for (int k = 0; k < kNComp[L]; ++k) h[k] = 0.0;
     for (int t = 0; t <= L; ++t)
         for (int u = 0; u <= L - t; ++u)
             for (int v = 0; v <= L - t - u; ++v) {
-                const double d = D[hermite_index(L, t, u, v)];
+                const double d = D[HX.v[L][t][u][v]];
                 if (d == 0.0) continue;
                 const Poly& P = derivative_poly(t, u, v);
                 const int k = t + u + v;
                 for (int a = 0; a <= k; ++a)
                     for (int b = 0; b <= k - a; ++b) {
                         const int c = k - a - b;
-                        h[hermite_index(L, a, b, c)] += d * P.c[a][b][c];
+                        h[HX.v[L][a][b][c]] += d * P.c[a][b][c];
                     }
             }
 }
@@ -578,7 +678,7 @@ void pack_records(const PairList& pl, bool fp64, const BoysParams& bp,
         const int L = pl.L[k], nc = kNComp[L];
         const double p = pl.p[k];
         const double c1 = 2.0 * std::sqrt(p / kPi);
-        const double* D = &pl.D[35 * k];
+        const double* D = &pl.D[pl.d_off[k]];
         far_coefs(L, D, h);
         const size_t o = rec.size();
         if (fp64) {

@@ -1,0 +1,82 @@
+"""The large and batched workloads at their full sizes, in the launch shapes
+the library picks for them; the oracle checks sampled points one by one."""
+import time
+
+import numpy as np
+import pytest
+
+from common import sample_indices
+from paper_1011_4687_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.timeout(900)
+def test_large_full_size():
+    """5000 atoms (500 neutral fragments, ~9e6 screened pairs), 1,048,576
+    points: FP32C within 1e-5 Ha of the unscreened oracle and FP64 within
+    1e-12 A of the screened oracle on 24 sampled points."""
+    import torch
+    from oracle import oracle as O
+    from paper_1011_4687_amd.envpot import Environment
+    print("[fullsize] large: building", flush=True)
+    env, pts = synth.workload("large")
+    sc = O.neutral_scales(env)
+    P = env.density_csr(sc)
+    shells = [(s.atom, s.l, s.exponents, s.coefs) for s in env.shells]
+    x = torch.from_numpy(pts).cuda()
+    idx = sample_indices(len(pts), 24)
+    res = {}
+    for prec in ("fp32c", "fp64"):
+        t0 = time.time()
+        E = Environment(env.xyz, env.Z, env.fragment, shells, P, precision=prec)
+        t1 = time.time()
+        V = E.eval(x)
+        torch.cuda.synchronize()
+        print(f"[fullsize] large {prec}: create {t1 - t0:.1f}s eval {time.time() - t1:.1f}s "
+              f"pairs {E.info()['n_pairs']}", flush=True)
+        res[prec] = V.cpu().numpy()
+        E.close()
+    Vs, _, _, A = O.potential(env, pts[idx], P=P, screen=True)
+    Vf, _, _, _ = O.potential(env, pts[idx], P=P, screen=False)
+    e32 = np.abs(res["fp32c"][idx] - Vf)
+    e64 = np.abs(res["fp64"][idx] - Vs)
+    print(f"[fullsize] large: fp32c max {e32.max():.3e}  fp64 max rel {(e64 / A).max():.3e}", flush=True)
+    assert e32.max() <= 1e-5
+    assert np.all(e64 <= 1e-12 * A)
+
+
+@pytest.mark.timeout(900)
+def test_batched_full_size():
+    """64 uneven instances (50..2000 atoms, 1k..200k points) in one persistent
+    FP32C launch; 4 sampled points per instance against the oracle."""
+    import torch
+    from oracle import oracle as O
+    from paper_1011_4687_amd.envpot import Batch, Environment
+    print("[fullsize] batched: building", flush=True)
+    inst = synth.batched_instances(64)
+    hs, xs = [], []
+    t0 = time.time()
+    for env, pts in inst:
+        shells = [(s.atom, s.l, s.exponents, s.coefs) for s in env.shells]
+        # the library's neutralisation (tr(P_f S_f) = Z_f, equal to the oracle's
+        # scaling to 1e-10, tested on the CPU); the oracle scales its own P below
+        hs.append(Environment(env.xyz, env.Z, env.fragment, shells, env.density_csr(),
+                              precision="fp32c", neutralize=True))
+        xs.append(torch.from_numpy(pts).cuda())
+    print(f"[fullsize] batched: {len(hs)} handles in {time.time() - t0:.1f}s, "
+          f"{sum(len(p) for _, p in inst)} points", flush=True)
+    B = Batch(hs)
+    outs = B.eval(xs)
+    torch.cuda.synchronize()
+    sizes = [env.n_nuclei for env, _ in inst]
+    check = sorted(set([int(np.argmin(sizes)), int(np.argmax(sizes))] + list(range(0, 64, 7))))
+    worst = 0.0
+    for k in check:
+        env, pts = inst[k]
+        idx = sample_indices(len(pts), 4, seed=k)
+        Vf, _, _, _ = O.potential(env, pts[idx], scale=O.neutral_scales(env), screen=False)
+        worst = max(worst, float(np.abs(outs[k].cpu().numpy()[idx] - Vf).max()))
+    print(f"[fullsize] batched: max err {worst:.3e}, stats {B.stats()}", flush=True)
+    assert worst <= 1e-5
+    B.close()
