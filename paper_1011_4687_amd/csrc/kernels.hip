@@ -35,6 +35,25 @@ namespace {
 
 constexpr int kTile = 8;  // pairs per FP32 partial sum
 
+// Address spaces.  The pair records, segments, nuclei and Boys table are
+// never written while a kernel runs, so they are read through the constant
+// address space: wave-uniform loads through it become scalar loads even in
+// the persistent kernel, whose work-queue atomics and output stores would
+// otherwise count as possible clobbers.  Points are read through the global
+// address space (per-lane vector loads).
+#define GLB __attribute__((address_space(4)))
+#define PTS __attribute__((address_space(1)))
+
+template <typename T>
+__device__ __forceinline__ const GLB T* glb(const T* p) {
+    return (const GLB T*)p;
+}
+
+template <typename T>
+__device__ __forceinline__ const PTS T* gpts(const T* p) {
+    return (const PTS T*)p;
+}
+
 template <int L, typename T>
 __device__ __forceinline__ T hermite_dot(const T* G, T X, T Y, T Z, const T* __restrict__ D) {
     if constexpr (L == 0) return hermite_dot_L0<T>(G, X, Y, Z, D);
@@ -71,10 +90,15 @@ struct Head {
     T h[kNComp[L]];
 };
 
+// Prefetch the next head only while two heads fit comfortably in SGPRs
+// (spilled SGPRs cost VALU writelane/readlane instructions).
+template <int L, typename T>
+constexpr bool kPipelined = (6 + (1 + kNComp[L]) * int(sizeof(T) / 4)) <= 20;
+
 template <int L>
-__device__ __forceinline__ void load_head32(const uint32_t* __restrict__ r, Head<L, float>& o) {
-    const double* rd = reinterpret_cast<const double*>(r);
-    const float* rf = reinterpret_cast<const float*>(r + 6);
+__device__ __forceinline__ void load_head32(const GLB uint32_t* __restrict__ r, Head<L, float>& o) {
+    const GLB double* rd = reinterpret_cast<const GLB double*>(r);
+    const GLB float* rf = reinterpret_cast<const GLB float*>(r + 6);
     o.px = rd[0];
     o.py = rd[1];
     o.pz = rd[2];
@@ -84,8 +108,8 @@ __device__ __forceinline__ void load_head32(const uint32_t* __restrict__ r, Head
 }
 
 template <int L>
-__device__ __forceinline__ void load_head64(const uint32_t* __restrict__ r, Head<L, double>& o) {
-    const double* rd = reinterpret_cast<const double*>(r);
+__device__ __forceinline__ void load_head64(const GLB uint32_t* __restrict__ r, Head<L, double>& o) {
+    const GLB double* rd = reinterpret_cast<const GLB double*>(r);
     o.px = rd[0];
     o.py = rd[1];
     o.pz = rd[2];
@@ -97,11 +121,13 @@ __device__ __forceinline__ void load_head64(const uint32_t* __restrict__ r, Head
 // Near field of one point (FP32): Boys values from the LDS table by a 6-term
 // Taylor step, then the Hermite recursion contracted with D.
 template <int L>
-__device__ __forceinline__ float near_f32(const uint32_t* __restrict__ r, float X, float Y, float Z,
+__device__ __forceinline__ float near_f32(const GLB uint32_t* __restrict__ r, float X, float Y, float Z,
                                           float r2, const float* tab) {
-    const float* rf = reinterpret_cast<const float*>(r + 6);
+    const GLB float* rf = reinterpret_cast<const GLB float*>(r + 6);
     const float p = rf[1], c1 = rf[2];
-    const float* D = rf + 3 + kNComp[L];
+    float D[kNComp[L]];
+#pragma unroll
+    for (int c = 0; c < kNComp[L]; ++c) D[c] = rf[3 + kNComp[L] + c];
     const float T = p * r2;
     const int kk = (int)__builtin_fmaf(T, (float)kBoysGridInv, 0.5f);
     const float d = __builtin_fmaf((float)kk, -1.0f / kBoysGridInv, T);
@@ -124,15 +150,17 @@ __device__ __forceinline__ float near_f32(const uint32_t* __restrict__ r, float 
 }
 
 template <int L>
-__device__ __forceinline__ double near_f64(const uint32_t* __restrict__ r, double X, double Y,
-                                           double Z, double r2, const double* __restrict__ tab) {
-    const double* rd = reinterpret_cast<const double*>(r);
+__device__ __forceinline__ double near_f64(const GLB uint32_t* __restrict__ r, double X, double Y,
+                                           double Z, double r2, const GLB double* __restrict__ tab) {
+    const GLB double* rd = reinterpret_cast<const GLB double*>(r);
     const double p = rd[4], c1 = rd[5];
-    const double* D = rd + kRec64Head + kNComp[L];
+    double D[kNComp[L]];
+#pragma unroll
+    for (int c = 0; c < kNComp[L]; ++c) D[c] = rd[kRec64Head + kNComp[L] + c];
     const double T = p * r2;
     const int kk = (int)__builtin_fma(T, (double)kBoysGridInv, 0.5);
     const double d = __builtin_fma((double)kk, -1.0 / kBoysGridInv, T);
-    const double* f = tab + kk * kBoysRowF64;
+    const GLB double* f = tab + kk * kBoysRowF64;
     double dj[kBoysTaylorF64];
 #pragma unroll
     for (int j = 1; j < kBoysTaylorF64; ++j) dj[j] = d * (1.0 / j);
@@ -152,7 +180,7 @@ __device__ __forceinline__ double near_f64(const uint32_t* __restrict__ r, doubl
 
 // FP32C pairs of one L.  Record: P (3 doubles), r2far, p, c1, h[nc], D[nc].
 template <int L, int NP>
-__device__ __forceinline__ void pairs_f32(const uint32_t* __restrict__ rec, int npairs,
+__device__ __forceinline__ void pairs_f32(const GLB uint32_t* __restrict__ rec, int npairs,
                                           const double* cx, const double* cy, const double* cz,
                                           const float* tab, double* ele) {
     constexpr int RW = rec32_words(L);
@@ -161,11 +189,12 @@ __device__ __forceinline__ void pairs_f32(const uint32_t* __restrict__ rec, int 
 #pragma unroll
     for (int k = 0; k < NP; ++k) tile[k] = 0.0f;
     Head<L, float> cur;
-    load_head32<L>(rec, cur);
+    if constexpr (kPipelined<L, float>) load_head32<L>(rec, cur);
     for (int i = 0; i < npairs; ++i) {
-        const uint32_t* r = rec + (int64_t)i * RW;
+        const GLB uint32_t* r = rec + (int64_t)i * RW;
         Head<L, float> nxt;
-        load_head32<L>(rec + (int64_t)min(i + 1, npairs - 1) * RW, nxt);
+        if constexpr (kPipelined<L, float>) load_head32<L>(rec + (int64_t)min(i + 1, npairs - 1) * RW, nxt);
+        else load_head32<L>(r, cur);
         float X[NP], Y[NP], Z[NP], r2[NP];
         bool nearp = false;
 #pragma unroll
@@ -208,7 +237,7 @@ __device__ __forceinline__ void pairs_f32(const uint32_t* __restrict__ rec, int 
                 tile[k] = 0.0f;
             }
         }
-        cur = nxt;
+        if constexpr (kPipelined<L, float>) cur = nxt;
     }
 #pragma unroll
     for (int k = 0; k < NP; ++k) ele[k] += (double)tile[k];
@@ -216,17 +245,18 @@ __device__ __forceinline__ void pairs_f32(const uint32_t* __restrict__ rec, int 
 
 // FP64 pairs of one L.  Record: P, r2far, p, c1 (doubles), h[nc], D[nc].
 template <int L, int NP>
-__device__ __forceinline__ void pairs_f64(const uint32_t* __restrict__ rec, int npairs,
+__device__ __forceinline__ void pairs_f64(const GLB uint32_t* __restrict__ rec, int npairs,
                                           const double* cx, const double* cy, const double* cz,
-                                          const double* __restrict__ tab, double* ele) {
+                                          const GLB double* __restrict__ tab, double* ele) {
     constexpr int RW = rec64_words(L);
     if (npairs <= 0) return;
     Head<L, double> cur;
-    load_head64<L>(rec, cur);
+    if constexpr (kPipelined<L, double>) load_head64<L>(rec, cur);
     for (int i = 0; i < npairs; ++i) {
-        const uint32_t* r = rec + (int64_t)i * RW;
+        const GLB uint32_t* r = rec + (int64_t)i * RW;
         Head<L, double> nxt;
-        load_head64<L>(rec + (int64_t)min(i + 1, npairs - 1) * RW, nxt);
+        if constexpr (kPipelined<L, double>) load_head64<L>(rec + (int64_t)min(i + 1, npairs - 1) * RW, nxt);
+        else load_head64<L>(r, cur);
         double X[NP], Y[NP], Z[NP], r2[NP];
         bool nearp = false;
 #pragma unroll
@@ -259,41 +289,53 @@ __device__ __forceinline__ void pairs_f64(const uint32_t* __restrict__ rec, int 
                 ele[k] += v;
             }
         }
-        cur = nxt;
+        if constexpr (kPipelined<L, double>) cur = nxt;
     }
 }
 
 // One workgroup's share: points of point block `pblock` against the pair
 // range of split `s` (all of it when S == 1).
 template <int NP, bool F64>
-__device__ __forceinline__ void block_work(const EvalArgs& a, int64_t pblock, int s,
-                                           const float* tab32) {
+__device__ __forceinline__ void block_work_impl(const PTS double* __restrict__ pts, int64_t n,
+                                                const GLB Segment* __restrict__ segs,
+                                                const GLB int32_t* __restrict__ split,
+                                                const GLB uint32_t* __restrict__ recs,
+                                                const GLB double* __restrict__ nuc,
+                                                const GLB double* __restrict__ boys64,
+                                                double* __restrict__ out,
+                                                int64_t pblock, int s, const float* tab32) {
     const int64_t base = pblock * (kBlock * NP) + threadIdx.x;
     double cx[NP], cy[NP], cz[NP], acc[NP], vn[NP], ve[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
         const int64_t i = base + (int64_t)k * kBlock;
-        const int64_t ic = i < a.n ? i : a.n - 1;  // ragged tail: recompute the last point
-        cx[k] = a.pts[3 * ic];
-        cy[k] = a.pts[3 * ic + 1];
-        cz[k] = a.pts[3 * ic + 2];
+        const int64_t ic = i < n ? i : n - 1;  // ragged tail: recompute the last point
+        cx[k] = pts[3 * ic];
+        cy[k] = pts[3 * ic + 1];
+        cz[k] = pts[3 * ic + 2];
         acc[k] = vn[k] = ve[k] = 0.0;
     }
-    const int sb = a.split[s], se = a.split[s + 1];
+    const int sb = split[s], se = split[s + 1];
     for (int g = sb; g < se; ++g) {
-        const Segment sg = a.segs[g];
+        Segment sg;
+        sg.L = segs[g].L;
+        sg.n_pairs = segs[g].n_pairs;
+        sg.rec_off = segs[g].rec_off;
+        sg.nuc_begin = segs[g].nuc_begin;
+        sg.nuc_end = segs[g].nuc_end;
+        sg.flags = segs[g].flags;
         for (int q = sg.nuc_begin; q < sg.nuc_end; ++q) {
-            const double qx = a.nuc[4 * q], qy = a.nuc[4 * q + 1], qz = a.nuc[4 * q + 2],
-                         qZ = a.nuc[4 * q + 3];
+            const double qx = nuc[4 * q], qy = nuc[4 * q + 1], qz = nuc[4 * q + 2],
+                         qZ = nuc[4 * q + 3];
 #pragma unroll
             for (int k = 0; k < NP; ++k) {
                 const double dx = cx[k] - qx, dy = cy[k] - qy, dz = cz[k] - qz;
                 vn[k] += qZ * rsqrt(__builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz)));
             }
         }
-        const uint32_t* rec = a.rec + sg.rec_off;
+        const GLB uint32_t* rec = recs + sg.rec_off;
         if constexpr (F64) {
-            const double* tab = static_cast<const double*>(a.boys);
+            const GLB double* tab = boys64;
             switch (sg.L) {
                 case 0: pairs_f64<0, NP>(rec, sg.n_pairs, cx, cy, cz, tab, ve); break;
                 case 1: pairs_f64<1, NP>(rec, sg.n_pairs, cx, cy, cz, tab, ve); break;
@@ -322,8 +364,18 @@ __device__ __forceinline__ void block_work(const EvalArgs& a, int64_t pblock, in
     for (int k = 0; k < NP; ++k) {
         acc[k] += vn[k] - ve[k];
         const int64_t i = base + (int64_t)k * kBlock;
-        if (i < a.n) a.out[(int64_t)s * a.n + i] = acc[k];
+        if (i < n) out[(int64_t)s * n + i] = acc[k];
     }
+}
+
+// The buffers go in as separate restrict pointers: stores to `out` then
+// provably do not clobber the pair records, which keeps the record loads
+// scalar even when block_work runs in a loop (persistent kernel).
+template <int NP, bool F64>
+__device__ __forceinline__ void block_work(const EvalArgs& a, int64_t pblock, int s,
+                                           const float* tab32) {
+    block_work_impl<NP, F64>(gpts(a.pts), a.n, glb(a.segs), glb(a.split), glb(a.rec), glb(a.nuc),
+                             glb(static_cast<const double*>(a.boys)), a.out, pblock, s, tab32);
 }
 
 template <bool F64>
