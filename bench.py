@@ -71,6 +71,69 @@ def time_path(E, x, out, steps, warmup, torch):
     return wall, float(np.mean(ms))
 
 
+def surrogate_leg(torch, envpot, synth):
+    """Learned surrogate on its own workload: 1000 atoms (box 68.4 bohr), the
+    network covering the 6-bohr region, trained on 2M samples of the exact FP64
+    kernel; evaluated with its gate on 1,000,000 points in the region plus
+    65,536 points in the 6..8-bohr shell (which the gate sends to the exact
+    FP32C kernel), against the exact FP32C kernel on the same points."""
+    env, _ = synth.workload("surrogate", n_points=1)
+    _, infer, outer = synth.surrogate_sets(n_train=1, n_infer=1_000_000, n_out=65536)
+    pts = np.ascontiguousarray(np.concatenate([infer, outer]))
+    x = torch.from_numpy(pts).cuda()
+    fb = envpot.Environment.from_synth(env, precision="fp32c", neutralize=True)
+    te = envpot.Environment.from_synth(env, precision="fp64", neutralize=True)
+    npairs = fb.info()["n_pairs"]
+    S = envpot.Surrogate(fb, envpot.fourier_matrix(1004, 0.25), envpot.init_params(1004), radius=6.0)
+    t0 = time.perf_counter()
+    S.train(te, n_train=2_000_000, epochs=30, batch=8192, lr=2e-3, lr_final=1e-5, poly_degree=8)
+    t_train = time.perf_counter() - t0
+    info = S.info()
+    out = torch.empty(len(pts), dtype=torch.float64, device="cuda")
+    _, ms_exact = time_path(fb, x, out, 3, 1, torch)
+    V_exact = out.cpu().numpy()
+    S.eval(x)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(3):
+        s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s_ev.record()
+        V, used = S.eval(x)
+        e_ev.record()
+        torch.cuda.synchronize()
+        times.append(s_ev.elapsed_time(e_ev))
+    ms_sur = float(np.mean(times))
+    used = used.cpu().numpy().astype(bool)
+    n = len(pts)
+    saved_per_eval = (ms_exact - ms_sur) * 1e-3
+    report = {
+        "workload": f"surrogate: {env.n_nuclei} atoms, {npairs} screened pairs, network radius "
+                    f"6 bohr; {len(infer)} points in the region + {len(outer)} in the 6-8 bohr shell",
+        "n_points": n,
+        "point_pairs_per_s": n * npairs / (ms_sur * 1e-3),
+        "ms_per_step": ms_sur,
+        "exact_fp32c_ms_per_step": ms_exact,
+        "exact_fp32c_point_pairs_per_s": n * npairs / (ms_exact * 1e-3),
+        "speedup_vs_fp32c": ms_exact / ms_sur,
+        "fallback_fraction": float(used.mean()),
+        "gate_pass_volume_fraction": info["gate_pass_volume_fraction"],
+        "gate_max_validation_err": info["gate_max_err_passed"],
+        "baseline_rms": info["baseline_rms"],
+        "teacher_s": info["teacher_seconds"],
+        "train_s": info["train_seconds"],
+        "gate_s": info["gate_seconds"],
+        "train_total_s": t_train,
+        "break_even_evaluations": (t_train / saved_per_eval) if saved_per_eval > 0 else None,
+    }
+    log(f"[bench] surrogate: {ms_sur:.2f} ms vs exact FP32C {ms_exact:.2f} ms, "
+        f"fallback {used.mean():.3f}, train {t_train:.1f}s")
+    V_sur = V.cpu().numpy()
+    S.close()
+    fb.close()
+    te.close()
+    return {"report": report, "env": env, "points": pts, "V_surrogate": V_sur, "V_exact": V_exact}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +144,8 @@ def main():
                     help="points of the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--paths", default="fp32c,fp64")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the learned-surrogate leg (1000-atom surrogate workload)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -124,6 +189,11 @@ def main():
         outs[prec] = out.cpu().numpy()
         log(f"[bench] {prec}: {ms:.3f} ms/step, {paths[prec]['point_pairs_per_s']:.4g} pp/s")
         E.close()
+
+    sur = None
+    if not args.no_surrogate and "fp32c" in args.paths.split(","):
+        sur = surrogate_leg(torch, envpot, synth)
+        paths["surrogate"] = sur["report"]
 
     if args.copy_calibration:
         # plain copy of known size: 256 MiB read + 256 MiB written per launch
@@ -197,6 +267,17 @@ def main():
             err = np.abs(V[idx] - Vo)
             acc[prec] = {"max_abs_err": float(err.max()), "rms_err": float(np.sqrt(np.mean(err ** 2))),
                          "max_rel_to_A": float((err / A).max())}
+        if sur is not None:
+            # the same oracle on a sample of the surrogate workload's points
+            k = min(48, len(sur["points"]))
+            sidx = np.sort(rng.choice(len(sur["points"]), size=k, replace=False))
+            sc2 = O.neutral_scales(sur["env"])
+            Vo2, _, _, _ = O.potential(sur["env"], sur["points"][sidx], scale=sc2, screen=False,
+                                       nthreads=cores)
+            for name, V in (("surrogate", sur["V_surrogate"]), ("surrogate_workload_fp32c", sur["V_exact"])):
+                err = np.abs(V[sidx] - Vo2)
+                acc[name] = {"max_abs_err": float(err.max()),
+                             "rms_err": float(np.sqrt(np.mean(err ** 2))), "n_checked": int(k)}
         result["accuracy_vs_oracle"] = acc
         log(f"[bench] oracle {t_or:.1f}s; accuracy {acc}")
 

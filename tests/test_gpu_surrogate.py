@@ -102,3 +102,51 @@ def test_train_gate_and_fallback():
     assert np.array_equal(V[idx], ref)
     assert S.info()["last_eval_fallback"] == len(idx)
     S.close()
+
+
+@pytest.mark.timeout(900)
+def test_gain_on_surrogate_workload():
+    """What the trained network gains over the exact kernel: on the 1000-atom
+    surrogate workload the gated surrogate is faster than exact FP32C on the
+    same points and stays within 1e-5 Ha of the oracle on sampled points."""
+    import time
+    import torch
+    from oracle import oracle as O
+    from paper_1011_4687_amd.envpot import Environment, Surrogate, fourier_matrix, init_params
+    print("[surrogate] gain", flush=True)
+    env, _ = synth.workload("surrogate", n_points=1)
+    _, infer, outer = synth.surrogate_sets(n_train=1, n_infer=200_000, n_out=8192)
+    pts = np.ascontiguousarray(np.concatenate([infer, outer]))
+    x = torch.from_numpy(pts).cuda()
+    fb = Environment.from_synth(env, precision="fp32c", neutralize=True)
+    te = Environment.from_synth(env, precision="fp64", neutralize=True)
+    S = Surrogate(fb, fourier_matrix(1004, 0.25), init_params(1004), radius=6.0)
+    S.train(te, n_train=1_000_000, epochs=12, batch=8192, lr=2e-3, lr_final=1e-5, poly_degree=8)
+    info = S.info()
+    print({k: info[k] for k in ("baseline_rms", "final_loss", "gate_pass_volume_fraction",
+                                "gate_max_err_passed", "train_seconds")}, flush=True)
+    fb.eval(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    V_exact = fb.eval(x)
+    torch.cuda.synchronize()
+    t_exact = time.perf_counter() - t0
+    S.eval(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    V, used = S.eval(x)
+    torch.cuda.synchronize()
+    t_sur = time.perf_counter() - t0
+    print(f"[surrogate] exact {t_exact * 1e3:.1f} ms, surrogate {t_sur * 1e3:.1f} ms, "
+          f"fallback {used.float().mean().item():.3f}", flush=True)
+    assert t_sur < t_exact
+    idx = np.concatenate([np.linspace(0, len(infer) - 1, 24).astype(int),
+                          len(infer) + np.arange(0, len(outer), len(outer) // 4)])
+    Vo, _, _, _ = O.potential(env, pts[idx], scale=O.neutral_scales(env), screen=False)
+    err = np.abs(V.cpu().numpy()[idx] - Vo)
+    print(f"[surrogate] max err vs oracle {err.max():.3e}", flush=True)
+    assert err.max() <= 1e-5
+    assert used.cpu().numpy()[len(infer):].all()
+    S.close()
+    fb.close()
+    te.close()
