@@ -34,6 +34,7 @@ struct Workspace {
     float* colb = nullptr;      // per-block column sums (bias gradient)
     float* colo = nullptr;      // per-block column sums (output weights)
     double* losspart = nullptr;
+    float* dypart = nullptr;    // per-block sums of dy
 };
 
 constexpr int kSplitK = 16;
@@ -62,6 +63,7 @@ void ws_free(Workspace& w) {
     (void)hipFree(w.colb);
     (void)hipFree(w.colo);
     (void)hipFree(w.losspart);
+    (void)hipFree(w.dypart);
     w = Workspace();
 }
 
@@ -83,7 +85,8 @@ bool ws_ensure(Workspace& w, int64_t rows, bool train) {
         ok = ok && dalloc(&w.dy, cap) && dalloc(&w.dZb, size_t(cap) * kHidden) &&
              dalloc(&w.dZT, size_t(cap) * kHidden) && dalloc(&w.dH, size_t(cap) * kHidden) &&
              dalloc(&w.gpart, size_t(kSplitK) * kHidden * kHidden) && dalloc(&w.colb, size_t(nb) * kHidden) &&
-             dalloc(&w.colo, size_t(nb) * kHidden) && dalloc(&w.losspart, size_t((cap + 255) / 256));
+             dalloc(&w.colo, size_t(nb) * kHidden) && dalloc(&w.losspart, size_t((cap + 255) / 256)) &&
+             dalloc(&w.dypart, size_t((cap + 255) / 256));
     }
     if (!ok) ws_free(w);
     return ok;
@@ -160,7 +163,7 @@ void forward(env_surrogate* s, const double* pts, int64_t n, int64_t Np, bool tr
 // Loss partials and the full gradient into d_grad (forward must have run with train = true).
 void backward(env_surrogate* s, const float* t, int64_t n, int64_t Np, void* st) {
     Workspace& w = s->ws;
-    sg_loss(w.y, t, n, Np, w.dy, w.losspart, st);
+    sg_loss(w.y, t, n, Np, w.dy, w.losspart, w.dypart, st);
     const int nb = int((Np + kRowsPerBlock - 1) / kRowsPerBlock);
     for (int l = kLayers - 1; l >= 0; --l) {
         const bool top = l == kLayers - 1;
@@ -170,7 +173,7 @@ void backward(env_surrogate* s, const float* t, int64_t n, int64_t Np, void* st)
         sg_reduce_rows(w.colb, nb, kHidden, gl + kHidden * kHidden, st);
         if (top) {
             sg_reduce_rows(w.colo, nb, kHidden, s->d_grad + kOutOffset, st);
-            sg_reduce_rows(w.dy, int(Np), 1, s->d_grad + kOutOffset + kHidden, st);
+            sg_reduce_rows(w.dypart, int((Np + 255) / 256), 1, s->d_grad + kOutOffset + kHidden, st);
         }
         const int nz = sg_gemm_nt(w.dZT, int(Np), w.HT[l], int(Np), w.gpart, kHidden, kHidden, kHidden, int(Np),
                                   kSplitK, st);

@@ -123,15 +123,17 @@ __global__ __launch_bounds__(256) void k_out_fwd(const uint16_t* __restrict__ H,
     y[row] = s + b[0];
 }
 
-// dy = 2 (y - t)/n on rows < n, 0 on padding; per-block partial of sum (y-t)^2.
+// dy = 2 (y - t)/n on rows < n, 0 on padding; per-block partials of
+// sum (y-t)^2 (FP64) and of sum dy (the output-bias gradient).
 __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ y, const float* __restrict__ t,
                                               int64_t n, int64_t Np, float* __restrict__ dy,
-                                              double* __restrict__ part) {
+                                              double* __restrict__ part, float* __restrict__ part_dy) {
     __shared__ double sh[256];
+    __shared__ float shd[256];
     const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
     double e2 = 0.0;
+    float d = 0.0f;
     if (row < Np) {
-        float d = 0.0f;
         if (row < n) {
             const float e = y[row] - t[row];
             d = 2.0f * e / (float)n;
@@ -140,12 +142,19 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ y, const
         dy[row] = d;
     }
     sh[threadIdx.x] = e2;
+    shd[threadIdx.x] = d;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        if (threadIdx.x < s) {
+            sh[threadIdx.x] += sh[threadIdx.x + s];
+            shd[threadIdx.x] += shd[threadIdx.x + s];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = sh[0];
+        part_dy[blockIdx.x] = shd[0];
+    }
 }
 
 // Backward through SiLU for one layer.  dH = dy (x) w_out for the top layer
@@ -440,8 +449,9 @@ void sg_out_fwd(const uint16_t* H, const float* w, const float* b, int64_t Np, f
     SG_LAUNCH(k_out_fwd, dim3(blocks(Np)), dim3(256), st, H, w, b, Np, y);
 }
 
-void sg_loss(const float* y, const float* t, int64_t n, int64_t Np, float* dy, double* part, void* st) {
-    SG_LAUNCH(k_loss, dim3(blocks(Np)), dim3(256), st, y, t, n, Np, dy, part);
+void sg_loss(const float* y, const float* t, int64_t n, int64_t Np, float* dy, double* part, float* part_dy,
+             void* st) {
+    SG_LAUNCH(k_loss, dim3(blocks(Np)), dim3(256), st, y, t, n, Np, dy, part, part_dy);
 }
 
 void sg_dsilu(const float* dH, const float* dy, const float* w_out, const float* Z, const uint16_t* Htop,

@@ -22,7 +22,8 @@ void sg_features(const double* pts, int64_t n, int64_t Np, const double* B, int 
                  uint16_t* HT, int64_t ldT, void* st);
 void sg_bias_silu(float* Z, const float* bias, uint16_t* H, uint16_t* HT, int64_t Np, int64_t ldT, void* st);
 void sg_out_fwd(const uint16_t* H, const float* w, const float* b, int64_t Np, float* y, void* st);
-void sg_loss(const float* y, const float* t, int64_t n, int64_t Np, float* dy, double* part, void* st);
+void sg_loss(const float* y, const float* t, int64_t n, int64_t Np, float* dy, double* part, float* part_dy,
+             void* st);
 void sg_dsilu(const float* dH, const float* dy, const float* w_out, const float* Z, const uint16_t* Htop,
               int64_t Np, uint16_t* dZb, uint16_t* dZT, int64_t ldT, float* colsum, float* colsum_out,
               void* st);
