@@ -78,6 +78,8 @@ typedef enum {
                                      that its electron count tr(P_f S_f) equals the
                                      fragment's nuclear charge (needs a block-diagonal P) */
 #define ENV_NO_SCREENING 0x4u     /* keep every primitive pair */
+#define ENV_NO_MERGE 0x8u         /* evaluate every pair on its own: no same-centre
+                                     clusters (results agree to rounding) */
 
 typedef struct {
     double xyz[3];     /* position, bohr */
@@ -129,6 +131,8 @@ typedef struct {
     int64_t device_bytes;         /* bytes held on the device by the handle */
     int32_t precision;
     int32_t built_on_device;      /* 0 with ENV_BUILD_ONLY */
+    int64_t n_clusters;           /* same-centre clusters (far fields merged per atom) */
+    int64_t n_cluster_members;    /* pairs inside those clusters (counted in n_pairs too) */
 } env_info;
 
 /* Default options: FP32C, current device, threshold 1e-12, no flags. */

@@ -129,7 +129,7 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
     else env_options_default(&opt);
     if (opt.precision != ENV_PREC_FP64 && opt.precision != ENV_PREC_FP32C) return ENV_E_ARG;
     if (opt.reserved[0] || opt.reserved[1] || opt.reserved[2]) return ENV_E_ARG;
-    if (opt.flags & ~(ENV_BUILD_ONLY | ENV_NEUTRALIZE | ENV_NO_SCREENING)) return ENV_E_ARG;
+    if (opt.flags & ~(ENV_BUILD_ONLY | ENV_NEUTRALIZE | ENV_NO_SCREENING | ENV_NO_MERGE)) return ENV_E_ARG;
     const bool build_only = (opt.flags & ENV_BUILD_ONLY) != 0;
 
     int device = opt.device;
@@ -180,12 +180,21 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
         return ENV_E_DEVICE;
     }
     const bool fp64 = h->precision == ENV_PREC_FP64;
+    Layout lay;
+    try {
+        pack_layout(pl, fp64, h->bp, (opt.flags & ENV_NO_MERGE) == 0, lay);
+    } catch (const std::bad_alloc&) {
+        delete h;
+        return ENV_E_NOMEM;
+    }
+    in.n_clusters = lay.n_clusters;
+    in.n_cluster_members = lay.n_members;
     std::vector<Segment> allsegs;
     std::vector<int32_t> allsplit;
     for (int k = 0; k <= kMaxSplitLog2; ++k) {
         std::vector<Segment> segs;
         std::vector<int32_t> split;
-        build_segments(pl, 1 << k, fp64, segs, split);
+        split_layout(lay, 1 << k, fp64, segs, split);
         h->seg_off[k] = int64_t(allsegs.size());
         h->split_off[k] = int64_t(allsplit.size());
         allsegs.insert(allsegs.end(), segs.begin(), segs.end());
@@ -196,8 +205,7 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
         *out = h;
         return ENV_OK;
     }
-    std::vector<uint32_t> rec;
-    pack_records(pl, fp64, h->bp, rec);
+    std::vector<uint32_t>& rec = lay.rec;
     {
         DeviceGuard g(device);
         hipDeviceProp_t prop;

@@ -48,11 +48,27 @@ constexpr int rec64_words(int L) { return 2 * (6 + 2 * kNComp[L]); }
 constexpr int kRec32Head = 9;   // words before h in an FP32C record
 constexpr int kRec64Head = 6;   // doubles before h in an FP64 record
 
-// A run of pairs of one L inside one fragment group, plus (on the group's
-// first segment) the group's nuclei.
+// Same-centre clusters.  A pair whose two shells sit on one atom has its
+// product centre exactly at that atom, so in the far field such pairs are
+// finite multipoles about one point and their polynomial coefficients h add
+// up exactly.  A cluster record holds the merged coefficients (at the largest
+// L of its members) and the largest far-field radius of its members; a wave
+// whose points are all beyond that radius evaluates the cluster once, any
+// other wave evaluates the members (ordinary pair records) one by one.
+//  FP32C cluster: P (3 doubles); r2far (float); member mask (bit L set when
+//                 there are members of that L); member table (word offset,
+//                 count) for L = 0..4; h[ncomp(Lc)] (float)
+//  FP64  cluster: P, r2far (doubles); mask, pad; member table; h (double)
+constexpr int kClMask32 = 7, kClTable32 = 8, kClHead32 = 18;  // in words
+constexpr int kClMask64 = 8, kClTable64 = 10, kClHead64 = 10; // words, words, doubles
+constexpr int cl32_words(int L) { return ((kClHead32 + kNComp[L]) + 1) & ~1; }
+constexpr int cl64_words(int L) { return 2 * (kClHead64 + kNComp[L]); }
+
+// A run of pairs (or of clusters) of one L inside one fragment group, plus
+// (on the group's first segment) the group's nuclei.
 struct Segment {
-    int32_t L;
-    int32_t n_pairs;
+    int32_t L;           // pair L, or the clusters' merged L
+    int32_t n_pairs;     // pairs, or clusters when flags has kSegCluster
     int64_t rec_off;     // offset of the first record, in 4-byte words
     int32_t nuc_begin;   // nuclei [nuc_begin, nuc_end) of the device array
     int32_t nuc_end;
@@ -60,6 +76,7 @@ struct Segment {
     int32_t pad;
 };
 constexpr int32_t kSegEndGroup = 1;
+constexpr int32_t kSegCluster = 2;
 
 struct BoysParams {
     float tfar32[kLMax + 1];   // FP32 path: asymptotic form for T >= tfar32[L]
@@ -115,6 +132,7 @@ struct PairList {
     std::vector<int32_t> L, group;
     std::vector<double> center;   // 3 per pair
     std::vector<double> p;
+    std::vector<int32_t> atom1;   // per pair: atom of both shells (one-centre pair) or -1
     std::vector<double> D;        // ncomp(L) per pair, pair k starts at d_off[k]
     std::vector<int64_t> d_off;   // n_pairs + 1
     std::vector<double> nuc;      // 4 per nucleus, grouped
@@ -131,19 +149,29 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
                            const env_shell* shells, int32_t n_shells,
                            const env_density* P, const env_options& opt, PairList& out);
 
+// Device image of a pair list in one precision: records (pair records,
+// cluster records and the clusters' member records) and the unsplit segments.
+struct Layout {
+    std::vector<uint32_t> rec;
+    std::vector<Segment> base;
+    std::vector<double> unit_cost;   // per base segment: estimated cost of one pair / cluster
+    int64_t n_clusters = 0;
+    int64_t n_members = 0;           // pairs inside clusters
+};
+
+// Pack the records of one precision; with merge, one-centre pairs are grouped
+// into clusters by atom and far-field radius band.
+void pack_layout(const PairList& pl, bool fp64, const BoysParams& bp, bool merge, Layout& out);
+
 // Segment table for split factor S: segments (cut where needed) and S+1
-// offsets, balancing the estimated cost of pairs and nuclei.
-void build_segments(const PairList& pl, int S, bool fp64, std::vector<Segment>& segs,
-                    std::vector<int32_t>& split);
+// offsets, balancing the estimated cost of pairs, clusters and nuclei.
+void split_layout(const Layout& lay, int S, bool fp64, std::vector<Segment>& segs,
+                  std::vector<int32_t>& split);
 
 // Far-field coefficients: for X = P - C with p |X|^2 >= tfar[L],
 //   sum_tuv D_tuv d^t_X d^u_Y d^v_Z (1/|X|) = (1/|X|) sum_abc h_abc x^a y^b z^c,
 //   x = X/|X|^2, y = Y/|X|^2, z = Z/|X|^2   (both in the hermite_index order).
 void far_coefs(int L, const double* D, double* h);
-
-// Pack the records of one precision.
-void pack_records(const PairList& pl, bool fp64, const BoysParams& bp,
-                  std::vector<uint32_t>& rec);
 
 // Boys tables (host FP64/long double) and the far-field thresholds.
 void build_boys_tables(std::vector<float>& t32, std::vector<double>& t64, BoysParams& bp);

@@ -293,6 +293,91 @@ __device__ __forceinline__ void pairs_f64(const GLB uint32_t* __restrict__ rec, 
     }
 }
 
+// Same-centre clusters of merged L = LC, from cluster i on: every cluster
+// whose far-field radius no point of the wave is inside is evaluated once
+// from its merged coefficients.  Stops at the first cluster with a point
+// inside that radius and returns its index (n when there is none); the
+// caller then evaluates that cluster's members pair by pair.
+template <int LC, int NP>
+__device__ __forceinline__ int clusters_f32(const GLB uint32_t* __restrict__ rec, int i, int n,
+                                            const double* cx, const double* cy, const double* cz,
+                                            double* ele) {
+    constexpr int CW = cl32_words(LC);
+    float tile[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) tile[k] = 0.0f;
+    int done = 0;
+    for (; i < n; ++i) {
+        const GLB uint32_t* r = rec + (int64_t)i * CW;
+        const GLB double* rd = reinterpret_cast<const GLB double*>(r);
+        const GLB float* rf = reinterpret_cast<const GLB float*>(r);
+        const double px = rd[0], py = rd[1], pz = rd[2];
+        const float r2far = rf[6];
+        float h[kNComp[LC]];
+#pragma unroll
+        for (int c = 0; c < kNComp[LC]; ++c) h[c] = rf[kClHead32 + c];
+        float X[NP], Y[NP], Z[NP], r2[NP];
+        bool nearp = false;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            X[k] = (float)(px - cx[k]);
+            Y[k] = (float)(py - cy[k]);
+            Z[k] = (float)(pz - cz[k]);
+            r2[k] = __builtin_fmaf(X[k], X[k], __builtin_fmaf(Y[k], Y[k], Z[k] * Z[k]));
+            nearp |= r2[k] < r2far;
+        }
+        if (__builtin_amdgcn_ballot_w64(nearp) != 0) break;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const float ri = rsqrt_refined(r2[k]);
+            const float w = ri * ri;
+            tile[k] = __builtin_fmaf(ri, far_poly<LC, float>(h, X[k] * w, Y[k] * w, Z[k] * w), tile[k]);
+        }
+        if ((++done & (kTile - 1)) == 0) {
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                ele[k] += (double)tile[k];
+                tile[k] = 0.0f;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) ele[k] += (double)tile[k];
+    return i;
+}
+
+template <int LC, int NP>
+__device__ __forceinline__ int clusters_f64(const GLB uint32_t* __restrict__ rec, int i, int n,
+                                            const double* cx, const double* cy, const double* cz,
+                                            double* ele) {
+    constexpr int CW = cl64_words(LC);
+    for (; i < n; ++i) {
+        const GLB double* rd = reinterpret_cast<const GLB double*>(rec + (int64_t)i * CW);
+        const double px = rd[0], py = rd[1], pz = rd[2], r2far = rd[3];
+        double h[kNComp[LC]];
+#pragma unroll
+        for (int c = 0; c < kNComp[LC]; ++c) h[c] = rd[kClHead64 + c];
+        double X[NP], Y[NP], Z[NP], r2[NP];
+        bool nearp = false;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            X[k] = px - cx[k];
+            Y[k] = py - cy[k];
+            Z[k] = pz - cz[k];
+            r2[k] = __builtin_fma(X[k], X[k], __builtin_fma(Y[k], Y[k], Z[k] * Z[k]));
+            nearp |= r2[k] < r2far;
+        }
+        if (__builtin_amdgcn_ballot_w64(nearp) != 0) break;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const double ri = rsqrt(r2[k]);
+            const double w = ri * ri;
+            ele[k] = __builtin_fma(ri, far_poly<LC, double>(h, X[k] * w, Y[k] * w, Z[k] * w), ele[k]);
+        }
+    }
+    return i;
+}
+
 // One workgroup's share: points of point block `pblock` against the pair
 // range of split `s` (all of it when S == 1).
 template <int NP, bool F64>
@@ -305,7 +390,7 @@ __device__ __forceinline__ void block_work_impl(const PTS double* __restrict__ p
                                                 double* __restrict__ out,
                                                 int64_t pblock, int s, const float* tab32) {
     const int64_t base = pblock * (kBlock * NP) + threadIdx.x;
-    double cx[NP], cy[NP], cz[NP], acc[NP], vn[NP], ve[NP];
+    double cx[NP], cy[NP], cz[NP], acc[NP], ve[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
         const int64_t i = base + (int64_t)k * kBlock;
@@ -313,56 +398,116 @@ __device__ __forceinline__ void block_work_impl(const PTS double* __restrict__ p
         cx[k] = pts[3 * ic];
         cy[k] = pts[3 * ic + 1];
         cz[k] = pts[3 * ic + 2];
-        acc[k] = vn[k] = ve[k] = 0.0;
+        acc[k] = ve[k] = 0.0;
     }
+    // Wave-uniform work loop over the segments of split s.  A cluster
+    // segment is scanned cluster by cluster; a cluster with some point of
+    // the wave inside its far-field radius hands its members (one run per L)
+    // to the same pair dispatch as ordinary segments.
     const int sb = split[s], se = split[s + 1];
-    for (int g = sb; g < se; ++g) {
-        Segment sg;
-        sg.L = segs[g].L;
-        sg.n_pairs = segs[g].n_pairs;
-        sg.rec_off = segs[g].rec_off;
-        sg.nuc_begin = segs[g].nuc_begin;
-        sg.nuc_end = segs[g].nuc_end;
-        sg.flags = segs[g].flags;
-        for (int q = sg.nuc_begin; q < sg.nuc_end; ++q) {
-            const double qx = nuc[4 * q], qy = nuc[4 * q + 1], qz = nuc[4 * q + 2],
-                         qZ = nuc[4 * q + 3];
-#pragma unroll
-            for (int k = 0; k < NP; ++k) {
-                const double dx = cx[k] - qx, dy = cy[k] - qy, dz = cz[k] - qz;
-                vn[k] += qZ * rsqrt(__builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz)));
+    int g = sb;
+    bool fold = false;
+    const GLB uint32_t* crec = recs;   // cluster segment in progress: clusters [ci, cn) of merged L lc
+    int ci = 0, cn = 0, lc = 0;
+    const GLB uint32_t* mtab = recs;   // member table of the cluster being expanded
+    uint32_t pend = 0;                 // its member runs (bit L) not yet evaluated
+    for (;;) {
+        int L, npairs;
+        const GLB uint32_t* rec;
+        if (pend != 0) {
+            L = __builtin_ctz(pend);
+            pend &= pend - 1;
+            rec = recs + mtab[2 * L];
+            npairs = (int)mtab[2 * L + 1];
+        } else if (ci < cn) {
+            if constexpr (F64) {
+                switch (lc) {
+                    case 0: ci = clusters_f64<0, NP>(crec, ci, cn, cx, cy, cz, ve); break;
+                    case 1: ci = clusters_f64<1, NP>(crec, ci, cn, cx, cy, cz, ve); break;
+                    case 2: ci = clusters_f64<2, NP>(crec, ci, cn, cx, cy, cz, ve); break;
+                    case 3: ci = clusters_f64<3, NP>(crec, ci, cn, cx, cy, cz, ve); break;
+                    default: ci = clusters_f64<4, NP>(crec, ci, cn, cx, cy, cz, ve); break;
+                }
+                if (ci < cn) {
+                    const GLB uint32_t* c = crec + (int64_t)ci * cl64_words(lc);
+                    mtab = c + kClTable64;
+                    pend = c[kClMask64];
+                    ++ci;
+                }
+            } else {
+                switch (lc) {
+                    case 0: ci = clusters_f32<0, NP>(crec, ci, cn, cx, cy, cz, ve); break;
+                    case 1: ci = clusters_f32<1, NP>(crec, ci, cn, cx, cy, cz, ve); break;
+                    case 2: ci = clusters_f32<2, NP>(crec, ci, cn, cx, cy, cz, ve); break;
+                    case 3: ci = clusters_f32<3, NP>(crec, ci, cn, cx, cy, cz, ve); break;
+                    default: ci = clusters_f32<4, NP>(crec, ci, cn, cx, cy, cz, ve); break;
+                }
+                if (ci < cn) {
+                    const GLB uint32_t* c = crec + (int64_t)ci * cl32_words(lc);
+                    mtab = c + kClTable32;
+                    pend = c[kClMask32];
+                    ++ci;
+                }
             }
+            continue;
+        } else {
+            if (fold) {
+#pragma unroll
+                for (int k = 0; k < NP; ++k) {
+                    acc[k] -= ve[k];
+                    ve[k] = 0.0;
+                }
+                fold = false;
+            }
+            if (g >= se) break;
+            const GLB Segment* sp = segs + g;
+            ++g;
+            const int sL = sp->L, sn = sp->n_pairs, nb = sp->nuc_begin, ne = sp->nuc_end,
+                      sf = sp->flags;
+            const int64_t so = sp->rec_off;
+            for (int q = nb; q < ne; ++q) {
+                const double qx = nuc[4 * q], qy = nuc[4 * q + 1], qz = nuc[4 * q + 2],
+                             qZ = nuc[4 * q + 3];
+#pragma unroll
+                for (int k = 0; k < NP; ++k) {
+                    const double dx = cx[k] - qx, dy = cy[k] - qy, dz = cz[k] - qz;
+                    ve[k] -= qZ * rsqrt(__builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz)));
+                }
+            }
+            fold = (sf & kSegEndGroup) != 0;
+            if (sf & kSegCluster) {
+                crec = recs + so;
+                ci = 0;
+                cn = sn;
+                lc = sL;
+                continue;
+            }
+            L = sL;
+            rec = recs + so;
+            npairs = sn;
         }
-        const GLB uint32_t* rec = recs + sg.rec_off;
         if constexpr (F64) {
             const GLB double* tab = boys64;
-            switch (sg.L) {
-                case 0: pairs_f64<0, NP>(rec, sg.n_pairs, cx, cy, cz, tab, ve); break;
-                case 1: pairs_f64<1, NP>(rec, sg.n_pairs, cx, cy, cz, tab, ve); break;
-                case 2: pairs_f64<2, NP>(rec, sg.n_pairs, cx, cy, cz, tab, ve); break;
-                case 3: pairs_f64<3, NP>(rec, sg.n_pairs, cx, cy, cz, tab, ve); break;
-                default: pairs_f64<4, NP>(rec, sg.n_pairs, cx, cy, cz, tab, ve); break;
+            switch (L) {
+                case 0: pairs_f64<0, NP>(rec, npairs, cx, cy, cz, tab, ve); break;
+                case 1: pairs_f64<1, NP>(rec, npairs, cx, cy, cz, tab, ve); break;
+                case 2: pairs_f64<2, NP>(rec, npairs, cx, cy, cz, tab, ve); break;
+                case 3: pairs_f64<3, NP>(rec, npairs, cx, cy, cz, tab, ve); break;
+                default: pairs_f64<4, NP>(rec, npairs, cx, cy, cz, tab, ve); break;
             }
         } else {
-            switch (sg.L) {
-                case 0: pairs_f32<0, NP>(rec, sg.n_pairs, cx, cy, cz, tab32, ve); break;
-                case 1: pairs_f32<1, NP>(rec, sg.n_pairs, cx, cy, cz, tab32, ve); break;
-                case 2: pairs_f32<2, NP>(rec, sg.n_pairs, cx, cy, cz, tab32, ve); break;
-                case 3: pairs_f32<3, NP>(rec, sg.n_pairs, cx, cy, cz, tab32, ve); break;
-                default: pairs_f32<4, NP>(rec, sg.n_pairs, cx, cy, cz, tab32, ve); break;
-            }
-        }
-        if (sg.flags & kSegEndGroup) {
-#pragma unroll
-            for (int k = 0; k < NP; ++k) {
-                acc[k] += vn[k] - ve[k];
-                vn[k] = ve[k] = 0.0;
+            switch (L) {
+                case 0: pairs_f32<0, NP>(rec, npairs, cx, cy, cz, tab32, ve); break;
+                case 1: pairs_f32<1, NP>(rec, npairs, cx, cy, cz, tab32, ve); break;
+                case 2: pairs_f32<2, NP>(rec, npairs, cx, cy, cz, tab32, ve); break;
+                case 3: pairs_f32<3, NP>(rec, npairs, cx, cy, cz, tab32, ve); break;
+                default: pairs_f32<4, NP>(rec, npairs, cx, cy, cz, tab32, ve); break;
             }
         }
     }
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-        acc[k] += vn[k] - ve[k];
+        acc[k] -= ve[k];
         const int64_t i = base + (int64_t)k * kBlock;
         if (i < n) out[(int64_t)s * n + i] = acc[k];
     }

@@ -98,6 +98,7 @@ struct Block {   // one unordered shell pair I <= J with its density block
 
 struct Bucket {  // pairs of one group and one L, appended in build order
     std::vector<double> rec;  // per pair: Px, Py, Pz, p, D[ncomp(L)]
+    std::vector<int32_t> atom;  // per pair: the atom of both shells, or -1 (two centres)
     int64_t n = 0;
 };
 
@@ -326,6 +327,7 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
             const int nI = ncart(lI), nJ = ncart(lJ);
             const double rab2 = (A[0] - Bc[0]) * (A[0] - Bc[0]) + (A[1] - Bc[1]) * (A[1] - Bc[1]) +
                                 (A[2] - Bc[2]) * (A[2] - Bc[2]);
+            const bool one_centre = SI.atom == SJ.atom;
             int eI[6][3], eJ[6][3];
             for (int c = 0; c < nI; ++c) cart(lI, c, eI[c]);
             for (int c = 0; c < nJ; ++c) cart(lJ, c, eJ[c]);
@@ -376,9 +378,16 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
                     }
                     const double sc = pp32;
                     Bucket& bu = go.b[L];
-                    bu.rec.push_back((a * A[0] + b * Bc[0]) / p);
-                    bu.rec.push_back((a * A[1] + b * Bc[1]) / p);
-                    bu.rec.push_back((a * A[2] + b * Bc[2]) / p);
+                    if (one_centre) {  // the product centre is the atom itself, exactly
+                        bu.rec.push_back(A[0]);
+                        bu.rec.push_back(A[1]);
+                        bu.rec.push_back(A[2]);
+                    } else {
+                        bu.rec.push_back((a * A[0] + b * Bc[0]) / p);
+                        bu.rec.push_back((a * A[1] + b * Bc[1]) / p);
+                        bu.rec.push_back((a * A[2] + b * Bc[2]) / p);
+                    }
+                    bu.atom.push_back(one_centre ? SI.atom : -1);
                     bu.rec.push_back(p);
                     for (int k = 0; k < nc; ++k) bu.rec.push_back(D[k] * sc);
                     ++bu.n;
@@ -471,6 +480,7 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
     out.group.resize(npairs);
     out.center.resize(3 * size_t(npairs));
     out.p.resize(npairs);
+    out.atom1.resize(npairs);
     out.d_off.resize(npairs + 1);
     out.D.resize(gd[n_groups]);
     out.d_off[npairs] = gd[n_groups];
@@ -498,12 +508,14 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
                             out.center[3 * k + 1] = r[1];
                             out.center[3 * k + 2] = r[2];
                             out.p[k] = r[3];
+                            out.atom1[k] = bu.atom[j];
                             out.d_off[k] = d;
                             for (int c = 0; c < kNComp[L]; ++c) out.D[d + c] = r[4 + c];
                             d += kNComp[L];
                             q += r[4];
                         }
                         std::vector<double>().swap(bu.rec);
+                        std::vector<int32_t>().swap(bu.atom);
                     }
                     qg[g] = q;
                 }
@@ -513,90 +525,6 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
     for (int g = 0; g < n_groups; ++g) out.electrons += qg[g];
     lap("order");
     return ENV_OK;
-}
-
-// ------------------------------------------------------------- segments
-
-namespace {
-// Estimated relative cost of one point-pair by L and of one point-nucleus.
-const double kCost32[kLMax + 1] = {1.0, 1.5, 2.6, 4.4, 7.5};
-const double kCost64[kLMax + 1] = {1.0, 1.4, 2.3, 3.8, 6.3};
-const double kCostNuc = 0.6;
-}  // namespace
-
-void build_segments(const PairList& pl, int S, bool fp64, std::vector<Segment>& segs,
-                    std::vector<int32_t>& split) {
-    const double* w = fp64 ? kCost64 : kCost32;
-    // base segments: one per (group, L) run, nuclei on the group's first one
-    std::vector<Segment> base;
-    int64_t word = 0;
-    for (int g = 0; g < pl.n_groups; ++g) {
-        const int64_t b = pl.group_pair_begin[g], e = pl.group_pair_begin[g + 1];
-        const size_t first = base.size();
-        int64_t k = b;
-        for (int L = 0; L <= kLMax; ++L) {
-            int64_t m = k;
-            while (m < e && pl.L[m] == L) ++m;
-            if (m > k) {
-                Segment s{};
-                s.L = L;
-                s.n_pairs = int32_t(m - k);
-                s.rec_off = word;
-                word += (m - k) * (fp64 ? rec64_words(L) : rec32_words(L));
-                base.push_back(s);
-            }
-            k = m;
-        }
-        const int nb = pl.group_nuc_begin[g], ne = pl.group_nuc_end[g];
-        if (base.size() == first && ne > nb) {
-            Segment s{};
-            s.L = 0;
-            s.rec_off = word;
-            base.push_back(s);
-        }
-        if (base.size() > first) {
-            base[first].nuc_begin = nb;
-            base[first].nuc_end = ne;
-            base.back().flags |= kSegEndGroup;
-        }
-    }
-    double total = 0.0;
-    for (const Segment& s : base) total += s.n_pairs * w[s.L] + (s.nuc_end - s.nuc_begin) * kCostNuc;
-    segs.clear();
-    split.assign(1, 0);
-    const double target = total / S;
-    double acc = 0.0;
-    int cur = 0;
-    for (Segment rem : base) {
-        double nucc = (rem.nuc_end - rem.nuc_begin) * kCostNuc;
-        for (;;) {
-            const double cost = nucc + rem.n_pairs * w[rem.L];
-            const double boundary = (cur + 1) * target;
-            if (cur < S - 1 && rem.n_pairs > 0 && acc + cost > boundary) {
-                int64_t k = int64_t(std::floor((boundary - acc - nucc) / w[rem.L]));
-                k = std::max<int64_t>(0, std::min<int64_t>(k, rem.n_pairs));
-                if (k > 0 || nucc > 0) {
-                    Segment a = rem;
-                    a.n_pairs = int32_t(k);
-                    a.flags = 0;
-                    segs.push_back(a);
-                }
-                acc += nucc + k * w[rem.L];
-                rem.rec_off += k * (fp64 ? rec64_words(rem.L) : rec32_words(rem.L));
-                rem.n_pairs -= int32_t(k);
-                rem.nuc_begin = rem.nuc_end;
-                nucc = 0.0;
-                split.push_back(int32_t(segs.size()));
-                ++cur;
-                continue;
-            }
-            if (rem.n_pairs > 0 || rem.nuc_end > rem.nuc_begin || (rem.flags & kSegEndGroup))
-                segs.push_back(rem);
-            acc += cost;
-            break;
-        }
-    }
-    while (int(split.size()) < S + 1) split.push_back(int32_t(segs.size()));
 }
 
 namespace {
@@ -669,44 +597,6 @@ void far_coefs(int L, const double* D, double* h) {
             }
 }
 
-void pack_records(const PairList& pl, bool fp64, const BoysParams& bp,
-                  std::vector<uint32_t>& rec) {
-    rec.clear();
-    const int64_t n = int64_t(pl.L.size());
-    double h[35];
-    for (int64_t k = 0; k < n; ++k) {
-        const int L = pl.L[k], nc = kNComp[L];
-        const double p = pl.p[k];
-        const double c1 = 2.0 * std::sqrt(p / kPi);
-        const double* D = &pl.D[pl.d_off[k]];
-        far_coefs(L, D, h);
-        const size_t o = rec.size();
-        if (fp64) {
-            rec.resize(o + rec64_words(L), 0u);
-            double* r = reinterpret_cast<double*>(&rec[o]);
-            r[0] = pl.center[3 * k];
-            r[1] = pl.center[3 * k + 1];
-            r[2] = pl.center[3 * k + 2];
-            r[3] = bp.tfar64[L] / p;
-            r[4] = p;
-            r[5] = c1;
-            for (int c = 0; c < nc; ++c) r[kRec64Head + c] = h[c];
-            for (int c = 0; c < nc; ++c) r[kRec64Head + nc + c] = D[c];
-        } else {
-            rec.resize(o + rec32_words(L), 0u);
-            double* r = reinterpret_cast<double*>(&rec[o]);
-            r[0] = pl.center[3 * k];
-            r[1] = pl.center[3 * k + 1];
-            r[2] = pl.center[3 * k + 2];
-            float* f = reinterpret_cast<float*>(&rec[o + 6]);
-            f[0] = float(double(bp.tfar32[L]) / p);
-            f[1] = float(p);
-            f[2] = float(c1);
-            for (int c = 0; c < nc; ++c) f[3 + c] = float(h[c]);
-            for (int c = 0; c < nc; ++c) f[3 + nc + c] = float(D[c]);
-        }
-    }
-}
 
 // ------------------------------------------------------------ Boys tables
 

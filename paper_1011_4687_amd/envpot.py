@@ -31,6 +31,7 @@ ENV_PREC_FP32C = 1
 ENV_BUILD_ONLY = 0x1
 ENV_NEUTRALIZE = 0x2
 ENV_NO_SCREENING = 0x4
+ENV_NO_MERGE = 0x8
 
 ENV_DENSITY_DENSE = 0
 ENV_DENSITY_CSR = 1
@@ -65,7 +66,8 @@ class env_info(ctypes.Structure):
                 ("n_pairs_unscreened", c_int64), ("electrons", c_double),
                 ("nuclear_charge", c_double), ("screened_bound", c_double),
                 ("device_bytes", c_int64), ("precision", c_int32),
-                ("built_on_device", c_int32)]
+                ("built_on_device", c_int32), ("n_clusters", c_int64),
+                ("n_cluster_members", c_int64)]
 
 
 class env_batch_stats(ctypes.Structure):
@@ -286,7 +288,7 @@ class Environment:
     def __init__(self, xyz, Z, fragment, shells, P, precision: str = "fp32c",
                  device: int = -1, screen_threshold: float = 1e-12,
                  neutralize: bool = False, build_only: bool = False,
-                 screening: bool = True):
+                 screening: bool = True, merge: bool = True):
         self.handle = 0
         xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
         K = xyz.shape[0]
@@ -328,7 +330,7 @@ class Environment:
         opt.device = int(device)
         opt.screen_threshold = float(screen_threshold)
         opt.flags = ((ENV_NEUTRALIZE if neutralize else 0) | (ENV_BUILD_ONLY if build_only else 0)
-                     | (0 if screening else ENV_NO_SCREENING))
+                     | (0 if screening else ENV_NO_SCREENING) | (0 if merge else ENV_NO_MERGE))
         self.precision = precision
         self.handle = env_potential_create(nuc, K, sh, len(shells), dens, opt)
         self._keep = None

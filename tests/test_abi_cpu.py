@@ -64,6 +64,26 @@ def test_build_only_info_and_counts():
     assert h2.info()["n_pairs_unscreened"] == O.count_pairs(env2, screen=False)
 
 
+def test_same_centre_clusters_counts():
+    """Pairs whose two shells sit on one atom are merged into clusters of at
+    least two members; without merging there are none."""
+    env, shells = _tiny_args()
+    P = env.density_csr()
+    one_centre = 0
+    nsh = [0] * len(env.xyz)
+    for s in env.shells:
+        nsh[s.atom] += len(s.exponents)   # tiny: uncontracted shells, one primitive each
+    one_centre = sum(n * (n + 1) // 2 for n in nsh)
+    for prec in ("fp32c", "fp64"):
+        info = _build_only(env, shells, P, screening=False, precision=prec).info()
+        assert info["n_clusters"] >= 1
+        assert 2 * info["n_clusters"] <= info["n_cluster_members"] <= one_centre
+        assert info["n_pairs"] == 1830
+        off = _build_only(env, shells, P, screening=False, precision=prec, merge=False).info()
+        assert off["n_clusters"] == 0 and off["n_cluster_members"] == 0
+        assert off["n_pairs"] == info["n_pairs"]
+
+
 def test_neutralize_matches_oracle_trace():
     """ENV_NEUTRALIZE scales every fragment to tr(P_f S_f) = Z_f; the library's
     electron counts (screened pairs' charges plus dropped pairs') follow the

@@ -96,3 +96,31 @@ def test_point_on_nucleus_is_inf():
     V = _gpu(E, env.xyz[:3])
     assert np.all(np.isposinf(V))
     E.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32c", "fp64"])
+def test_clusters_match_pairwise(precision):
+    """Same-centre clusters change only the rounding: on every point of the
+    full mid workload the merged evaluation agrees with the pair-by-pair one
+    (waves with some point inside a cluster's radius take its members), and
+    the sampled points agree with the oracle."""
+    from oracle import oracle as O
+    from paper_1011_4687_amd.envpot import Environment
+    print(f"[parity] clusters {precision}", flush=True)
+    env, pts, P, _ = workload_scaled("mid", None)
+    shells = [(s.atom, s.l, s.exponents, s.coefs) for s in env.shells]
+    Em = Environment(env.xyz, env.Z, env.fragment, shells, P, precision=precision)
+    Ep = Environment(env.xyz, env.Z, env.fragment, shells, P, precision=precision, merge=False)
+    assert Em.info()["n_clusters"] > 0 and Ep.info()["n_clusters"] == 0
+    Vm, Vp = _gpu(Em, pts), _gpu(Ep, pts)
+    d = np.abs(Vm - Vp)
+    print(f"[parity] clusters {precision}: max |merged - pairwise| {d.max():.3e}", flush=True)
+    assert d.max() <= (2e-6 if precision == "fp32c" else 1e-11)
+    idx = sample_indices(len(pts), 24)
+    Vo, _, _, A = O.potential(env, pts[idx], P=P, screen=precision == "fp64")
+    if precision == "fp64":
+        assert np.all(np.abs(Vm[idx] - Vo) <= FP64_REL * A)
+    else:
+        assert np.abs(Vm[idx] - Vo).max() <= FP32_TOL
+    Em.close()
+    Ep.close()
