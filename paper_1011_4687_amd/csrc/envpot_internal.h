@@ -19,7 +19,7 @@ constexpr int kBlock = 256;               // threads per workgroup of the point 
 constexpr int kBoysGridInv = 8;
 constexpr int kBoysRowF32 = 12;           // floats per row: F_0..F_9 (+2 pad)
 constexpr int kBoysTaylorF32 = 6;         // Taylor terms j = 0..5, |dT| <= 1/16
-constexpr int kBoysRowF64 = 16;           // doubles per row: F_0..F_13 (+2 pad)
+constexpr int kBoysRowF64 = 14;           // doubles per row: F_0..F_13
 constexpr int kBoysTaylorF64 = 10;        // Taylor terms j = 0..9
 constexpr int kBoysMaxRowsF32 = 8 * 40 + 1;
 

@@ -71,6 +71,19 @@ __device__ __forceinline__ float rsqrt_refined(float x) {
     return __builtin_fmaf(0.5f * e, y, y);
 }
 
+// 1/sqrt(x) for finite x > 0 (far-field distances): v_rsq_f64 plus the
+// second-order correction y (1 + e/2 + 3e^2/8), e = 1 - x y^2, of the series
+// of (1 - e)^(-1/2).
+__device__ __forceinline__ double rsqrt_far(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double h = x * y;
+    const double e = __builtin_fma(-h, y, 1.0);
+    return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
+}
+
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <int L, typename T>
 __device__ __forceinline__ T far_poly(const T* __restrict__ h, T x, T y, T z) {
     if constexpr (L == 0) return far_poly_L0<T>(h, x, y, z);
@@ -78,6 +91,19 @@ __device__ __forceinline__ T far_poly(const T* __restrict__ h, T x, T y, T z) {
     else if constexpr (L == 2) return far_poly_L2<T>(h, x, y, z);
     else if constexpr (L == 3) return far_poly_L3<T>(h, x, y, z);
     else return far_poly_L4<T>(h, x, y, z);
+}
+
+// The far-field polynomial at X = P - C with w = 1/|X|^2.  For L = 1 the
+// degree-1 part is formed from X directly, h0 + w (hx X + hy Y + hz Z),
+// which saves the three scalings X w, Y w, Z w.
+template <int L, typename T>
+__device__ __forceinline__ T far_value(const T* __restrict__ h, T X, T Y, T Z, T w) {
+    if constexpr (L == 1) {
+        // component order (0,0,0), (0,0,1), (0,1,0), (1,0,0)
+        return fma_t(w, fma_t(h[1], Z, fma_t(h[2], Y, h[3] * X)), h[0]);
+    } else {
+        return far_poly<L, T>(h, X * w, Y * w, Z * w);
+    }
 }
 
 // The part of a record every point needs: centre, far-field radius^2 and
@@ -185,62 +211,60 @@ __device__ __forceinline__ void pairs_f32(const GLB uint32_t* __restrict__ rec, 
                                           const float* tab, double* ele) {
     constexpr int RW = rec32_words(L);
     if (npairs <= 0) return;
-    float tile[NP];
-#pragma unroll
-    for (int k = 0; k < NP; ++k) tile[k] = 0.0f;
     Head<L, float> cur;
     if constexpr (kPipelined<L, float>) load_head32<L>(rec, cur);
-    for (int i = 0; i < npairs; ++i) {
-        const GLB uint32_t* r = rec + (int64_t)i * RW;
-        Head<L, float> nxt;
-        if constexpr (kPipelined<L, float>) load_head32<L>(rec + (int64_t)min(i + 1, npairs - 1) * RW, nxt);
-        else load_head32<L>(r, cur);
-        float X[NP], Y[NP], Z[NP], r2[NP];
-        bool nearp = false;
+    // tiles of kTile pairs: FP32 partial sums, promoted to FP64 per tile
+    for (int i0 = 0; i0 < npairs; i0 += kTile) {
+        const int i1 = min(i0 + kTile, npairs);
+        float tile[NP];
 #pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            X[k] = (float)(cur.px - cx[k]);
-            Y[k] = (float)(cur.py - cy[k]);
-            Z[k] = (float)(cur.pz - cz[k]);
-            r2[k] = __builtin_fmaf(X[k], X[k], __builtin_fmaf(Y[k], Y[k], Z[k] * Z[k]));
-            nearp |= r2[k] < cur.r2far;
-        }
-        if (__builtin_amdgcn_ballot_w64(nearp) == 0) {
-            // every point of the wave is in the far field of this pair:
-            // (1/R) sum h_abc (X/R^2)^a (Y/R^2)^b (Z/R^2)^c
+        for (int k = 0; k < NP; ++k) tile[k] = 0.0f;
+        int i = i0;
+        while (i < i1) {
+            float X[NP], Y[NP], Z[NP], r2[NP];
+            Head<L, float> nxt;
+            // far-field run: pairs whose far-field radius no point of the wave is inside
+            for (; i < i1; ++i) {
+                if constexpr (kPipelined<L, float>) load_head32<L>(rec + (int64_t)min(i + 1, npairs - 1) * RW, nxt);
+                else load_head32<L>(rec + (int64_t)i * RW, cur);
 #pragma unroll
-            for (int k = 0; k < NP; ++k) {
-                const float ri = rsqrt_refined(r2[k]);
-                const float w = ri * ri;
-                tile[k] = __builtin_fmaf(ri, far_poly<L, float>(cur.h, X[k] * w, Y[k] * w, Z[k] * w),
-                                         tile[k]);
+                for (int k = 0; k < NP; ++k) {
+                    X[k] = (float)(cur.px - cx[k]);
+                    Y[k] = (float)(cur.py - cy[k]);
+                    Z[k] = (float)(cur.pz - cz[k]);
+                    r2[k] = __builtin_fmaf(X[k], X[k], __builtin_fmaf(Y[k], Y[k], Z[k] * Z[k]));
+                }
+                float m = r2[0];
+#pragma unroll
+                for (int k = 1; k < NP; ++k) m = fminf(m, r2[k]);
+                if (__builtin_expect(__builtin_amdgcn_ballot_w64(m < cur.r2far) != 0, 0)) break;
+#pragma unroll
+                for (int k = 0; k < NP; ++k) {
+                    const float ri = rsqrt_refined(r2[k]);
+                    const float w = ri * ri;
+                    tile[k] = __builtin_fmaf(ri, far_value<L, float>(cur.h, X[k], Y[k], Z[k], w), tile[k]);
+                }
+                if constexpr (kPipelined<L, float>) cur = nxt;
             }
-        } else {
-            // rare: some point inside the near-field radius of this pair
+            if (i >= i1) break;
+            // pair i has some point of the wave inside its far-field radius
+            const GLB uint32_t* r = rec + (int64_t)i * RW;
 #pragma unroll
             for (int k = 0; k < NP; ++k) {
-                float v;
                 if (r2[k] < cur.r2far) {
-                    v = near_f32<L>(r, X[k], Y[k], Z[k], r2[k], tab);
+                    tile[k] += near_f32<L>(r, X[k], Y[k], Z[k], r2[k], tab);
                 } else {
                     const float ri = rsqrt_refined(r2[k]);
                     const float w = ri * ri;
-                    v = ri * far_poly<L, float>(cur.h, X[k] * w, Y[k] * w, Z[k] * w);
+                    tile[k] = __builtin_fmaf(ri, far_value<L, float>(cur.h, X[k], Y[k], Z[k], w), tile[k]);
                 }
-                tile[k] += v;
             }
+            if constexpr (kPipelined<L, float>) cur = nxt;
+            ++i;
         }
-        if ((i & (kTile - 1)) == kTile - 1) {
 #pragma unroll
-            for (int k = 0; k < NP; ++k) {
-                ele[k] += (double)tile[k];
-                tile[k] = 0.0f;
-            }
-        }
-        if constexpr (kPipelined<L, float>) cur = nxt;
+        for (int k = 0; k < NP; ++k) ele[k] += (double)tile[k];
     }
-#pragma unroll
-    for (int k = 0; k < NP; ++k) ele[k] += (double)tile[k];
 }
 
 // FP64 pairs of one L.  Record: P, r2far, p, c1 (doubles), h[nc], D[nc].
@@ -270,9 +294,9 @@ __device__ __forceinline__ void pairs_f64(const GLB uint32_t* __restrict__ rec, 
         if (__builtin_amdgcn_ballot_w64(nearp) == 0) {
 #pragma unroll
             for (int k = 0; k < NP; ++k) {
-                const double ri = rsqrt(r2[k]);
+                const double ri = rsqrt_far(r2[k]);
                 const double w = ri * ri;
-                ele[k] = __builtin_fma(ri, far_poly<L, double>(cur.h, X[k] * w, Y[k] * w, Z[k] * w),
+                ele[k] = __builtin_fma(ri, far_value<L, double>(cur.h, X[k], Y[k], Z[k], w),
                                        ele[k]);
             }
         } else {
@@ -282,9 +306,9 @@ __device__ __forceinline__ void pairs_f64(const GLB uint32_t* __restrict__ rec, 
                 if (r2[k] < cur.r2far) {
                     v = near_f64<L>(r, X[k], Y[k], Z[k], r2[k], tab);
                 } else {
-                    const double ri = rsqrt(r2[k]);
+                    const double ri = rsqrt_far(r2[k]);
                     const double w = ri * ri;
-                    v = ri * far_poly<L, double>(cur.h, X[k] * w, Y[k] * w, Z[k] * w);
+                    v = ri * far_value<L, double>(cur.h, X[k], Y[k], Z[k], w);
                 }
                 ele[k] += v;
             }
@@ -331,7 +355,7 @@ __device__ __forceinline__ int clusters_f32(const GLB uint32_t* __restrict__ rec
         for (int k = 0; k < NP; ++k) {
             const float ri = rsqrt_refined(r2[k]);
             const float w = ri * ri;
-            tile[k] = __builtin_fmaf(ri, far_poly<LC, float>(h, X[k] * w, Y[k] * w, Z[k] * w), tile[k]);
+            tile[k] = __builtin_fmaf(ri, far_value<LC, float>(h, X[k], Y[k], Z[k], w), tile[k]);
         }
         if ((++done & (kTile - 1)) == 0) {
 #pragma unroll
@@ -370,9 +394,9 @@ __device__ __forceinline__ int clusters_f64(const GLB uint32_t* __restrict__ rec
         if (__builtin_amdgcn_ballot_w64(nearp) != 0) break;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
-            const double ri = rsqrt(r2[k]);
+            const double ri = rsqrt_far(r2[k]);
             const double w = ri * ri;
-            ele[k] = __builtin_fma(ri, far_poly<LC, double>(h, X[k] * w, Y[k] * w, Z[k] * w), ele[k]);
+            ele[k] = __builtin_fma(ri, far_value<LC, double>(h, X[k], Y[k], Z[k], w), ele[k]);
         }
     }
     return i;
@@ -523,6 +547,10 @@ __device__ __forceinline__ void block_work(const EvalArgs& a, int64_t pblock, in
                              glb(static_cast<const double*>(a.boys)), a.out, pblock, s, tab32);
 }
 
+// Stage the FP32 Boys table into LDS (one copy per workgroup; the near
+// field gathers from it by per-lane row).  The FP64 table is read through
+// the caches: at 45 KB per workgroup it would cost a quarter of the FP64
+// kernel's occupancy, which measured slower.
 template <bool F64>
 __device__ __forceinline__ void load_boys_lds(const void* boys, int rows32, float* tab32) {
     if constexpr (!F64) {

@@ -7,6 +7,7 @@
 // ordinary pair records reached only through their cluster's member table.
 #include <algorithm>
 #include <cstdint>
+#include <cstdlib>
 #include <cmath>
 #include <limits>
 #include <map>
@@ -27,8 +28,13 @@ const double kCostNuc = 0.6;
 // Extra cost of a cluster per unit of member cost: the share of waves that
 // have some point inside the cluster's far-field radius.
 const double kClusterNearShare = 0.1;
-// Far-field radius bands per atom (log-uniform over the one-centre pairs).
-const int kBands = 3;
+// Far-field radius bands per atom (log-uniform over the one-centre pairs);
+// ENVPOT_BANDS (1..8) overrides it for tuning.
+int radius_bands() {
+    const char* e = std::getenv("ENVPOT_BANDS");
+    const int v = e ? std::atoi(e) : 0;
+    return (v >= 1 && v <= 8) ? v : 4;
+}
 
 double pair_r2far(const PairList& pl, int64_t k, bool fp64, const BoysParams& bp) {
     const int L = pl.L[k];
@@ -95,7 +101,8 @@ void pack_layout(const PairList& pl, bool fp64, const BoysParams& bp, bool merge
             hi = std::max(hi, v);
         }
     }
-    const double band_w = (hi > lo) ? (hi - lo) / kBands : 1.0;
+    const int bands = radius_bands();
+    const double band_w = (hi > lo) ? (hi - lo) / bands : 1.0;
 
     for (int g = 0; g < pl.n_groups; ++g) {
         const int64_t b = pl.group_pair_begin[g], e = pl.group_pair_begin[g + 1];
@@ -106,7 +113,7 @@ void pack_layout(const PairList& pl, bool fp64, const BoysParams& bp, bool merge
             for (int64_t k = b; k < e; ++k) {
                 if (merge && pl.atom1[k] >= 0) {
                     const double v = std::log(pair_r2far(pl, k, fp64, bp));
-                    const int band = std::min(kBands - 1, std::max(0, int((v - lo) / band_w)));
+                    const int band = std::min(bands - 1, std::max(0, int((v - lo) / band_w)));
                     by_key[{pl.atom1[k], band}].push_back(k);
                 } else {
                     ord.push_back(k);
