@@ -561,7 +561,7 @@ __device__ __forceinline__ void load_boys_lds(const void* boys, int rows32, floa
 }
 
 template <int NP, bool F64>
-__global__ __launch_bounds__(kBlock) void k_potential(EvalArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_potential(EvalArgs a) {
     __shared__ float tab32[F64 ? 1 : kBoysMaxRowsF32 * kBoysRowF32];
     load_boys_lds<F64>(a.boys, a.bp.rows32, tab32);
     block_work<NP, F64>(a, blockIdx.x, blockIdx.y, tab32);
@@ -573,7 +573,7 @@ __global__ __launch_bounds__(kBlock) void k_potential(EvalArgs a) {
 // first.  Every workgroup reaches the exit test once the counter passes
 // n_items, so the grid always drains.
 template <int NP, bool F64>
-__global__ __launch_bounds__(kBlock) void k_potential_persistent(BatchArgs b) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_potential_persistent(BatchArgs b) {
     __shared__ float tab32[F64 ? 1 : kBoysMaxRowsF32 * kBoysRowF32];
     __shared__ unsigned long long item_sh;
     load_boys_lds<F64>(b.boys, b.rows32, tab32);
