@@ -79,4 +79,34 @@ def test_batched_full_size():
         worst = max(worst, float(np.abs(outs[k].cpu().numpy()[idx] - Vf).max()))
     print(f"[fullsize] batched: max err {worst:.3e}, stats {B.stats()}", flush=True)
     assert worst <= 1e-5
+    # throughput on a side stream (the default stream cannot be captured):
+    # the persistent launch replayed from its graph against one launch per
+    # instance on the same stream
+    work = sum(h.info()["n_pairs"] * len(x) for h, x in zip(hs, xs))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(2):
+            B.eval(xs, outs)
+        side.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            B.eval(xs, outs)
+        side.synchronize()
+        t_batch = (time.perf_counter() - t0) / 3
+        ref = [o.clone() for o in outs]
+        for h, x, o in zip(hs, xs, outs):
+            h.eval(x, out=o)
+        side.synchronize()
+        t0 = time.perf_counter()
+        for h, x, o in zip(hs, xs, outs):
+            h.eval(x, out=o)
+        side.synchronize()
+        t_each = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    assert B.stats()["graph_launches"] >= 5
+    worst_diff = max(float((a - b).abs().max()) for a, b in zip(ref, outs))
+    assert worst_diff <= 1e-5, worst_diff
+    print(f"[fullsize] batched: persistent launch {t_batch * 1e3:.1f} ms ({work / t_batch:.3e} point-pairs/s), "
+          f"64 separate launches {t_each * 1e3:.1f} ms, stats {B.stats()}", flush=True)
     B.close()
