@@ -244,6 +244,23 @@ def main():
         "paths": paths,
     }
 
+    # on-device peak probes: what independent FMA / rsq streams sustain here
+    try:
+        pk = envpot.peak_probe()
+        result["peak_probe"] = {
+            "fp32_fma_tflops": pk["fp32_fma_tflops"],
+            "fp64_fma_tflops": pk["fp64_fma_tflops"],
+            "rsq_f32_per_s": pk["rsq_f32_per_s"],
+            "fp32c_achieved_frac": (flops / (paths["fp32c"]["ms_per_step"] * 1e-3) / 1e12)
+            / pk["fp32_fma_tflops"] if "fp32c" in paths else None,
+            "fp64_achieved_frac": (flops / (paths["fp64"]["ms_per_step"] * 1e-3) / 1e12)
+            / pk["fp64_fma_tflops"] if "fp64" in paths else None,
+        }
+        log(f"[bench] peak probe: FP32 FMA {pk['fp32_fma_tflops']:.1f} TFLOP/s, "
+            f"FP64 FMA {pk['fp64_fma_tflops']:.1f} TFLOP/s, rsq {pk['rsq_f32_per_s']:.3g}/s")
+    except envpot.EnvError as e:
+        log(f"[bench] peak probe failed: {e}")
+
     if not args.no_cpu_baseline:
         # CPU-baseline leg: the FP64 oracle on a bounded sample of the same points
         from oracle import oracle as O

@@ -214,6 +214,21 @@ env_status env_potential_autotune(env_potential* h, const double* points, int64_
 /* Statistics of the built pair list. */
 env_status env_potential_info(const env_potential* h, env_info* info);
 
+/* Vector-ALU rates this device sustains, for roofline reports (measurement
+ * support; not part of the method).  Runs three short kernels on `device`
+ * (-1 = current): independent v_fma_f32 chains, v_fma_f64 chains and
+ * v_rsq_f32 chains, eight per lane, 2048 iterations, 8192 x 256 threads.
+ * Fills the achieved rates; blocks until done (about 10 ms).
+ * Errors: ENV_E_ARG (NULL), ENV_E_DEVICE (no gfx950 device, launch failure),
+ * ENV_E_NOMEM. */
+typedef struct {
+    double fp32_fma_tflops;   /* 2 flops per lane FMA */
+    double fp64_fma_tflops;
+    double rsq_f32_per_s;     /* lane reciprocal square roots per second */
+    double ms[3];             /* kernel times: fma32, fma64, rsq32 */
+} env_peak;
+env_status env_peak_probe(int32_t device, env_peak* out);
+
 /* Copy of the pair list for inspection (host buffers, any handle):
  * for each of the n_pairs pairs, in the library's internal order:
  *   L[k] (int32), group[k] (int32), center[3k..3k+2], exponent p[k] and the

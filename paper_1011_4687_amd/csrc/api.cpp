@@ -317,6 +317,24 @@ env_status env_potential_info(const env_potential* h, env_info* info) {
     return ENV_OK;
 }
 
+env_status env_peak_probe(int32_t device, env_peak* out) {
+    if (!out) return ENV_E_ARG;
+    int dev = device;
+    if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return ENV_E_DEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return ENV_E_DEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return ENV_E_DEVICE;
+    DeviceGuard g(dev);
+    double ms[3] = {0.0, 0.0, 0.0};
+    if (run_peak_probe(ms) != 0) return ENV_E_DEVICE;
+    const double ops = double(peak_probe_lane_ops());
+    out->fp32_fma_tflops = 2.0 * ops / (ms[0] * 1e-3) / 1e12;
+    out->fp64_fma_tflops = 2.0 * ops / (ms[1] * 1e-3) / 1e12;
+    out->rsq_f32_per_s = ops / (ms[2] * 1e-3);
+    for (int k = 0; k < 3; ++k) out->ms[k] = ms[k];
+    return ENV_OK;
+}
+
 env_status env_potential_export_pairs(const env_potential* h, int64_t cap, int32_t* L,
                                       int32_t* group, double* center, double* p, double* D) {
     if (!h) return ENV_E_ARG;

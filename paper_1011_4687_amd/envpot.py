@@ -60,6 +60,11 @@ class env_options(ctypes.Structure):
                 ("flags", c_uint32), ("reserved", c_int32 * 3)]
 
 
+class env_peak(ctypes.Structure):
+    _fields_ = [("fp32_fma_tflops", c_double), ("fp64_fma_tflops", c_double),
+                ("rsq_f32_per_s", c_double), ("ms", c_double * 3)]
+
+
 class env_info(ctypes.Structure):
     _fields_ = [("nbf", c_int32), ("n_nuclei", c_int32), ("n_groups", c_int32),
                 ("n_segments", c_int32), ("n_pairs", c_int64), ("n_pairs_by_L", c_int64 * 5),
@@ -131,6 +136,8 @@ def lib():
         L.env_potential_eval_batched.argtypes = [POINTER(c_void_p), c_int32, POINTER(c_void_p),
                                                  POINTER(c_int64), POINTER(c_void_p), c_void_p]
         L.env_potential_eval_batched.restype = c_int32
+        L.env_peak_probe.argtypes = [c_int32, POINTER(env_peak)]
+        L.env_peak_probe.restype = c_int32
         L.env_potential_info.argtypes = [c_void_p, POINTER(env_info)]
         L.env_potential_info.restype = c_int32
         L.env_potential_export_pairs.argtypes = [c_void_p, c_int64, POINTER(c_int32),
@@ -257,6 +264,16 @@ def env_batch_get_stats(batch: int) -> dict:
 def env_batch_destroy(batch: int) -> None:
     if batch:
         lib().env_batch_destroy(c_void_p(batch))
+
+
+def peak_probe(device: int = -1) -> dict:
+    """Vector-ALU rates the device sustains (independent FMA / rsq streams)."""
+    r = env_peak()
+    st = lib().env_peak_probe(int(device), ctypes.byref(r))
+    if st != ENV_OK:
+        raise EnvError(st, "env_peak_probe")
+    return {"fp32_fma_tflops": r.fp32_fma_tflops, "fp64_fma_tflops": r.fp64_fma_tflops,
+            "rsq_f32_per_s": r.rsq_f32_per_s, "ms": list(r.ms)}
 
 
 def env_potential_info(handle: int) -> env_info:
