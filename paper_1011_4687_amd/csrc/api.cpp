@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "handle.h"
+#include "probe.h"
 
 using namespace envpot;
 

@@ -183,9 +183,4 @@ int launch_persistent(const BatchArgs& b, int grid, int precision, int np, void*
 int launch_sum_multi(const SumDesc* d, int n_desc, int64_t max_n, void* stream);
 int persistent_grid(int precision, int np, int cu_count);
 
-// Peak probes (probe.hip): times of independent v_fma_f32, v_fma_f64 and
-// v_rsq_f32 streams (ms_out[0..2]); lane operations per probe.
-int run_peak_probe(double* ms_out);
-int64_t peak_probe_lane_ops();
-
 }  // namespace envpot

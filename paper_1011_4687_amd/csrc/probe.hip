@@ -4,7 +4,7 @@
 // saturate issue) and writes one value per lane, so nothing is optimised away.
 #include <hip/hip_runtime.h>
 
-#include "envpot_internal.h"
+#include "probe.h"
 
 namespace envpot {
 namespace {
