@@ -22,9 +22,14 @@
 //   Hermite density (hermite_gen.h),
 //   FP32 sums over tiles of kTile pairs, promoted to FP64 per tile.
 // The nuclear term and the per-fragment (nuclear - electronic) sums are FP64.
+// Pairs whose two shells sit on one atom share that atom as product centre;
+// their far fields are merged per atom and radius band into one multipole
+// ("cluster"), evaluated once per wave while no point is inside its radius.
 // With a split factor S > 1 the pair list is cut into S cost-balanced ranges
 // (grid dimension y) whose FP64 partials a second kernel adds in fixed order,
-// so results are bitwise reproducible.
+// so results are bitwise reproducible.  The point kernels ask for four waves
+// per SIMD (128 VGPRs): the long-lived per-point state then spills to scratch
+// once per segment, which costs less than the latency a third wave hides.
 #include <hip/hip_runtime.h>
 
 #include "envpot_internal.h"
@@ -549,8 +554,8 @@ __device__ __forceinline__ void block_work(const EvalArgs& a, int64_t pblock, in
 
 // Stage the FP32 Boys table into LDS (one copy per workgroup; the near
 // field gathers from it by per-lane row).  The FP64 table is read through
-// the caches: at 45 KB per workgroup it would cost a quarter of the FP64
-// kernel's occupancy, which measured slower.
+// the caches: staged in LDS (45 KB, or 26 KB on a coarser grid with more
+// Taylor terms) it measured slower or no faster.
 template <bool F64>
 __device__ __forceinline__ void load_boys_lds(const void* boys, int rows32, float* tab32) {
     if constexpr (!F64) {
