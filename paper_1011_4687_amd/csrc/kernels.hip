@@ -252,16 +252,40 @@ __device__ __forceinline__ void pairs_f32(const GLB uint32_t* __restrict__ rec, 
                 if constexpr (kPipelined<L, float>) cur = nxt;
             }
             if (i >= i1) break;
-            // pair i has some point of the wave inside its far-field radius
+            // pair i has some point of the wave inside its far-field radius:
+            // far form for the other points, then the near points of every
+            // lane one per pass (a pass per near point of the busiest lane,
+            // not one per point slot that has a near point in some lane)
             const GLB uint32_t* r = rec + (int64_t)i * RW;
+            uint32_t nm = 0;
 #pragma unroll
             for (int k = 0; k < NP; ++k) {
                 if (r2[k] < cur.r2far) {
-                    tile[k] += near_f32<L>(r, X[k], Y[k], Z[k], r2[k], tab);
+                    nm |= 1u << k;
                 } else {
                     const float ri = rsqrt_refined(r2[k]);
                     const float w = ri * ri;
                     tile[k] = __builtin_fmaf(ri, far_value<L, float>(cur.h, X[k], Y[k], Z[k], w), tile[k]);
+                }
+            }
+            while (__builtin_amdgcn_ballot_w64(nm != 0) != 0) {
+                if (nm != 0) {
+                    const int kn = __builtin_ctz(nm);
+                    nm &= nm - 1;
+                    float xn = X[0], yn = Y[0], zn = Z[0], qn = r2[0];
+#pragma unroll
+                    for (int k = 1; k < NP; ++k) {
+                        if (kn == k) {
+                            xn = X[k];
+                            yn = Y[k];
+                            zn = Z[k];
+                            qn = r2[k];
+                        }
+                    }
+                    const float v = near_f32<L>(r, xn, yn, zn, qn, tab);
+#pragma unroll
+                    for (int k = 0; k < NP; ++k)
+                        if (kn == k) tile[k] += v;
                 }
             }
             if constexpr (kPipelined<L, float>) cur = nxt;
