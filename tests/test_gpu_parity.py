@@ -124,3 +124,36 @@ def test_clusters_match_pairwise(precision):
         assert np.abs(Vm[idx] - Vo).max() <= FP32_TOL
     Em.close()
     Ep.close()
+
+
+@pytest.mark.parametrize("precision,shapes", [
+    ("fp32c", [(4, 0), (4, 3), (4, 6), (2, 5), (1, 2)]),
+    ("fp64", [(2, 0), (2, 6), (1, 3)]),
+])
+def test_launch_shapes_agree(precision, shapes, monkeypatch):
+    """Every points-per-lane / pair-split shape gives the same potential up to
+    rounding: splits cut ordinary and cluster segments at different places,
+    and each shape is bitwise reproducible."""
+    from oracle import oracle as O
+    from paper_1011_4687_amd.envpot import Environment
+    print(f"[parity] shapes {precision}", flush=True)
+    env, pts, P, _ = workload_scaled("mid", 8192)
+    shells = [(s.atom, s.l, s.exponents, s.coefs) for s in env.shells]
+    E = Environment(env.xyz, env.Z, env.fragment, shells, P, precision=precision)
+    ref = _gpu(E, pts)
+    idx = sample_indices(len(pts), 6)
+    Vo, _, _, A = O.potential(env, pts[idx], P=P, screen=precision == "fp64")
+    for np_, k in shapes:
+        monkeypatch.setenv("ENVPOT_NP", str(np_))
+        monkeypatch.setenv("ENVPOT_SPLIT_LOG2", str(k))
+        V1 = _gpu(E, pts)
+        V2 = _gpu(E, pts)
+        assert np.array_equal(V1, V2), (np_, k)
+        d = np.abs(V1 - ref).max()
+        if precision == "fp64":
+            assert d <= 1e-11, (np_, k, d)
+            assert np.all(np.abs(V1[idx] - Vo) <= FP64_REL * A), (np_, k)
+        else:
+            assert d <= 2e-6, (np_, k, d)
+            assert np.abs(V1[idx] - Vo).max() <= FP32_TOL, (np_, k)
+    E.close()
