@@ -47,12 +47,12 @@ def test_tiny_all_points(precision):
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
 def test_mid_full_size_sampled(precision):
     """The mid workload at its full size (131072 points, the benchmark's
-    launch configuration); the oracle checks 40 sampled points."""
+    launch configuration); the oracle checks 256 sampled points."""
     from oracle import oracle as O
     print(f"[parity] mid {precision}", flush=True)
     E, env, pts, P = _env("mid", precision)
     V = _gpu(E, pts)
-    idx = sample_indices(len(pts), 40)
+    idx = sample_indices(len(pts), 256)
     if precision == "fp64":
         Vo, _, _, A = O.potential(env, pts[idx], P=P, screen=True)
         assert np.all(np.abs(V[idx] - Vo) <= FP64_REL * A), (np.abs(V[idx] - Vo) / A).max()
