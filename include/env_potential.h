@@ -344,6 +344,48 @@ env_status env_surrogate_get_info(const env_surrogate* s, env_surrogate_info* in
 
 void env_surrogate_destroy(env_surrogate* s);
 
+/* ------------------------------------------------------------------------
+ * The paper's own form of the environment (Sec. II.B, Eq. ElectrostaticField;
+ * Sec. III): nuclei plus the electron density given on M cells, each cell a
+ * point charge q_m = rho(r_m) h^3 (electron count).  The library returns
+ *     V(r) = sum_A Z_A / |r - R_A| - sum_m q_m / |r - r_m|,   U_ES = -V,
+ * the same sign convention as env_potential_eval.
+ * ------------------------------------------------------------------------ */
+typedef struct env_cells env_cells;
+
+/* Upload nuclei (fragment ids ignored; Z = 0 allowed) and cells (host, M x 4
+ * row-major: x, y, z, q; bohr and electrons) once.  Options: precision
+ * (ENV_PREC_FP64 or ENV_PREC_FP32C) and device; flags and the screening
+ * threshold are ignored.  The inputs are copied.
+ * Errors: ENV_E_ARG (NULL with a count > 0, negative counts, non-finite
+ * values, M > 2^31 - 1), ENV_E_DEVICE (no gfx950 device), ENV_E_NOMEM. */
+env_status env_cells_create(const env_nucleus* nuclei, int32_t n_nuclei, const double* cells,
+                            int64_t n_cells, const env_options* options, env_cells** out);
+
+/* V at n device points (n x 3 float64, row-major) into out (device, n
+ * float64), asynchronous on `stream`.  Every point against every cell and
+ * nucleus (a point on a nucleus gives +inf, a point on a cell a non-finite
+ * value).  n = 0 is a no-op.
+ * Errors: ENV_E_ARG, ENV_E_DEVICE, ENV_E_NOMEM (split partials). */
+env_status env_cells_eval(env_cells* h, const double* points, int64_t n, double* out,
+                          void* stream);
+
+/* Single-point latency mode, one electron move at a time as in the paper's
+ * QMC loop (Sec. III): V at one device point (3 float64) into out (device, 1
+ * float64), one kernel launch, asynchronous on `stream`.  The whole GPU
+ * shares the M cells; block partial sums are added by the last block to
+ * finish, in fixed order (bitwise reproducible).
+ *   mode 0: as many workgroups as fill the device;
+ *   mode 1: the paper's decomposition, 120 blocks x 256 threads, each thread
+ *           taking every (120 x 256)-th cell (Sec. III, Eq. coalease).
+ * Calls on one handle must not overlap (they share the block-partial
+ * buffer): issue them on one stream.
+ * Errors: ENV_E_ARG (NULL, bad mode), ENV_E_DEVICE. */
+env_status env_cells_eval_single(env_cells* h, const double* point, double* out, int32_t mode,
+                                 void* stream);
+
+void env_cells_destroy(env_cells* h);
+
 void env_potential_destroy(env_potential* h);
 
 const char* env_status_string(env_status s);

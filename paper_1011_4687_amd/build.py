@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libenvpot.so")
 
 SOURCES = ["kernels.hip", "pairlist.cpp", "layout.cpp", "api.cpp", "batch.cpp", "surrogate.hip", "surrogate.cpp",
-           "probe.hip"]
+           "probe.hip", "cells.hip", "cells.cpp"]
 
 HIP_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -1,0 +1,198 @@
+// C ABI of the cell-sum environment (the paper's own form of the field:
+// nuclei plus point-charge cells, Sec. II.B, Eq. ElectrostaticField).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "cells_internal.h"
+#include "envpot_internal.h"
+#include "handle.h"
+
+struct env_cells {
+    int device = -1;
+    int precision = ENV_PREC_FP32C;
+    int cu_count = 256;
+    int64_t m = 0;                 // cells
+    int32_t n_nuc = 0;
+    uint32_t* d_cells = nullptr;   // records, kCellWords each
+    double* d_nuc = nullptr;
+    int32_t* d_split = nullptr;    // split tables for S = 1, 2, ..., 64
+    int64_t split_off[envpot::kMaxSplitLog2 + 1] = {};
+    double* d_part = nullptr;      // single-point mode: one partial per workgroup
+    unsigned int* d_ticket = nullptr;
+    int one_grid = 512;            // workgroups of single-point mode 0
+};
+
+namespace {
+
+using envpot::DeviceGuard;
+
+void free_cells(env_cells* h) {
+    DeviceGuard g(h->device);
+    (void)hipFree(h->d_cells);
+    (void)hipFree(h->d_nuc);
+    (void)hipFree(h->d_split);
+    (void)hipFree(h->d_part);
+    (void)hipFree(h->d_ticket);
+}
+
+template <typename T>
+env_status to_device(const std::vector<T>& v, T** dst) {
+    const size_t nb = std::max<size_t>(v.size(), 1) * sizeof(T);
+    if (hipMalloc(reinterpret_cast<void**>(dst), nb) != hipSuccess) return ENV_E_NOMEM;
+    if (!v.empty() && hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+        return ENV_E_DEVICE;
+    return ENV_OK;
+}
+
+// Points per lane and cell-split factor of a batched evaluation: enough
+// waves in flight (about 24 per SIMD) over the whole launch.
+void cells_shape(const env_cells* h, int64_t n, int* np, int* klog) {
+    *np = h->precision == ENV_PREC_FP64 ? 2 : 4;
+    const int64_t waves = (n + 64 * *np - 1) / (64 * *np);
+    const int64_t want = int64_t(h->cu_count) * 4 * 24;
+    int k = 0;
+    while (k < envpot::kMaxSplitLog2 && waves * (int64_t(1) << k) < want && (h->m >> (k + 1)) >= 64) ++k;
+    *klog = k;
+}
+
+}  // namespace
+
+extern "C" {
+
+env_status env_cells_create(const env_nucleus* nuclei, int32_t n_nuclei, const double* cells,
+                            int64_t n_cells, const env_options* options, env_cells** out) {
+    if (!out) return ENV_E_ARG;
+    *out = nullptr;
+    if (n_nuclei < 0 || n_cells < 0 || n_cells > int64_t(INT32_MAX)) return ENV_E_ARG;
+    if ((n_nuclei > 0 && !nuclei) || (n_cells > 0 && !cells)) return ENV_E_ARG;
+    env_options opt;
+    if (options) opt = *options;
+    else env_options_default(&opt);
+    if (opt.precision != ENV_PREC_FP64 && opt.precision != ENV_PREC_FP32C) return ENV_E_ARG;
+    for (int32_t a = 0; a < n_nuclei; ++a)
+        for (int c = 0; c < 3; ++c)
+            if (!std::isfinite(nuclei[a].xyz[c]) || !std::isfinite(nuclei[a].Z)) return ENV_E_ARG;
+    for (int64_t m = 0; m < 4 * n_cells; ++m)
+        if (!std::isfinite(cells[m])) return ENV_E_ARG;
+    int device = opt.device;
+    if (device < 0 && hipGetDevice(&device) != hipSuccess) return ENV_E_DEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return ENV_E_DEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return ENV_E_DEVICE;
+
+    env_cells* h = new (std::nothrow) env_cells;
+    if (!h) return ENV_E_NOMEM;
+    h->device = device;
+    h->precision = opt.precision;
+    h->cu_count = prop.multiProcessorCount;
+    h->m = n_cells;
+    h->one_grid = 2 * prop.multiProcessorCount;
+    env_status st = ENV_OK;
+    try {
+        // records
+        std::vector<uint32_t> rec(size_t(std::max<int64_t>(n_cells, 1)) * envpot::kCellWords, 0u);
+        for (int64_t m = 0; m < n_cells; ++m) {
+            uint32_t* r = &rec[size_t(m) * envpot::kCellWords];
+            double* d = reinterpret_cast<double*>(r);
+            d[0] = cells[4 * m];
+            d[1] = cells[4 * m + 1];
+            d[2] = cells[4 * m + 2];
+            if (h->precision == ENV_PREC_FP64) d[3] = cells[4 * m + 3];
+            else reinterpret_cast<float*>(r)[6] = float(cells[4 * m + 3]);
+        }
+        std::vector<double> nuc;
+        for (int32_t a = 0; a < n_nuclei; ++a) {
+            if (nuclei[a].Z == 0.0) continue;
+            nuc.insert(nuc.end(), {nuclei[a].xyz[0], nuclei[a].xyz[1], nuclei[a].xyz[2], nuclei[a].Z});
+        }
+        h->n_nuc = int32_t(nuc.size() / 4);
+        // split tables: S equal cell ranges
+        std::vector<int32_t> split;
+        for (int k = 0; k <= envpot::kMaxSplitLog2; ++k) {
+            const int S = 1 << k;
+            h->split_off[k] = int64_t(split.size());
+            for (int s = 0; s <= S; ++s) split.push_back(int32_t((n_cells * s) / S));
+        }
+        DeviceGuard g(device);
+        st = to_device(rec, &h->d_cells);
+        if (st == ENV_OK) st = to_device(nuc, &h->d_nuc);
+        if (st == ENV_OK) st = to_device(split, &h->d_split);
+        if (st == ENV_OK && hipMalloc(reinterpret_cast<void**>(&h->d_part),
+                                      size_t(std::max(h->one_grid, envpot::kCellsPaperGrid)) * sizeof(double)) !=
+                                hipSuccess)
+            st = ENV_E_NOMEM;
+        if (st == ENV_OK && hipMalloc(reinterpret_cast<void**>(&h->d_ticket), sizeof(unsigned int)) != hipSuccess)
+            st = ENV_E_NOMEM;
+        if (st == ENV_OK && hipMemset(h->d_ticket, 0, sizeof(unsigned int)) != hipSuccess) st = ENV_E_DEVICE;
+    } catch (const std::bad_alloc&) {
+        st = ENV_E_NOMEM;
+    }
+    if (st != ENV_OK) {
+        free_cells(h);
+        delete h;
+        return st;
+    }
+    *out = h;
+    return ENV_OK;
+}
+
+env_status env_cells_eval(env_cells* h, const double* points, int64_t n, double* out, void* stream) {
+    if (!h || n < 0) return ENV_E_ARG;
+    if (n == 0) return ENV_OK;
+    if (!points || !out) return ENV_E_ARG;
+    DeviceGuard g(h->device);
+    int np, k;
+    cells_shape(h, n, &np, &k);
+    const int S = 1 << k;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    envpot::CellArgs a{};
+    a.pts = points;
+    a.n = n;
+    a.cells = h->d_cells;
+    a.split = h->d_split + h->split_off[k];
+    a.nuc = h->d_nuc;
+    a.n_nuc = h->n_nuc;
+    if (S == 1) {
+        a.out = out;
+        return envpot::launch_cells(a, 1, h->precision, np, stream) == 0 ? ENV_OK : ENV_E_DEVICE;
+    }
+    double* part = nullptr;
+    if (hipMallocAsync(reinterpret_cast<void**>(&part), size_t(S) * size_t(n) * sizeof(double), st) !=
+        hipSuccess)
+        return ENV_E_NOMEM;
+    a.out = part;
+    int rc = envpot::launch_cells(a, S, h->precision, np, stream);
+    if (rc == 0) rc = envpot::launch_sum_splits(part, S, n, out, stream);
+    (void)hipFreeAsync(part, st);
+    return rc == 0 ? ENV_OK : ENV_E_DEVICE;
+}
+
+env_status env_cells_eval_single(env_cells* h, const double* point, double* out, int32_t mode,
+                                 void* stream) {
+    if (!h || !point || !out || (mode != 0 && mode != 1)) return ENV_E_ARG;
+    DeviceGuard g(h->device);
+    envpot::CellOneArgs a{};
+    a.pt = point;
+    a.cells = h->d_cells;
+    a.m = h->m;
+    a.nuc = h->d_nuc;
+    a.n_nuc = h->n_nuc;
+    a.part = h->d_part;
+    a.ticket = h->d_ticket;
+    a.out = out;
+    const int grid = mode == 0 ? h->one_grid : envpot::kCellsPaperGrid;
+    return envpot::launch_cells_one(a, grid, h->precision, stream) == 0 ? ENV_OK : ENV_E_DEVICE;
+}
+
+void env_cells_destroy(env_cells* h) {
+    if (!h) return;
+    free_cells(h);
+    delete h;
+}
+
+}  // extern "C"

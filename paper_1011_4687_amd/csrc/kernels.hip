@@ -32,6 +32,7 @@
 // once per segment, which costs less than the latency a third wave hides.
 #include <hip/hip_runtime.h>
 
+#include "device_math.h"
 #include "envpot_internal.h"
 #include "hermite_gen.h"
 
@@ -40,25 +41,6 @@ namespace {
 
 constexpr int kTile = 8;  // pairs per FP32 partial sum
 
-// Address spaces.  The pair records, segments, nuclei and Boys table are
-// never written while a kernel runs, so they are read through the constant
-// address space: wave-uniform loads through it become scalar loads even in
-// the persistent kernel, whose work-queue atomics and output stores would
-// otherwise count as possible clobbers.  Points are read through the global
-// address space (per-lane vector loads).
-#define GLB __attribute__((address_space(4)))
-#define PTS __attribute__((address_space(1)))
-
-template <typename T>
-__device__ __forceinline__ const GLB T* glb(const T* p) {
-    return (const GLB T*)p;
-}
-
-template <typename T>
-__device__ __forceinline__ const PTS T* gpts(const T* p) {
-    return (const PTS T*)p;
-}
-
 template <int L, typename T>
 __device__ __forceinline__ T hermite_dot(const T* G, T X, T Y, T Z, const T* __restrict__ D) {
     if constexpr (L == 0) return hermite_dot_L0<T>(G, X, Y, Z, D);
@@ -66,24 +48,6 @@ __device__ __forceinline__ T hermite_dot(const T* G, T X, T Y, T Z, const T* __r
     else if constexpr (L == 2) return hermite_dot_L2<T>(G, X, Y, Z, D);
     else if constexpr (L == 3) return hermite_dot_L3<T>(G, X, Y, Z, D);
     else return hermite_dot_L4<T>(G, X, Y, Z, D);
-}
-
-// 1/sqrt(x) from v_rsq_f32 plus one Newton correction y + y (1 - x y^2) / 2.
-__device__ __forceinline__ float rsqrt_refined(float x) {
-    const float y = __builtin_amdgcn_rsqf(x);
-    const float h = x * y;
-    const float e = __builtin_fmaf(-h, y, 1.0f);
-    return __builtin_fmaf(0.5f * e, y, y);
-}
-
-// 1/sqrt(x) for finite x > 0 (far-field distances): v_rsq_f64 plus the
-// second-order correction y (1 + e/2 + 3e^2/8), e = 1 - x y^2, of the series
-// of (1 - e)^(-1/2).
-__device__ __forceinline__ double rsqrt_far(double x) {
-    const double y = __builtin_amdgcn_rsq(x);
-    const double h = x * y;
-    const double e = __builtin_fma(-h, y, 1.0);
-    return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
 }
 
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }

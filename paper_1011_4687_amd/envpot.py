@@ -177,6 +177,15 @@ def lib():
         L.env_surrogate_get_info.restype = c_int32
         L.env_surrogate_destroy.argtypes = [c_void_p]
         L.env_surrogate_destroy.restype = None
+        L.env_cells_create.argtypes = [POINTER(env_nucleus), c_int32, POINTER(c_double), c_int64,
+                                       POINTER(env_options), POINTER(c_void_p)]
+        L.env_cells_create.restype = c_int32
+        L.env_cells_eval.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]
+        L.env_cells_eval.restype = c_int32
+        L.env_cells_eval_single.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]
+        L.env_cells_eval_single.restype = c_int32
+        L.env_cells_destroy.argtypes = [c_void_p]
+        L.env_cells_destroy.restype = None
         _lib = L
     return _lib
 
@@ -563,6 +572,82 @@ class Surrogate:
     def close(self):
         if self.handle:
             lib().env_surrogate_destroy(c_void_p(self.handle))
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class CellEnvironment:
+    """The paper's own form of the environment: nuclei plus M point-charge
+    cells (xyz (K,3), Z (K,), cells (M,4): x, y, z, electron count)."""
+
+    def __init__(self, xyz, Z, cells, precision: str = "fp32c", device: int = -1):
+        self.handle = 0
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+        K = xyz.shape[0]
+        Z = np.ascontiguousarray(Z, dtype=np.float64).reshape(K)
+        nuc = (env_nucleus * max(K, 1))()
+        for a in range(K):
+            nuc[a].xyz[0], nuc[a].xyz[1], nuc[a].xyz[2] = xyz[a]
+            nuc[a].Z = Z[a]
+        c = np.ascontiguousarray(cells, dtype=np.float64).reshape(-1, 4)
+        opt = env_options_default()
+        opt.precision = PRECISIONS[precision]
+        opt.device = int(device)
+        h = c_void_p()
+        _check(lib().env_cells_create(nuc, K, _dp(c), c.shape[0], ctypes.byref(opt), ctypes.byref(h)),
+               "env_cells_create")
+        self.handle = h.value
+        self.precision = precision
+        self.n_cells = c.shape[0]
+
+    @classmethod
+    def from_synth(cls, env, **kw) -> "CellEnvironment":
+        return cls(env.xyz, env.Z, env.cells, **kw)
+
+    def eval(self, points, out=None, stream=None):
+        """V at a (n,3) float64 CUDA tensor; returns a (n,) tensor."""
+        import torch
+        if not (isinstance(points, torch.Tensor) and points.is_cuda):
+            raise TypeError("points must be a torch CUDA tensor")
+        if points.dtype != torch.float64 or points.dim() != 2 or points.shape[1] != 3:
+            raise TypeError("points must be float64 of shape (n, 3)")
+        points = points.contiguous()
+        n = points.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=points.device)
+        if out.dtype != torch.float64 or out.numel() != n or not out.is_contiguous():
+            raise TypeError("out must be a contiguous float64 tensor of n elements")
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        _check(lib().env_cells_eval(c_void_p(self.handle), c_void_p(points.data_ptr()), n,
+                                    c_void_p(out.data_ptr()), c_void_p(stream.cuda_stream)),
+               "env_cells_eval")
+        return out
+
+    def eval_single(self, point, out, mode: int = 0, stream=None):
+        """V at one device point (3 float64) into out (1 float64, device):
+        mode 0 fills the GPU, mode 1 is the paper's 120 x 256 decomposition."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        if point.dtype != torch.float64 or point.numel() != 3 or not point.is_cuda:
+            raise TypeError("point must be 3 float64 values on the device")
+        if out.dtype != torch.float64 or out.numel() < 1 or not out.is_cuda:
+            raise TypeError("out must be a float64 device tensor")
+        _check(lib().env_cells_eval_single(c_void_p(self.handle), c_void_p(point.data_ptr()),
+                                           c_void_p(out.data_ptr()), int(mode),
+                                           c_void_p(stream.cuda_stream)),
+               "env_cells_eval_single")
+        return out
+
+    def close(self):
+        if self.handle:
+            lib().env_cells_destroy(c_void_p(self.handle))
             self.handle = 0
 
     def __del__(self):

@@ -330,6 +330,62 @@ def surrogate_sets(seed: int = 1004, n_train: int = 2_000_000,
     return train, infer, outer
 
 
+@dataclasses.dataclass
+class CellEnvironment:
+    """The paper's own form of the environment (Sec. II.B, Eq.
+    ElectrostaticField): nuclei plus the electron density given on cells,
+    each cell a point charge q_m = rho(r_m) h^3 (electron count, >= 0)."""
+    xyz: np.ndarray      # (K, 3) nuclei, bohr
+    Z: np.ndarray        # (K,)
+    cells: np.ndarray    # (M, 4): x, y, z, q_m
+    h: float             # cell edge, bohr
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.cells.shape[0])
+
+
+def cell_workload(seed: int = 1006, n_points: int = 131072, n_atoms: int = 19,
+                  h: float = 0.194, r_cut: float = 3.0, r_points: float = 3.0):
+    """(CellEnvironment, points) shaped like the paper's benchmark (Sec. III:
+    19 MM atoms, M = 268,782 cells, QMC electrons in the QM fragment).
+
+    Atoms: uniform in the shell 6.5 <= |R| <= 11 bohr, at least 1.8 bohr
+    apart, Z uniform in {1, 6, 7, 8}.  Cells: the points of the cubic grid of
+    edge h (origin on a grid point) within r_cut of some atom; each cell
+    carries a sum of atom-centred Gaussian profiles Z_A exp(-b_A d^2) with b_A
+    uniform in [0.6, 1.6] 1/bohr^2, scaled so that the cells hold as many
+    electrons as the nuclei carry charge (a neutral environment).  Points:
+    uniform in the r_points sphere, so every point is at least 0.5 bohr from
+    every cell.  Draw order: atoms -> Z -> b -> points."""
+    rng = _rng(seed)
+    pos = []
+    while len(pos) < n_atoms:
+        u = rng.uniform(-1.0, 1.0, 3)
+        r = np.linalg.norm(u)
+        if r == 0.0 or r > 1.0:
+            continue
+        c = u / r * rng.uniform(6.5, 11.0)
+        if all(np.linalg.norm(c - q) >= 1.8 for q in pos):
+            pos.append(c)
+    xyz = np.array(pos)
+    Z = Z_CHOICES[rng.integers(0, len(Z_CHOICES), n_atoms)].astype(np.float64)
+    b = rng.uniform(0.6, 1.6, n_atoms)
+    lo = np.floor((xyz.min(axis=0) - r_cut) / h) * h
+    hi = np.ceil((xyz.max(axis=0) + r_cut) / h) * h
+    axes = [np.arange(lo[k], hi[k] + 0.5 * h, h) for k in range(3)]
+    gx, gy, gz = np.meshgrid(*axes, indexing="ij")
+    grid = np.stack([gx.ravel(), gy.ravel(), gz.ravel()], axis=1)
+    d2 = ((grid[:, None, :] - xyz[None, :, :]) ** 2).sum(axis=2)
+    keep = (d2 <= r_cut * r_cut).any(axis=1)
+    grid, d2 = grid[keep], d2[keep]
+    w = (Z[None, :] * np.exp(-b[None, :] * d2)).sum(axis=1)
+    q = w * (Z.sum() / w.sum())
+    cells = np.concatenate([grid, q[:, None]], axis=1)
+    pts = points_in_ball(rng, n_points, r_points)
+    return CellEnvironment(xyz, Z, cells, h), pts
+
+
 def digest(*arrays: np.ndarray) -> str:
     h = hashlib.sha256()
     for a in arrays:
