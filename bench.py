@@ -71,6 +71,60 @@ def time_path(E, x, out, steps, warmup, torch):
     return wall, float(np.mean(ms))
 
 
+def cells_leg(torch, envpot, synth, steps, warmup):
+    """The paper's own form of the environment: 19 nuclei and 268,398
+    point-charge cells.  Batched throughput (131,072 points per call) and the
+    single-point latency of the paper's QMC loop (one electron position per
+    call), for the full-device decomposition and the paper's 120 x 256 one."""
+    env, pts = synth.cell_workload()
+    x = torch.from_numpy(pts).cuda()
+    n, m = len(pts), env.n_cells
+    rep = {"workload": f"cells: {len(env.Z)} nuclei, {m} point-charge cells (h = {env.h} bohr), "
+                       f"{n} points in the 3-bohr QM sphere"}
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for prec in ("fp32c", "fp64"):
+            E = envpot.CellEnvironment.from_synth(env, precision=prec)
+            out = torch.empty(n, dtype=torch.float64, device="cuda")
+            wall, ms = time_path(E, x, out, steps, warmup, torch)
+            r = {"point_cell_evals_per_s": n * m / (ms * 1e-3), "ms_per_step": ms}
+            # single point: back-to-back launches on the device, then the
+            # host round trip of the paper's loop (position in, value out)
+            one = torch.empty(1, dtype=torch.float64, device="cuda")
+            host = torch.from_numpy(np.ascontiguousarray(pts[:256]))
+            for mode in (0, 1):
+                for j in range(32):
+                    E.eval_single(x[j], one, mode=mode)
+                k = 2000
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(side)
+                for j in range(k):
+                    E.eval_single(x[j % n], one, mode=mode)
+                e1.record(side)
+                side.synchronize()
+                dev_us = e0.elapsed_time(e1) * 1e3 / k
+                p1 = torch.empty(3, dtype=torch.float64, device="cuda")
+                t0 = time.perf_counter()
+                kk = 256
+                for j in range(kk):
+                    p1.copy_(host[j])
+                    E.eval_single(p1, one, mode=mode)
+                    one.item()
+                rt_us = (time.perf_counter() - t0) * 1e6 / kk
+                r[f"single_point_mode{mode}_us"] = dev_us
+                r[f"single_point_mode{mode}_roundtrip_us"] = rt_us
+            rep[prec] = r
+            log(f"[bench] cells {prec}: {ms:.3f} ms per {n} points ({r['point_cell_evals_per_s']:.4g} "
+                f"point-cell/s); one point: {r['single_point_mode0_us']:.1f} us (full device), "
+                f"{r['single_point_mode1_us']:.1f} us (120 x 256), round trip "
+                f"{r['single_point_mode0_roundtrip_us']:.1f} / {r['single_point_mode1_roundtrip_us']:.1f} us")
+            E.close()
+    torch.cuda.synchronize()
+    return rep
+
+
 def surrogate_leg(torch, envpot, synth):
     """Learned surrogate on its own workload: 1000 atoms (box 68.4 bohr), the
     network covering the 6-bohr region, trained on 2M samples of the exact FP64
@@ -144,6 +198,8 @@ def main():
                     help="points of the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--paths", default="fp32c,fp64")
+    ap.add_argument("--no-cells", action="store_true",
+                    help="skip the cell-sum leg (the paper's own form of the environment)")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the learned-surrogate leg (1000-atom surrogate workload)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -189,6 +245,9 @@ def main():
         outs[prec] = out.cpu().numpy()
         log(f"[bench] {prec}: {ms:.3f} ms/step, {paths[prec]['point_pairs_per_s']:.4g} pp/s")
         E.close()
+
+    if not args.no_cells:
+        paths["cells"] = cells_leg(torch, envpot, synth, args.steps, args.warmup)
 
     sur = None
     if not args.no_surrogate and "fp32c" in args.paths.split(","):

@@ -375,7 +375,9 @@ env_status env_cells_eval(env_cells* h, const double* points, int64_t n, double*
  * float64), one kernel launch, asynchronous on `stream`.  The whole GPU
  * shares the M cells; block partial sums are added by the last block to
  * finish, in fixed order (bitwise reproducible).
- *   mode 0: as many workgroups as fill the device;
+ *   mode 0: one workgroup of 256 threads per two compute units (the
+ *           measured latency optimum: more workgroups cost more in launch
+ *           and in the final sum than they save);
  *   mode 1: the paper's decomposition, 120 blocks x 256 threads, each thread
  *           taking every (120 x 256)-th cell (Sec. III, Eq. coalease).
  * Calls on one handle must not overlap (they share the block-partial

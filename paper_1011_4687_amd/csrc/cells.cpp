@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -24,7 +25,7 @@ struct env_cells {
     int64_t split_off[envpot::kMaxSplitLog2 + 1] = {};
     double* d_part = nullptr;      // single-point mode: one partial per workgroup
     unsigned int* d_ticket = nullptr;
-    int one_grid = 512;            // workgroups of single-point mode 0
+    int one_grid = 128;            // workgroups of single-point mode 0
 };
 
 namespace {
@@ -91,7 +92,11 @@ env_status env_cells_create(const env_nucleus* nuclei, int32_t n_nuclei, const d
     h->precision = opt.precision;
     h->cu_count = prop.multiProcessorCount;
     h->m = n_cells;
-    h->one_grid = 2 * prop.multiProcessorCount;
+    h->one_grid = std::max(1, prop.multiProcessorCount / 2);  // latency optimum (measured)
+    if (const char* e = std::getenv("ENVPOT_CELLS_GRID")) {  // tuning override
+        const int g = std::atoi(e);
+        if (g >= 1 && g <= 4 * prop.multiProcessorCount) h->one_grid = g;
+    }
     env_status st = ENV_OK;
     try {
         // records

@@ -152,28 +152,39 @@ __global__ __launch_bounds__(kCellBlock) void k_cells_one(CellOneArgs a) {
     const double px = pt[0], py = pt[1], pz = pt[2];
     const PTS double* __restrict__ cd = gpts(reinterpret_cast<const double*>(a.cells));
     const int64_t stride = (int64_t)gridDim.x * kCellBlock;
+    // each thread takes every stride-th cell; kOneUnroll of them are loaded
+    // before any is used, so their memory latencies overlap
+    constexpr int kOneUnroll = 4;
     double acc = 0.0;
-    if constexpr (F64) {
-        for (int64_t m = (int64_t)blockIdx.x * kCellBlock + threadIdx.x; m < a.m; m += stride) {
-            const PTS double* c = cd + m * (kCellWords / 2);
-            const double X = c[0] - px, Y = c[1] - py, Z = c[2] - pz;
-            acc = __builtin_fma(c[3], rsqrt_far(__builtin_fma(X, X, __builtin_fma(Y, Y, Z * Z))), acc);
+    for (int64_t m0 = (int64_t)blockIdx.x * kCellBlock + threadIdx.x; m0 < a.m; m0 += kOneUnroll * stride) {
+        double cx[kOneUnroll], cy[kOneUnroll], cz[kOneUnroll], cq[kOneUnroll];
+#pragma unroll
+        for (int u = 0; u < kOneUnroll; ++u) {
+            const int64_t m = m0 + u * stride;
+            const bool ok = m < a.m;
+            const PTS double* c = cd + (ok ? m : m0) * (kCellWords / 2);
+            cx[u] = c[0];
+            cy[u] = c[1];
+            cz[u] = c[2];
+            if constexpr (F64) cq[u] = ok ? c[3] : 0.0;
+            else cq[u] = ok ? (double)reinterpret_cast<const PTS float*>(c)[6] : 0.0;
         }
-    } else {
-        float tile = 0.0f;
-        int cnt = 0;
-        for (int64_t m = (int64_t)blockIdx.x * kCellBlock + threadIdx.x; m < a.m; m += stride) {
-            const PTS double* c = cd + m * (kCellWords / 2);
-            const float q = reinterpret_cast<const PTS float*>(c)[6];
-            const float X = (float)(c[0] - px), Y = (float)(c[1] - py), Z = (float)(c[2] - pz);
-            tile = __builtin_fmaf(q, rsqrt_refined(__builtin_fmaf(X, X, __builtin_fmaf(Y, Y, Z * Z))), tile);
-            if (++cnt == kCellTile) {
-                acc += (double)tile;
-                tile = 0.0f;
-                cnt = 0;
+        if constexpr (F64) {
+#pragma unroll
+            for (int u = 0; u < kOneUnroll; ++u) {
+                const double X = cx[u] - px, Y = cy[u] - py, Z = cz[u] - pz;
+                acc = __builtin_fma(cq[u], rsqrt_far(__builtin_fma(X, X, __builtin_fma(Y, Y, Z * Z))), acc);
             }
+        } else {
+            float tile = 0.0f;
+#pragma unroll
+            for (int u = 0; u < kOneUnroll; ++u) {
+                const float X = (float)(cx[u] - px), Y = (float)(cy[u] - py), Z = (float)(cz[u] - pz);
+                tile = __builtin_fmaf((float)cq[u], rsqrt_refined(__builtin_fmaf(X, X, __builtin_fmaf(Y, Y, Z * Z))),
+                                      tile);
+            }
+            acc += (double)tile;
         }
-        acc += (double)tile;
     }
     const double bs = block_sum(acc, sh);
     if (threadIdx.x == 0) {
