@@ -81,6 +81,7 @@ def cells_leg(torch, envpot, synth, steps, warmup):
     n, m = len(pts), env.n_cells
     rep = {"workload": f"cells: {len(env.Z)} nuclei, {m} point-charge cells (h = {env.h} bohr), "
                        f"{n} points in the 3-bohr QM sphere"}
+    values = {}
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -89,6 +90,7 @@ def cells_leg(torch, envpot, synth, steps, warmup):
             out = torch.empty(n, dtype=torch.float64, device="cuda")
             wall, ms = time_path(E, x, out, steps, warmup, torch)
             r = {"point_cell_evals_per_s": n * m / (ms * 1e-3), "ms_per_step": ms}
+            values[prec] = out.cpu().numpy()
             # single point: back-to-back launches on the device, then the
             # host round trip of the paper's loop (position in, value out)
             one = torch.empty(1, dtype=torch.float64, device="cuda")
@@ -122,7 +124,7 @@ def cells_leg(torch, envpot, synth, steps, warmup):
                 f"{r['single_point_mode0_roundtrip_us']:.1f} / {r['single_point_mode1_roundtrip_us']:.1f} us")
             E.close()
     torch.cuda.synchronize()
-    return rep
+    return {"report": rep, "env": env, "points": pts, "values": values}
 
 
 def surrogate_leg(torch, envpot, synth):
@@ -246,8 +248,10 @@ def main():
         log(f"[bench] {prec}: {ms:.3f} ms/step, {paths[prec]['point_pairs_per_s']:.4g} pp/s")
         E.close()
 
+    cells = None
     if not args.no_cells:
-        paths["cells"] = cells_leg(torch, envpot, synth, args.steps, args.warmup)
+        cells = cells_leg(torch, envpot, synth, args.steps, args.warmup)
+        paths["cells"] = cells["report"]
 
     sur = None
     if not args.no_surrogate and "fp32c" in args.paths.split(","):
@@ -354,6 +358,22 @@ def main():
                 err = np.abs(V[sidx] - Vo2)
                 acc[name] = {"max_abs_err": float(err.max()),
                              "rms_err": float(np.sqrt(np.mean(err ** 2))), "n_checked": int(k)}
+        if cells is not None:
+            # the cell-sum oracle, one host core, on a sample of that workload
+            from oracle import cells_oracle as CO
+            cenv, cpts = cells["env"], cells["points"]
+            cidx = np.sort(rng.choice(len(cpts), size=16, replace=False))
+            t0 = time.perf_counter()
+            Vc, _, _, Ac = CO.potential(cenv.xyz, cenv.Z, cenv.cells, cpts[cidx])
+            t_c = time.perf_counter() - t0
+            result["cpu_baseline"]["cells"] = {
+                "value": len(cidx) * cenv.n_cells / t_c, "unit": "point-cell evals/s", "cores": 1,
+                "ms_per_point": t_c * 1e3 / len(cidx),
+                "sample": f"{len(cidx)} of the {len(cpts)} cell-workload points, FP64 cell-sum oracle (numpy)"}
+            for prec, V in cells["values"].items():
+                err = np.abs(V[cidx] - Vc)
+                acc[f"cells_{prec}"] = {"max_abs_err": float(err.max()),
+                                        "max_rel_to_A": float((err / Ac).max()), "n_checked": len(cidx)}
         result["accuracy_vs_oracle"] = acc
         log(f"[bench] oracle {t_or:.1f}s; accuracy {acc}")
 
