@@ -18,6 +18,10 @@
  * The paper's U_ES of Eq. ElectrostaticField is -V (it is the potential energy
  * of an electron; V is the electrostatic potential).
  *
+ * oracle_field gives the field E = -grad V of the same environment (an
+ * extension: the paper uses only the potential), from the derivative of the
+ * Hermite integrals with respect to the point, R_{t+1,u,v} etc.
+ *
  * Every [mu nu | r] is evaluated per Cartesian component pair and per
  * primitive pair by the McMurchie-Davidson scheme (textbook: McMurchie and
  * Davidson 1978; Helgaker, Joergensen, Olsen 2000, Sec. 9.5 and 9.9):
@@ -219,7 +223,7 @@ double oracle_hermite_E(int i, int j, int t, double a, double b, double A, doubl
 
 /* --------------------------------------------- Hermite Coulomb integrals */
 
-#define RDIM (ORACLE_LSUM + 1)
+#define RDIM (ORACLE_LSUM + 2)  /* one order more than V needs: the field */
 #define RIDX(n, t, u, v) ((((n) * RDIM + (t)) * RDIM + (u)) * RDIM + (v))
 
 /* R^n_{tuv}(p, X, Y, Z) for n+t+u+v <= L; returns R^0_{tuv} in out[t][u][v]
@@ -461,6 +465,117 @@ int oracle_potential(int K, const double* xyz, const double* Z, int S,
     (void)nthreads;
 #endif
     for (int64_t i = 0; i < n; ++i) potential_one(&e, &pr, pts + 3 * i, screen, thr, out + 4 * i);
+    release(&e, &pr);
+    return 0;
+}
+
+/* Field at one point, E = -grad V (same input and pair loop as
+ * potential_one).  With X = P - r, the Hermite integrals R_tuv are
+ * derivatives with respect to P, and moving r moves X the other way:
+ *   d/dr_x [a b | r] = -(2 pi / p) sum_tuv E_t E_u E_v R_{t+1,u,v}(p, X),
+ * likewise y (u+1) and z (v+1).  Hence
+ *   E(r) = sum_A Z_A (r - R_A) / |r - R_A|^3
+ *          - sum_{mu nu} P_{mu nu} (2 pi / p) sum_tuv E E E (R_{t+1,u,v}, R_{t,u+1,v}, R_{t,u,v+1}),
+ * which needs R up to total order l_I + l_J + 1.
+ * out[0..2] = E, out[3] = AE = sum_A Z_A / |r - R_A|^2 + sum over terms of
+ * the Euclidean length of each term's vector (the conditioning scale). */
+static void field_one(const oracle_env* e, const prepared* pr, const double* r,
+                      int screen, double thr, double out[4]) {
+    nsum ex = {0, 0}, ey = {0, 0}, ez = {0, 0};
+    double absterms = 0.0;
+    for (int A = 0; A < e->K; ++A) {
+        double dx = r[0] - e->xyz[3 * A], dy = r[1] - e->xyz[3 * A + 1],
+               dz = r[2] - e->xyz[3 * A + 2];
+        double d2 = dx * dx + dy * dy + dz * dz, d = sqrt(d2);
+        double f = e->Z[A] / (d2 * d);
+        nsum_add(&ex, f * dx);
+        nsum_add(&ey, f * dy);
+        nsum_add(&ez, f * dz);
+        absterms += fabs(e->Z[A]) / d2;
+    }
+    double Ex[(ORACLE_LMAX + 1) * (ORACLE_LMAX + 1) * (ORACLE_LSUM + 1)];
+    double Ey[(ORACLE_LMAX + 1) * (ORACLE_LMAX + 1) * (ORACLE_LSUM + 1)];
+    double Ez[(ORACLE_LMAX + 1) * (ORACLE_LMAX + 1) * (ORACLE_LSUM + 1)];
+    double R[RDIM * RDIM * RDIM];
+    for (int k = 0; k < pr->n; ++k) {
+        const shellpair* q = &pr->sp[k];
+        int I = q->I, J = q->J, lI = e->l[I], lJ = e->l[J];
+        const double* A = e->xyz + 3 * e->atom[I];
+        const double* B = e->xyz + 3 * e->atom[J];
+        double RAB2 = (A[0] - B[0]) * (A[0] - B[0]) + (A[1] - B[1]) * (A[1] - B[1]) +
+                      (A[2] - B[2]) * (A[2] - B[2]);
+        int nI = ncart(lI), nJ = ncart(lJ), tw = lI + lJ + 1;
+        for (int pa = 0; pa < e->nprim[I]; ++pa)
+            for (int pb = 0; pb < e->nprim[J]; ++pb) {
+                double a = e->ex[e->poff[I] + pa], b = e->ex[e->poff[J] + pb];
+                double ca = e->co[e->poff[I] + pa], cb = e->co[e->poff[J] + pb];
+                if (screen && screened_out(ca, cb, a, b, RAB2, thr)) continue;
+                double p = a + b;
+                double P[3] = {(a * A[0] + b * B[0]) / p, (a * A[1] + b * B[1]) / p,
+                               (a * A[2] + b * B[2]) / p};
+                hermite_E(lI, lJ, a, b, A[0], B[0], Ex);
+                hermite_E(lI, lJ, a, b, A[1], B[1], Ey);
+                hermite_E(lI, lJ, a, b, A[2], B[2], Ez);
+                oracle_hermite_R(lI + lJ + 1, p, P[0] - r[0], P[1] - r[1], P[2] - r[2], R);
+                double pref = 2.0 * PI / p;
+                for (int ci = 0; ci < nI; ++ci) {
+                    int ei[3];
+                    cart_exps(lI, ci, ei);
+                    double Na = oracle_prim_norm(a, ei[0], ei[1], ei[2]);
+                    for (int cj = 0; cj < nJ; ++cj) {
+                        double Pmn = q->Pblk[ci * nJ + cj];
+                        if (Pmn == 0.0) continue;
+                        int ej[3];
+                        cart_exps(lJ, cj, ej);
+                        double Nb = oracle_prim_norm(b, ej[0], ej[1], ej[2]);
+                        double gx = 0.0, gy = 0.0, gz = 0.0;
+                        for (int t = 0; t <= ei[0] + ej[0]; ++t)
+                            for (int u = 0; u <= ei[1] + ej[1]; ++u)
+                                for (int v = 0; v <= ei[2] + ej[2]; ++v) {
+                                    double E3 = Ex[(ei[0] * (lJ + 1) + ej[0]) * tw + t] *
+                                                Ey[(ei[1] * (lJ + 1) + ej[1]) * tw + u] *
+                                                Ez[(ei[2] * (lJ + 1) + ej[2]) * tw + v];
+                                    if (g_mutation == 7) gx += E3 * R[(t * RDIM + u + 1) * RDIM + v];
+                                    else gx += E3 * R[((t + 1) * RDIM + u) * RDIM + v];
+                                    gy += E3 * R[(t * RDIM + u + 1) * RDIM + v];
+                                    gz += E3 * R[(t * RDIM + u) * RDIM + v + 1];
+                                }
+                        double c = Pmn * ca * cb * Na * Nb * pref;
+                        if (g_mutation == 8) c = -c;
+                        nsum_add(&ex, -c * gx);
+                        nsum_add(&ey, -c * gy);
+                        nsum_add(&ez, -c * gz);
+                        absterms += fabs(c) * sqrt(gx * gx + gy * gy + gz * gz);
+                    }
+                }
+            }
+    }
+    out[0] = nsum_get(&ex);
+    out[1] = nsum_get(&ey);
+    out[2] = nsum_get(&ez);
+    out[3] = absterms;
+}
+
+/* Field E = -grad V at n points.  out is n x 4: E_x, E_y, E_z, AE.
+ * Arguments and return value as oracle_potential. */
+int oracle_field(int K, const double* xyz, const double* Z, int S,
+                 const int32_t* atom, const int32_t* l, const int32_t* nprim,
+                 const int64_t* poff, const double* ex, const double* co, int nbf,
+                 const int64_t* rowp, const int32_t* col, const double* val,
+                 int64_t n, const double* pts, int screen, double thr,
+                 int nthreads, double* out) {
+    for (int s = 0; s < S; ++s)
+        if (l[s] < 0 || l[s] > ORACLE_LMAX) return -1;
+    oracle_env e = {K, xyz, Z, S, atom, l, nprim, poff, ex, co, nbf, rowp, col, val};
+    prepared pr;
+    prepare(&e, &pr);
+#ifdef _OPENMP
+    int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+#else
+    (void)nthreads;
+#endif
+    for (int64_t i = 0; i < n; ++i) field_one(&e, &pr, pts + 3 * i, screen, thr, out + 4 * i);
     release(&e, &pr);
     return 0;
 }

@@ -57,6 +57,8 @@ def lib():
             ctypes.c_int, _i64p, _i32p, _dp, ctypes.c_int64, _dp, ctypes.c_int,
             ctypes.c_double, ctypes.c_int, _dp]
         L.oracle_potential.restype = ctypes.c_int
+        L.oracle_field.argtypes = L.oracle_potential.argtypes
+        L.oracle_field.restype = ctypes.c_int
         L.oracle_density_overlap_rows.argtypes = [
             ctypes.c_int, _dp, ctypes.c_int, _i32p, _i32p, _i32p, _i64p, _dp, _dp,
             ctypes.c_int, _i64p, _i32p, _dp, _dp]
@@ -102,7 +104,7 @@ def hermite_E(i, j, t, a, b, A, B) -> float:
                                   float(A), float(B))
 
 
-RDIM = 5
+RDIM = 6
 
 
 def hermite_R(L: int, p: float, X: float, Y: float, Z: float) -> np.ndarray:
@@ -192,6 +194,32 @@ def potential(env, points, P=None, scale=None, screen=False, thr=1e-12,
         P = env.density_csr(scale)
     return potential_raw(env.xyz, env.Z, env.shell_arrays(), P, points, screen,
                          thr, nthreads)
+
+
+def field_raw(xyz, Z, shells_flat, P, points, screen=False, thr=1e-12, nthreads=0):
+    """E = -grad V (n x 3) and the conditioning scale AE (n) at ``points``
+    for explicit arrays (arguments as potential_raw)."""
+    pk = _Packed(xyz, Z, shells_flat, P)
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros((pts.shape[0], 4))
+    rc = lib().oracle_field(
+        pk.xyz.shape[0], _p(pk.xyz, ctypes.c_double), _p(pk.Z, ctypes.c_double),
+        pk.l.shape[0], _p(pk.atom, ctypes.c_int32), _p(pk.l, ctypes.c_int32),
+        _p(pk.nprim, ctypes.c_int32), _p(pk.off, ctypes.c_int64),
+        _p(pk.ex, ctypes.c_double), _p(pk.co, ctypes.c_double), pk.nbf,
+        _p(pk.rowp, ctypes.c_int64), _p(pk.col, ctypes.c_int32),
+        _p(pk.val, ctypes.c_double), pts.shape[0], _p(pts, ctypes.c_double),
+        int(bool(screen)), float(thr), int(nthreads), _p(out, ctypes.c_double))
+    if rc != 0:
+        raise ValueError("oracle_field: bad argument")
+    return out[:, :3].copy(), out[:, 3].copy()
+
+
+def field(env, points, P=None, scale=None, screen=False, thr=1e-12, nthreads=0):
+    """E = -grad V and AE of a synth.Environment at ``points``."""
+    if P is None:
+        P = env.density_csr(scale)
+    return field_raw(env.xyz, env.Z, env.shell_arrays(), P, points, screen, thr, nthreads)
 
 
 def overlap_matrix_raw(xyz, shells_flat) -> np.ndarray:
