@@ -160,6 +160,21 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
 env_status env_potential_eval(env_potential* h, const double* points, int64_t n,
                               double* out, void* stream);
 
+/* The field E = -grad V together with V (an extension of the paper's
+ * quantity, Sec. II.B, Eq. ElectrostaticField: the force on a unit positive
+ * charge, whose negative is the electron's drift term).  For a pair the
+ * gradient is the Hermite recursion one order further,
+ *   d/dC [mu nu | C] = -(R_{t+1,u,v}, R_{t,u+1,v}, R_{t,u,v+1}) . D,
+ * and for a nucleus Z (C - R_A) / |C - R_A|^3.
+ * points: device n x 3 float64; out: device n x 4 float64 row-major
+ * (V, E_x, E_y, E_z per point, hartree/e and hartree/(e bohr)).  Same
+ * handle, precision and stream semantics as env_potential_eval; the
+ * precision's far-field switch is applied one Boys order higher.  A point on
+ * a nucleus gives non-finite values.  n = 0 is a no-op.
+ * Errors: as env_potential_eval. */
+env_status env_potential_eval_field(env_potential* h, const double* points, int64_t n,
+                                    double* out, void* stream);
+
 /* Several independent evaluations in one persistent launch (convenience
  * form of the env_batch calls below): instance i evaluates handle hs[i] at
  * points[i] (n[i] x 3) into out[i] (n[i]).  All handles must be on the same

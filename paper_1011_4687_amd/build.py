@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libenvpot.so")
 
 SOURCES = ["kernels.hip", "pairlist.cpp", "layout.cpp", "api.cpp", "batch.cpp", "surrogate.hip", "surrogate.cpp",
-           "probe.hip", "cells.hip", "cells.cpp"]
+           "probe.hip", "cells.hip", "cells.cpp", "field.hip", "field.cpp"]
 
 HIP_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -31,14 +31,15 @@ def hipcc() -> str:
 
 
 def generate() -> None:
-    """Regenerate hermite_gen.h from gen_hermite.py."""
-    out = subprocess.run([sys.executable, os.path.join(CSRC, "gen_hermite.py")],
-                         check=True, capture_output=True, text=True).stdout
-    path = os.path.join(CSRC, "hermite_gen.h")
-    old = open(path).read() if os.path.exists(path) else None
-    if old != out:
-        with open(path, "w") as f:
-            f.write(out)
+    """Regenerate hermite_gen.h (gen_hermite.py) and field_gen.h (gen_field.py)."""
+    for gen, header in (("gen_hermite.py", "hermite_gen.h"), ("gen_field.py", "field_gen.h")):
+        out = subprocess.run([sys.executable, os.path.join(CSRC, gen)],
+                             check=True, capture_output=True, text=True).stdout
+        path = os.path.join(CSRC, header)
+        old = open(path).read() if os.path.exists(path) else None
+        if old != out:
+            with open(path, "w") as f:
+                f.write(out)
 
 
 def build(verbose: bool = False, extra=None) -> str:

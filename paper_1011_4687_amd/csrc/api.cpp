@@ -34,6 +34,8 @@ void free_device(env_potential* h) {
     (void)hipFree(h->d_split);
     (void)hipFree(h->d_nuc);
     (void)hipFree(h->d_boys);
+    (void)hipFree(h->d_boys_field);
+    h->d_boys_field = nullptr;
     h->d_rec = nullptr;
     h->d_segs = nullptr;
     h->d_split = nullptr;
@@ -176,7 +178,10 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
     std::vector<float> t32;
     std::vector<double> t64;
     build_boys_tables(t32, t64, h->bp);
-    if (h->bp.rows32 > kBoysMaxRowsF32) {
+    std::vector<float> tf32;
+    std::vector<double> tf64;
+    build_field_tables(h->bp, tf32, tf64, h->fp);
+    if (h->bp.rows32 > kBoysMaxRowsF32 || h->fp.rows32 > kFieldMaxRowsF32) {
         delete h;
         return ENV_E_DEVICE;
     }
@@ -219,6 +224,10 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
         if (st == ENV_OK) {
             if (fp64) st = upload(t64, reinterpret_cast<double**>(&h->d_boys), h->device_bytes);
             else st = upload(t32, reinterpret_cast<float**>(&h->d_boys), h->device_bytes);
+        }
+        if (st == ENV_OK) {
+            if (fp64) st = upload(tf64, reinterpret_cast<double**>(&h->d_boys_field), h->device_bytes);
+            else st = upload(tf32, reinterpret_cast<float**>(&h->d_boys_field), h->device_bytes);
         }
     }
     if (st != ENV_OK) {

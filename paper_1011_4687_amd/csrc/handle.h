@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "envpot_internal.h"
+#include "field_internal.h"
 
 struct env_potential {
     int device = -1;
@@ -19,6 +20,8 @@ struct env_potential {
     int32_t* d_split = nullptr;
     double* d_nuc = nullptr;
     void* d_boys = nullptr;
+    void* d_boys_field = nullptr;       // Boys table of the field (one order more)
+    envpot::FieldParams fp{};
     int64_t seg_off[envpot::kMaxSplitLog2 + 1] = {};    // per split factor 2^k: first segment
     int64_t split_off[envpot::kMaxSplitLog2 + 1] = {};  // per split factor 2^k: first offset
     int64_t device_bytes = 0;

@@ -600,8 +600,6 @@ void far_coefs(int L, const double* D, double* h) {
 
 // ------------------------------------------------------------ Boys tables
 
-namespace {
-
 // F_n(T), n = 0..nmax, in long double: F_N for a high order N by its power
 // series, then the stable downward recursion F_n = (2T F_{n+1} + e^{-T})/(2n+1).
 void boys_ld(int nmax, long double T, long double* F) {
@@ -639,8 +637,6 @@ double far_threshold(int L, long double eps) {
     }
     return (last_bad + 1) / 8.0;
 }
-
-}  // namespace
 
 void build_boys_tables(std::vector<float>& t32, std::vector<double>& t64, BoysParams& bp) {
     std::memset(&bp, 0, sizeof(bp));

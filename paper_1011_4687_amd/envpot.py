@@ -133,6 +133,8 @@ def lib():
         L.env_potential_create.restype = c_int32
         L.env_potential_eval.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]
         L.env_potential_eval.restype = c_int32
+        L.env_potential_eval_field.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]
+        L.env_potential_eval_field.restype = c_int32
         L.env_potential_eval_batched.argtypes = [POINTER(c_void_p), c_int32, POINTER(c_void_p),
                                                  POINTER(c_int64), POINTER(c_void_p), c_void_p]
         L.env_potential_eval_batched.restype = c_int32
@@ -219,6 +221,14 @@ def env_potential_eval(handle: int, points_ptr: int, n: int, out_ptr: int,
                                   c_void_p(out_ptr), c_void_p(stream))
     if st != ENV_OK:
         raise EnvError(st, "env_potential_eval")
+
+
+def env_potential_eval_field(handle: int, points_ptr: int, n: int, out_ptr: int,
+                             stream: int = 0) -> None:
+    st = lib().env_potential_eval_field(c_void_p(handle), c_void_p(points_ptr), int(n),
+                                        c_void_p(out_ptr), c_void_p(stream))
+    if st != ENV_OK:
+        raise EnvError(st, "env_potential_eval_field")
 
 
 def env_potential_eval_batched(handles: Sequence[int], points_ptrs: Sequence[int],
@@ -404,6 +414,26 @@ class Environment:
             stream = torch.cuda.current_stream(points.device)
         env_potential_eval(self.handle, points.data_ptr(), n, out.data_ptr(),
                            stream.cuda_stream)
+        return out
+
+    def eval_field(self, points, out=None, stream=None):
+        """V and the field E = -grad V at a (n,3) float64 torch CUDA tensor;
+        returns a (n,4) tensor of rows (V, E_x, E_y, E_z)."""
+        import torch
+        if not (isinstance(points, torch.Tensor) and points.is_cuda):
+            raise TypeError("points must be a torch CUDA tensor")
+        if points.dtype != torch.float64 or points.dim() != 2 or points.shape[1] != 3:
+            raise TypeError("points must be float64 of shape (n, 3)")
+        points = points.contiguous()
+        n = points.shape[0]
+        if out is None:
+            out = torch.empty((n, 4), dtype=torch.float64, device=points.device)
+        if out.dtype != torch.float64 or out.numel() != 4 * n or not out.is_contiguous():
+            raise TypeError("out must be a contiguous float64 tensor of n x 4 elements")
+        if stream is None:
+            stream = torch.cuda.current_stream(points.device)
+        env_potential_eval_field(self.handle, points.data_ptr(), n, out.data_ptr(),
+                                 stream.cuda_stream)
         return out
 
     def autotune(self, points, stream=None):

@@ -1,0 +1,187 @@
+"""GPU parity of the field E = -grad V (with V) through the C ABI.
+
+FP64:  |E_gpu - E_oracle(screened)| <= 1e-12 AE per component, AE = sum_A Z_A/d^2
+       + sum over terms of |term gradient| (the field's conditioning scale);
+       V as the potential's bar, 1e-12 A.
+FP32C: |E_gpu - E_oracle| <= 1e-6 AE per component (about 2^-20 of the scale:
+       a few FP32 roundings per term, FP32 sums over 8 pairs), V within 1e-5 Ha."""
+import math
+
+import numpy as np
+import pytest
+
+from common import sample_indices, workload_scaled
+
+pytestmark = pytest.mark.gpu
+
+FP64_REL = 1e-12
+FP32_EREL = 1e-6
+FP32_VTOL = 1e-5
+
+
+def _env(name, precision, n_points=None, screening=True, merge=True):
+    from paper_1011_4687_amd.envpot import Environment
+    env, pts, P, _ = workload_scaled(name, n_points)
+    shells = [(s.atom, s.l, s.exponents, s.coefs) for s in env.shells]
+    return Environment(env.xyz, env.Z, env.fragment, shells, P, precision=precision,
+                       screening=screening, merge=merge), env, pts, P
+
+
+def _field(E, pts):
+    import torch
+    x = torch.from_numpy(np.ascontiguousarray(pts)).cuda()
+    f = E.eval_field(x)
+    torch.cuda.synchronize()
+    return f.cpu().numpy()
+
+
+def _check(precision, F, Eo, AE, Vo, A):
+    dE = np.abs(F[:, 1:] - Eo).max(axis=1)
+    dV = np.abs(F[:, 0] - Vo)
+    if precision == "fp64":
+        assert np.all(dE <= FP64_REL * AE), (dE / AE).max()
+        assert np.all(dV <= FP64_REL * A), (dV / A).max()
+    else:
+        assert np.all(dE <= FP32_EREL * AE), (dE / AE).max()
+        assert dV.max() <= FP32_VTOL, dV.max()
+    return (dE / AE).max()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_tiny_all_points(precision):
+    from oracle import oracle as O
+    print(f"[field] tiny {precision}", flush=True)
+    E, env, pts, P = _env("tiny", precision, screening=False)
+    F = _field(E, pts)
+    Eo, AE = O.field(env, pts, P=P, screen=False)
+    Vo, _, _, A = O.potential(env, pts, P=P, screen=False)
+    r = _check(precision, F, Eo, AE, Vo, A)
+    print(f"[field] tiny {precision}: max |dE|/AE {r:.3e}", flush=True)
+    E.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_mid_full_size_sampled(precision):
+    """131,072 points in one call (the benchmark's launch), 48 sampled points
+    against the oracle; the V column agrees with env_potential_eval; two
+    calls are bitwise equal."""
+    import torch
+    from oracle import oracle as O
+    print(f"[field] mid {precision}", flush=True)
+    E, env, pts, P = _env("mid", precision)
+    F = _field(E, pts)
+    F2 = _field(E, pts)
+    assert np.array_equal(F, F2)
+    idx = sample_indices(len(pts), 48)
+    screen = precision == "fp64"
+    Eo, AE = O.field(env, pts[idx], P=P, screen=screen)
+    Vo, _, _, A = O.potential(env, pts[idx], P=P, screen=screen)
+    r = _check(precision, F[idx], Eo, AE, Vo, A)
+    print(f"[field] mid {precision}: max |dE|/AE {r:.3e}", flush=True)
+    V = E.eval(torch.from_numpy(pts).cuda()).cpu().numpy()
+    d = np.abs(F[:, 0] - V).max()
+    assert d <= (1e-11 if precision == "fp64" else 2e-6), d
+    E.close()
+
+
+@pytest.mark.parametrize("n", [1, 63, 255, 513, 4097])
+def test_ragged_sizes(n):
+    from oracle import oracle as O
+    print(f"[field] ragged n={n}", flush=True)
+    E, env, pts, P = _env("tiny", "fp64", n_points=n, screening=False)
+    F = _field(E, pts)
+    assert F.shape == (n, 4)
+    idx = sample_indices(n, 12)
+    Eo, AE = O.field(env, pts[idx], P=P, screen=False)
+    Vo, _, _, A = O.potential(env, pts[idx], P=P, screen=False)
+    _check("fp64", F[idx], Eo, AE, Vo, A)
+    E.close()
+
+
+def test_zero_points():
+    import torch
+    from paper_1011_4687_amd.envpot import env_potential_eval_field
+    E, env, pts, P = _env("tiny", "fp32c", n_points=4)
+    env_potential_eval_field(E.handle, 0, 0, 0, 0)
+    out = E.eval_field(torch.zeros((0, 3), dtype=torch.float64, device="cuda"))
+    assert out.shape == (0, 4)
+    E.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32c", "fp64"])
+def test_clusters_and_launch_shapes(precision, monkeypatch):
+    """Merged same-centre clusters against pair-by-pair evaluation, and every
+    points-per-lane / split shape, agree to rounding on 8192 mid points."""
+    print(f"[field] clusters/shapes {precision}", flush=True)
+    Em, env, pts, P = _env("mid", precision, n_points=8192)
+    Ep, _, _, _ = _env("mid", precision, n_points=8192, merge=False)
+    Fm, Fp = _field(Em, pts), _field(Ep, pts)
+    tol = 1e-11 if precision == "fp64" else 2e-6
+    assert np.abs(Fm - Fp).max() <= tol, np.abs(Fm - Fp).max()
+    for np_, k in [(1, 0), (1, 4), (2, 6), (2, 2)]:
+        monkeypatch.setenv("ENVPOT_FIELD_NP", str(np_))
+        monkeypatch.setenv("ENVPOT_FIELD_SPLIT_LOG2", str(k))
+        F1 = _field(Em, pts)
+        assert np.array_equal(F1, _field(Em, pts)), (np_, k)
+        assert np.abs(F1 - Fm).max() <= tol, (np_, k, np.abs(F1 - Fm).max())
+    Em.close()
+    Ep.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+@pytest.mark.parametrize("alpha", [0.08, 1.7, 950.0])
+def test_gaussian_charge_closed_form(precision, alpha):
+    """One atom (Z = 6) with one normalised s Gaussian of q electrons:
+    E = [Z - q erf(sqrt(p) r) + 2 q sqrt(p/pi) r exp(-p r^2)] r_vec / r^3,
+    p = 2 alpha, over p r^2 from 1e-6 to 4e3 (no oracle in between)."""
+    from paper_1011_4687_amd.envpot import Environment
+    print(f"[field] closed form {precision} alpha={alpha}", flush=True)
+    A = np.array([[1.25, -0.5, 2.0]])
+    Z, q = 6.0, 1.7
+    p = 2.0 * alpha
+    rng = np.random.default_rng(7)
+    r0 = np.exp(rng.uniform(np.log(1e-3 / math.sqrt(p)), np.log(60.0 / math.sqrt(p) + 1.0), 4097))
+    u = rng.normal(size=(4097, 3))
+    pts = A[0] + (u / np.linalg.norm(u, axis=1)[:, None]) * r0[:, None]
+    E = Environment(A, [Z], [0], [(0, 0, np.array([alpha]), np.array([1.0]))], np.array([[q]]),
+                    precision=precision, screening=False)
+    F = _field(E, pts)
+    ref = np.zeros((len(pts), 3))
+    scale = np.zeros(len(pts))
+    for k, v in enumerate(pts - A[0]):
+        r = math.sqrt(float(v @ v))
+        x = math.sqrt(p) * r
+        if x < 0.5:
+            g = sum((-1) ** (m + 1) * 2 * m * x ** (2 * m + 1) / (math.factorial(m) * (2 * m + 1))
+                    for m in range(1, 20)) * 2.0 / math.sqrt(math.pi)
+        else:
+            g = math.erf(x) - 2.0 * x * math.exp(-x * x) / math.sqrt(math.pi)
+        ref[k] = (Z - q * g) * v / r ** 3
+        scale[k] = (Z + q) / r ** 2
+    err = np.abs(F[:, 1:] - ref).max(axis=1)
+    if precision == "fp64":
+        assert np.all(err <= 4e-15 * scale), (err / scale).max()
+    else:
+        assert np.all(err <= 1e-6 * scale), (err / scale).max()
+    E.close()
+
+
+def test_fp64_field_is_minus_gradient_of_gpu_potential():
+    """On the GPU alone: fourth-order differences of the FP64 potential kernel
+    reproduce the FP64 field kernel (mid environment, 16 points)."""
+    import torch
+    print("[field] gradient of the GPU potential", flush=True)
+    E, env, pts, P = _env("mid", "fp64", n_points=16)
+    F = _field(E, pts)
+    h = 1e-3
+    stencil = []
+    for C in pts:
+        for d in range(3):
+            for s in (-2, -1, 1, 2):
+                e = np.zeros(3)
+                e[d] = s * h
+                stencil.append(C + e)
+    V = E.eval(torch.from_numpy(np.array(stencil)).cuda()).cpu().numpy().reshape(len(pts), 3, 4)
+    g = (V[:, :, 0] - 8 * V[:, :, 1] + 8 * V[:, :, 2] - V[:, :, 3]) / (12 * h)
+    assert np.abs(F[:, 1:] + g).max() <= 1e-7 * np.abs(F[:, 1:]).max() + 1e-9, np.abs(F[:, 1:] + g).max()
+    E.close()
