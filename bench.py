@@ -71,6 +71,24 @@ def time_path(E, x, out, steps, warmup, torch):
     return wall, float(np.mean(ms))
 
 
+def time_field(E, x, out, steps, warmup, torch):
+    """Mean device time (ms) of one field evaluation, HIP events on a side
+    stream around each call."""
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            E.eval_field(x, out=out, stream=stream)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        for s, e in evs:
+            s.record(stream)
+            E.eval_field(x, out=out, stream=stream)
+            e.record(stream)
+    torch.cuda.synchronize()
+    return float(np.mean([s.elapsed_time(e) for s, e in evs]))
+
+
 def cells_leg(torch, envpot, synth, steps, warmup):
     """The paper's own form of the environment: 19 nuclei and 268,398
     point-charge cells.  Batched throughput (131,072 points per call) and the
@@ -202,6 +220,8 @@ def main():
     ap.add_argument("--paths", default="fp32c,fp64")
     ap.add_argument("--no-cells", action="store_true",
                     help="skip the cell-sum leg (the paper's own form of the environment)")
+    ap.add_argument("--no-field", action="store_true",
+                    help="skip the field leg (E = -grad V with V on the same workload)")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the learned-surrogate leg (1000-atom surrogate workload)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -214,7 +234,7 @@ def main():
 
     import torch
     from paper_1011_4687_amd import envpot, synth
-    from paper_1011_4687_amd.workcount import eval_flops
+    from paper_1011_4687_amd.workcount import eval_field_flops, eval_flops
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -227,6 +247,7 @@ def main():
 
     paths = {}
     outs = {}
+    fields = {}
     info = None
     for prec in args.paths.split(","):
         t0 = time.perf_counter()
@@ -246,6 +267,19 @@ def main():
         }
         outs[prec] = out.cpu().numpy()
         log(f"[bench] {prec}: {ms:.3f} ms/step, {paths[prec]['point_pairs_per_s']:.4g} pp/s")
+        if not args.no_field:
+            # the field E = -grad V (with V) of the same handle at the same points
+            fout = torch.empty((n, 4), dtype=torch.float64, device="cuda")
+            fms = time_field(E, x, fout, args.steps, args.warmup, torch)
+            fflops = eval_field_flops(n, info["n_pairs_by_L"], info["n_nuclei"])
+            paths[prec]["field"] = {
+                "point_pairs_per_s": n * npairs / (fms * 1e-3),
+                "ms_per_step": fms,
+                "tflops_algorithmic": fflops / (fms * 1e-3) / 1e12,
+            }
+            fields[prec] = fout.cpu().numpy()
+            log(f"[bench] {prec} field: {fms:.3f} ms/step, {n * npairs / (fms * 1e-3):.4g} pp/s, "
+                f"{fflops / (fms * 1e-3) / 1e12:.1f} TFLOP/s algorithmic")
         E.close()
 
     cells = None
@@ -358,6 +392,20 @@ def main():
                 err = np.abs(V[sidx] - Vo2)
                 acc[name] = {"max_abs_err": float(err.max()),
                              "rms_err": float(np.sqrt(np.mean(err ** 2))), "n_checked": int(k)}
+        if fields:
+            # the field oracle on a smaller sample of the same points
+            fidx = idx[: max(8, len(idx) // 4)]
+            t0 = time.perf_counter()
+            Eo, AE = O.field(env, pts[fidx], scale=sc, screen=True, nthreads=cores)
+            t_f = time.perf_counter() - t0
+            result["cpu_baseline"]["field"] = {
+                "value": len(fidx) * info["n_pairs"] / t_f, "unit": "point-pair field evals/s",
+                "cores": cores, "sample": f"{len(fidx)} of the {n} points, screened FP64 field oracle, "
+                                          f"{t_f:.1f} s on {cores} threads"}
+            for prec, F in fields.items():
+                err = np.abs(F[fidx, 1:] - Eo).max(axis=1)
+                acc[f"field_{prec}"] = {"max_abs_err": float(err.max()),
+                                        "max_rel_to_AE": float((err / AE).max()), "n_checked": len(fidx)}
         if cells is not None:
             # the cell-sum oracle, one host core, on a sample of that workload
             from oracle import cells_oracle as CO

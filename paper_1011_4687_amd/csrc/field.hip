@@ -62,7 +62,7 @@ __device__ __forceinline__ void far_eval(const T* __restrict__ h, T X, T Y, T Z,
     const T x = X * w, y = Y * w, z = Z * w;
     T f[4];
     far_poly<L, T>(h, x, y, z, f);
-    const T W = fmat(T(2) * x, f[1], fmat(T(2) * y, f[2], fmat(T(2) * z, f[3], f[0])));
+    const T W = fmat(T(2), fmat(x, f[1], fmat(y, f[2], z * f[3])), f[0]);  // H + 2 x.dH
     const T t = ri * w;
     o[0] = ri * f[0];
     o[1] = t * fmat(-X, W, f[1]);

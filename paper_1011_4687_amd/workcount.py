@@ -12,11 +12,18 @@ kernels schedule them:
 * contraction sum_tuv D_tuv R_tuv: 2 per component
 * accumulation: 1
 and one point x one nucleus costs 10 (difference, R^2, Z/R, add).
+
+The field E = -grad V (with V) of one point x one pair runs the same steps one
+order further: Boys values G_0..G_{L+1}, the recursion of total order L+1,
+four contractions (V and three gradient components, 2 flops per component
+each) and four accumulations; one point x one nucleus costs 19 (difference 3,
+R^2 5, 1/R 1, Z/R 1, Z/R^3 2, three products 3, four accumulations).
 """
 from functools import lru_cache
 
 NCOMP = (1, 4, 10, 20, 35)
 NUCLEUS_FLOPS = 10
+NUCLEUS_FIELD_FLOPS = 19
 
 
 @lru_cache(maxsize=None)
@@ -43,4 +50,16 @@ def eval_flops(n_points: int, pairs_by_L, n_nuclei: int) -> float:
     """Algorithmic flops of one evaluation at n_points points."""
     per_point = sum(int(c) * pair_flops(L) for L, c in enumerate(pairs_by_L))
     per_point += NUCLEUS_FLOPS * int(n_nuclei)
+    return float(n_points) * per_point
+
+
+@lru_cache(maxsize=None)
+def field_pair_flops(L: int) -> int:
+    return 9 + (3 * (L + 1) + 4) + recursion_flops(L + 1) + 8 * NCOMP[L] + 4
+
+
+def eval_field_flops(n_points: int, pairs_by_L, n_nuclei: int) -> float:
+    """Algorithmic flops of one field evaluation (V and E) at n_points points."""
+    per_point = sum(int(c) * field_pair_flops(L) for L, c in enumerate(pairs_by_L))
+    per_point += NUCLEUS_FIELD_FLOPS * int(n_nuclei)
     return float(n_points) * per_point
