@@ -55,19 +55,40 @@ __device__ __forceinline__ void far_poly(const T* __restrict__ h, T x, T y, T z,
 __device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// Far-field potential and gradient (with respect to X) at X = P - C; ri = 1/R.
+// Far-field potential and gradient (with respect to X) at X = P - C, added
+// to a[0..3]; ri = 1/R.  With t = ri w and W = H + 2 x.dH:
+//     a0 += ri H,   a_i += t dH_i - t W X_i.
+// L = 0: dH = 0, W = H = h0.  L = 1: H = h0 + w s with s = h.X (the degree-1
+// coefficients), dH = those coefficients, x.dH = w s, so W = h0 + 3 w s and
+// no scaled coordinates are needed.
 template <int L, typename T>
-__device__ __forceinline__ void far_eval(const T* __restrict__ h, T X, T Y, T Z, T ri, T* o) {
+__device__ __forceinline__ void far_acc(const T* __restrict__ h, T X, T Y, T Z, T ri, T* a) {
     const T w = ri * ri;
-    const T x = X * w, y = Y * w, z = Z * w;
-    T f[4];
-    far_poly<L, T>(h, x, y, z, f);
-    const T W = fmat(T(2), fmat(x, f[1], fmat(y, f[2], z * f[3])), f[0]);  // H + 2 x.dH
     const T t = ri * w;
-    o[0] = ri * f[0];
-    o[1] = t * fmat(-X, W, f[1]);
-    o[2] = t * fmat(-Y, W, f[2]);
-    o[3] = t * fmat(-Z, W, f[3]);
+    if constexpr (L == 0) {
+        a[0] = fmat(ri, h[0], a[0]);
+        const T tw = t * h[0];
+        a[1] = fmat(-tw, X, a[1]);
+        a[2] = fmat(-tw, Y, a[2]);
+        a[3] = fmat(-tw, Z, a[3]);
+    } else if constexpr (L == 1) {
+        // component order (0,0,0), (0,0,1), (0,1,0), (1,0,0)
+        const T ws = w * fmat(h[1], Z, fmat(h[2], Y, h[3] * X));
+        const T tw = t * fmat(T(3), ws, h[0]);
+        a[0] = fmat(ri, h[0] + ws, a[0]);
+        a[1] = fmat(-tw, X, fmat(t, h[3], a[1]));
+        a[2] = fmat(-tw, Y, fmat(t, h[2], a[2]));
+        a[3] = fmat(-tw, Z, fmat(t, h[1], a[3]));
+    } else {
+        const T x = X * w, y = Y * w, z = Z * w;
+        T f[4];
+        far_poly<L, T>(h, x, y, z, f);
+        const T tw = t * fmat(T(2), fmat(x, f[1], fmat(y, f[2], z * f[3])), f[0]);
+        a[0] = fmat(ri, f[0], a[0]);
+        a[1] = fmat(-tw, X, fmat(t, f[1], a[1]));
+        a[2] = fmat(-tw, Y, fmat(t, f[2], a[2]));
+        a[3] = fmat(-tw, Z, fmat(t, f[3], a[3]));
+    }
 }
 
 // Near field (FP32): Boys F_0..F_{L+1} by a 6-term Taylor step from the
@@ -164,20 +185,18 @@ __device__ __forceinline__ void pairs_f32(const GLB uint32_t* __restrict__ rec, 
             }
             if (__builtin_amdgcn_ballot_w64(nearp) == 0) {
 #pragma unroll
-                for (int k = 0; k < NP; ++k) {
-                    float o[4];
-                    far_eval<L, float>(h, X[k], Y[k], Z[k], rsqrt_refined(r2[k]), o);
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) t[k][c] += o[c];
-                }
+                for (int k = 0; k < NP; ++k) far_acc<L, float>(h, X[k], Y[k], Z[k], rsqrt_refined(r2[k]), t[k]);
             } else {
 #pragma unroll
                 for (int k = 0; k < NP; ++k) {
-                    float o[4];
-                    if (r2[k] < r2f) near_f32<L>(r, X[k], Y[k], Z[k], r2[k], tab, o);
-                    else far_eval<L, float>(h, X[k], Y[k], Z[k], rsqrt_refined(r2[k]), o);
+                    if (r2[k] < r2f) {
+                        float o[4];
+                        near_f32<L>(r, X[k], Y[k], Z[k], r2[k], tab, o);
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) t[k][c] += o[c];
+                        for (int c = 0; c < 4; ++c) t[k][c] += o[c];
+                    } else {
+                        far_acc<L, float>(h, X[k], Y[k], Z[k], rsqrt_refined(r2[k]), t[k]);
+                    }
                 }
             }
         }
@@ -213,20 +232,18 @@ __device__ __forceinline__ void pairs_f64(const GLB uint32_t* __restrict__ rec, 
         }
         if (__builtin_amdgcn_ballot_w64(nearp) == 0) {
 #pragma unroll
-            for (int k = 0; k < NP; ++k) {
-                double o[4];
-                far_eval<L, double>(h, X[k], Y[k], Z[k], rsqrt_far(r2[k]), o);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) ge[k][c] += o[c];
-            }
+            for (int k = 0; k < NP; ++k) far_acc<L, double>(h, X[k], Y[k], Z[k], rsqrt_far(r2[k]), ge[k]);
         } else {
 #pragma unroll
             for (int k = 0; k < NP; ++k) {
-                double o[4];
-                if (r2[k] < r2f) near_f64<L>(r, X[k], Y[k], Z[k], r2[k], tab, o);
-                else far_eval<L, double>(h, X[k], Y[k], Z[k], rsqrt_far(r2[k]), o);
+                if (r2[k] < r2f) {
+                    double o[4];
+                    near_f64<L>(r, X[k], Y[k], Z[k], r2[k], tab, o);
 #pragma unroll
-                for (int c = 0; c < 4; ++c) ge[k][c] += o[c];
+                    for (int c = 0; c < 4; ++c) ge[k][c] += o[c];
+                } else {
+                    far_acc<L, double>(h, X[k], Y[k], Z[k], rsqrt_far(r2[k]), ge[k]);
+                }
             }
         }
     }
@@ -240,6 +257,13 @@ __device__ __forceinline__ int clusters(const GLB uint32_t* __restrict__ rec, in
                                         const double* cy, const double* cz, double ratio, double (*ge)[4]) {
     using T = typename std::conditional<F64, double, float>::type;
     constexpr int CW = F64 ? cl64_words(LC) : cl32_words(LC);
+    // FP32: partial sums over kFTile clusters, promoted to FP64
+    T tile[NP][4];
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) tile[k][c] = T(0);
+    int done = 0;
     for (; i < n; ++i) {
         const GLB uint32_t* r = rec + (int64_t)i * CW;
         const GLB double* rd = reinterpret_cast<const GLB double*>(r);
@@ -269,13 +293,23 @@ __device__ __forceinline__ int clusters(const GLB uint32_t* __restrict__ rec, in
         if (__builtin_amdgcn_ballot_w64(nearp) != 0) break;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
-            T o[4];
-            if constexpr (F64) far_eval<LC, double>(h, X[k], Y[k], Z[k], rsqrt_far(r2[k]), o);
-            else far_eval<LC, float>(h, X[k], Y[k], Z[k], rsqrt_refined(r2[k]), o);
+            if constexpr (F64) far_acc<LC, double>(h, X[k], Y[k], Z[k], rsqrt_far(r2[k]), tile[k]);
+            else far_acc<LC, float>(h, X[k], Y[k], Z[k], rsqrt_refined(r2[k]), tile[k]);
+        }
+        if ((++done & (kFTile - 1)) == 0) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) ge[k][c] += (double)o[c];
+            for (int k = 0; k < NP; ++k)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    ge[k][c] += (double)tile[k][c];
+                    tile[k][c] = T(0);
+                }
         }
     }
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) ge[k][c] += (double)tile[k][c];
     return i;
 }
 
@@ -411,8 +445,11 @@ __device__ __forceinline__ void field_block(const PTS double* __restrict__ pts, 
     }
 }
 
+// Four waves per SIMD (128 VGPRs): the per-point state and the near-field
+// recursion spill to scratch, which costs less than the latency that two
+// or three resident waves leave exposed.
 template <int NP, bool F64>
-__global__ __launch_bounds__(kBlock) void k_field(FieldArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_field(FieldArgs a) {
     __shared__ float tab32[F64 ? 1 : kFieldMaxRowsF32 * kFieldRowF32];
     if constexpr (!F64) {
         const float* g = static_cast<const float*>(a.boys);
