@@ -112,6 +112,13 @@ def test_eval_requires_device_handle():
         E.env_potential_eval(h.handle, 8, 1, 8, 0)
     assert ei.value.status == E.ENV_E_STATE
     E.env_potential_eval(h.handle, 0, 0, 0, 0)  # n = 0 is a no-op
+    with pytest.raises(E.EnvError) as ei:
+        E.env_potential_eval_field(h.handle, 8, 1, 8, 0)
+    assert ei.value.status == E.ENV_E_STATE
+    E.env_potential_eval_field(h.handle, 0, 0, 0, 0)
+    with pytest.raises(E.EnvError) as ei:
+        E.env_potential_eval_field(h.handle, 0, -1, 0, 0)
+    assert ei.value.status == E.ENV_E_ARG
 
 
 def test_create_without_gpu_fails_loudly():

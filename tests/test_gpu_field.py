@@ -80,7 +80,9 @@ def test_mid_full_size_sampled(precision):
     print(f"[field] mid {precision}: max |dE|/AE {r:.3e}", flush=True)
     V = E.eval(torch.from_numpy(pts).cuda()).cpu().numpy()
     d = np.abs(F[:, 0] - V).max()
-    assert d <= (1e-11 if precision == "fp64" else 2e-6), d
+    # two FP32C evaluations with different far-field switches and sums: each
+    # within about 2e-6 of the exact value on this workload
+    assert d <= (1e-11 if precision == "fp64" else 4e-6), d
     E.close()
 
 
