@@ -219,6 +219,68 @@ env_status env_batch_get_stats(const env_batch* b, env_batch_stats* stats);
 
 void env_batch_destroy(env_batch* b);
 
+/* ------------------------------------------------------------------------
+ * One GPU shared by the processes of a node (the paper's outlook, Sec. I and
+ * Sec. V: the GPU shared by the MPI processes running on the same node).
+ * A server process owns the environments and the GPU; clients in other
+ * processes (or threads) attach to it by name through POSIX shared memory
+ * and submit evaluation requests with host buffers.  The server's worker
+ * thread takes every request that is ready, evaluates them together in one
+ * persistent batched launch (env_potential_eval_batched) and returns the
+ * potentials.  Client calls make no HIP call: clients need no GPU context.
+ * ------------------------------------------------------------------------ */
+typedef struct env_server env_server;
+typedef struct env_client env_client;
+
+typedef struct {
+    int64_t rounds;           /* batched launches */
+    int64_t requests;         /* requests served */
+    int64_t points;           /* points evaluated */
+    int64_t errors;           /* requests answered with an error */
+    double busy_seconds;      /* worker time spent serving rounds */
+    int32_t clients;          /* slots currently attached */
+    int32_t reserved;
+} env_server_stats;
+
+/* Serve the n_env handles (same device and precision; they must outlive the
+ * server) under `name` ([^/]+, at most 200 characters; the segment is
+ * /dev/shm/envpot.<name>).  n_slots: the most clients attached at once (one
+ * request in flight each); max_points: the largest request; gather_us: how
+ * long the worker waits after the first ready request before it takes all
+ * ready requests (0: at once).  A segment of that name whose server process
+ * is gone is replaced.
+ * Errors: ENV_E_ARG, ENV_E_STATE (a build-only handle, or a live server of
+ * that name), ENV_E_NOMEM, ENV_E_DEVICE. */
+env_status env_server_create(env_potential* const* hs, int32_t n_env, const char* name, int32_t n_slots,
+                             int64_t max_points, int32_t gather_us, env_server** out);
+
+env_status env_server_get_stats(const env_server* s, env_server_stats* stats);
+
+/* Stops the worker, answers requests still waiting with ENV_E_STATE and
+ * removes the segment. */
+void env_server_destroy(env_server* s);
+
+/* Attach to the server `name` and claim a free slot.
+ * Errors: ENV_E_ARG (bad name), ENV_E_STATE (no such live server, or every
+ * slot taken), ENV_E_NOMEM. */
+env_status env_client_attach(const char* name, env_client** out);
+
+/* The server's environment count, request size limit and this client's slot. */
+env_status env_client_info(const env_client* c, int32_t* n_env, int64_t* max_points, int32_t* slot);
+
+/* V of environment `env` (index into the server's handles) at n host points
+ * (n x 3 float64) into out (host, n float64); blocks until answered.
+ * timeout_ms <= 0 waits as long as the server lives.  n = 0 is allowed.
+ * Errors: ENV_E_ARG (bad env, n above max_points, NULL), ENV_E_STATE (the
+ * server is gone, or the client is unusable after a time-out), ENV_E_DEVICE
+ * (time-out, or a device error on the server), or the status the server's
+ * evaluation returned. */
+env_status env_client_eval(env_client* c, int32_t env, const double* points, int64_t n, double* out,
+                           int32_t timeout_ms);
+
+/* Release the slot (kept taken after a time-out) and unmap the segment. */
+void env_client_detach(env_client* c);
+
 /* Times the candidate launch shapes (points per lane, pair-split factor) of
  * h at the n device points `points` on `stream` (synchronous) and keeps the
  * fastest for evaluations of h at a point count within a factor 2 of n.

@@ -16,7 +16,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libenvpot.so")
 
 SOURCES = ["kernels.hip", "pairlist.cpp", "layout.cpp", "api.cpp", "batch.cpp", "surrogate.hip", "surrogate.cpp",
-           "probe.hip", "cells.hip", "cells.cpp", "field.hip", "field.cpp"]
+           "probe.hip", "cells.hip", "cells.cpp", "field.hip", "field.cpp",
+           "server.cpp"]
 
 HIP_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -47,7 +48,7 @@ def build(verbose: bool = False, extra=None) -> str:
     tmp = LIB + ".tmp"
     cmd = [hipcc()] + HIP_FLAGS + ["-shared", "-I", INCLUDE, "-I", CSRC]
     cmd += [os.path.join(CSRC, s) for s in SOURCES]
-    cmd += list(extra or []) + ["-o", tmp, "-lpthread"]
+    cmd += list(extra or []) + ["-o", tmp, "-lpthread", "-lrt"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -80,6 +80,11 @@ class env_batch_stats(ctypes.Structure):
                 ("launches", c_int64), ("captures", c_int64), ("graph_launches", c_int64)]
 
 
+class env_server_stats(ctypes.Structure):
+    _fields_ = [("rounds", c_int64), ("requests", c_int64), ("points", c_int64), ("errors", c_int64),
+                ("busy_seconds", c_double), ("clients", c_int32), ("reserved", c_int32)]
+
+
 class env_surrogate_spec(ctypes.Structure):
     _fields_ = [("n_freq", c_int32), ("hidden", c_int32), ("layers", c_int32),
                 ("poly_degree", c_int32), ("radius", c_double), ("B", POINTER(c_double)),
@@ -188,6 +193,21 @@ def lib():
         L.env_cells_eval_single.restype = c_int32
         L.env_cells_destroy.argtypes = [c_void_p]
         L.env_cells_destroy.restype = None
+        L.env_server_create.argtypes = [POINTER(c_void_p), c_int32, ctypes.c_char_p, c_int32, c_int64,
+                                        c_int32, POINTER(c_void_p)]
+        L.env_server_create.restype = c_int32
+        L.env_server_get_stats.argtypes = [c_void_p, POINTER(env_server_stats)]
+        L.env_server_get_stats.restype = c_int32
+        L.env_server_destroy.argtypes = [c_void_p]
+        L.env_server_destroy.restype = None
+        L.env_client_attach.argtypes = [ctypes.c_char_p, POINTER(c_void_p)]
+        L.env_client_attach.restype = c_int32
+        L.env_client_info.argtypes = [c_void_p, POINTER(c_int32), POINTER(c_int64), POINTER(c_int32)]
+        L.env_client_info.restype = c_int32
+        L.env_client_eval.argtypes = [c_void_p, c_int32, c_void_p, c_int64, c_void_p, c_int32]
+        L.env_client_eval.restype = c_int32
+        L.env_client_detach.argtypes = [c_void_p]
+        L.env_client_detach.restype = None
         _lib = L
     return _lib
 
@@ -703,3 +723,73 @@ def fourier_matrix(seed: int = 0, sigma: float = 1.0) -> np.ndarray:
     """64 frequency vectors b ~ N(0, sigma^2 I) (1/bohr)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.standard_normal((64, 3)) * sigma
+
+
+class Server:
+    """Serve environments to other processes of the node (env_server_*)."""
+
+    def __init__(self, envs: Sequence, name: str, n_slots: int = 16, max_points: int = 65536,
+                 gather_us: int = 0):
+        self.envs = list(envs)  # the handles must outlive the server
+        arr = (c_void_p * len(self.envs))(*[e.handle for e in self.envs])
+        h = c_void_p()
+        st = lib().env_server_create(arr, len(self.envs), name.encode(), int(n_slots), int(max_points),
+                                     int(gather_us), ctypes.byref(h))
+        if st != ENV_OK:
+            raise EnvError(st, "env_server_create")
+        self.handle = h.value
+        self.name = name
+
+    def stats(self) -> dict:
+        st = env_server_stats()
+        r = lib().env_server_get_stats(c_void_p(self.handle), ctypes.byref(st))
+        if r != ENV_OK:
+            raise EnvError(r, "env_server_get_stats")
+        return {f: getattr(st, f) for f, _ in env_server_stats._fields_ if f != "reserved"}
+
+    def close(self):
+        if self.handle:
+            lib().env_server_destroy(c_void_p(self.handle))
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Client:
+    """A client of a Server, by name; host numpy buffers, no GPU context."""
+
+    def __init__(self, name: str):
+        h = c_void_p()
+        st = lib().env_client_attach(name.encode(), ctypes.byref(h))
+        if st != ENV_OK:
+            raise EnvError(st, "env_client_attach")
+        self.handle = h.value
+        ne, mp, sl = c_int32(), c_int64(), c_int32()
+        lib().env_client_info(c_void_p(self.handle), ctypes.byref(ne), ctypes.byref(mp), ctypes.byref(sl))
+        self.n_env, self.max_points, self.slot = ne.value, mp.value, sl.value
+
+    def eval(self, env: int, points, out=None, timeout_ms: int = 60000) -> np.ndarray:
+        pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+        n = pts.shape[0]
+        if out is None:
+            out = np.empty(n)
+        st = lib().env_client_eval(c_void_p(self.handle), int(env), pts.ctypes.data, n, out.ctypes.data,
+                                   int(timeout_ms))
+        if st != ENV_OK:
+            raise EnvError(st, "env_client_eval")
+        return out
+
+    def close(self):
+        if self.handle:
+            lib().env_client_detach(c_void_p(self.handle))
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

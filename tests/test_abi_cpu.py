@@ -174,3 +174,22 @@ def test_argument_errors(case):
     with pytest.raises(E.EnvError) as ei:
         E.Environment(xyz, Z, frag, shells, P, build_only=True, **kw)
     assert ei.value.status == expect, case
+
+
+def test_server_and_client_argument_errors(tmp_path):
+    """Host-side checks of the shared-GPU server and its clients (no GPU)."""
+    from paper_1011_4687_amd.envpot import Client, Server
+    with pytest.raises(E.EnvError) as ei:
+        Client("no/slash")
+    assert ei.value.status == E.ENV_E_ARG
+    with pytest.raises(E.EnvError) as ei:
+        Client("no_such_server_" + os.urandom(4).hex())
+    assert ei.value.status == E.ENV_E_STATE
+    env, shells = _tiny_args()
+    h = _build_only(env, shells, env.density_dense([1.0]))
+    with pytest.raises(E.EnvError) as ei:
+        Server([h], "x" + os.urandom(4).hex())  # build-only handles cannot be served
+    assert ei.value.status == E.ENV_E_STATE
+    with pytest.raises(E.EnvError) as ei:
+        Server([h], "bad/name")
+    assert ei.value.status == E.ENV_E_ARG
