@@ -89,6 +89,70 @@ def time_field(E, x, out, steps, warmup, torch):
     return float(np.mean([s.elapsed_time(e) for s, e in evs]))
 
 
+def shared_leg(torch, envpot, synth, n_clients=8, n_req=16, n_pts=4096):
+    """One GPU shared by the processes of a node (the paper's outlook): each
+    of n_clients client processes (no GPU context) evaluates its own QM/MM
+    instance at n_pts host points n_req times through the server, which
+    evaluates whatever requests are ready in one batched launch.  Baseline:
+    the same requests one after another from one process (host points copied
+    in, env_potential_eval, host values copied out).  FP32C."""
+    import subprocess
+    import tempfile
+    import uuid
+    root = os.path.dirname(os.path.abspath(__file__))
+    insts = synth.batched_instances(n_clients, seed0=3100, max_points=n_pts)
+    envs = [envpot.Environment.from_synth(env, precision="fp32c", neutralize=True) for env, _ in insts]
+    pairs = [E.info()["n_pairs"] for E in envs]
+    work = float(sum(n_req * len(p) * q for (_, p), q in zip(insts, pairs)))
+    name = "bench" + uuid.uuid4().hex[:10]
+    srv = envpot.Server(envs, name, n_slots=n_clients, max_points=n_pts, gather_us=20)
+    with tempfile.TemporaryDirectory() as td:
+        procs, answers = [], []
+        for c, (_, pts) in enumerate(insts):
+            req, ans = os.path.join(td, f"req{c}.npz"), os.path.join(td, f"ans{c}.npz")
+            np.savez(req, env=np.array([c]), n=np.array([len(pts)]), points=pts)
+            answers.append(ans)
+            procs.append(subprocess.Popen([sys.executable, "-m", "paper_1011_4687_amd.server_client", name, req, ans,
+                                           str(n_req)], cwd=root))
+        rcs = [p.wait(timeout=300) for p in procs]
+        if any(rcs):
+            raise RuntimeError(f"shared-GPU clients failed: {rcs}")
+        res = [dict(np.load(a)) for a in answers]
+    stats = srv.stats()
+    srv.close()
+    t_span = max(r["t_end"] for r in res) - min(r["t_start"] for r in res)
+    # baseline: the same requests serially from this process
+    stream = torch.cuda.current_stream()
+    ref = []
+    for _ in range(2):  # the first pass warms up
+        ref = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in range(n_req):
+            for E, (_, pts) in zip(envs, insts):
+                v = E.eval(torch.from_numpy(pts).cuda(), stream=stream).cpu().numpy()
+                if r == n_req - 1:
+                    ref.append(v)
+        t_serial = time.perf_counter() - t0
+    diff = max(float(np.abs(r["V"] - v).max()) for r, v in zip(res, ref))
+    for E in envs:
+        E.close()
+    rep = {
+        "workload": f"{n_clients} client processes, each its own instance (atoms "
+                    f"{min(e.n_nuclei for e, _ in insts)}-{max(e.n_nuclei for e, _ in insts)}), "
+                    f"{n_req} requests of {n_pts} host points, FP32C",
+        "shared_point_pairs_per_s": work / t_span,
+        "serial_point_pairs_per_s": work / t_serial,
+        "speedup_vs_serial": t_serial / t_span,
+        "rounds": stats["rounds"], "requests": stats["requests"],
+        "requests_per_round": stats["requests"] / max(stats["rounds"], 1),
+        "max_abs_diff_vs_serial": diff,
+    }
+    log(f"[bench] shared GPU: {n_clients} clients, {work / t_span:.4g} pp/s vs serial {work / t_serial:.4g} "
+        f"({t_serial / t_span:.2f}x), {rep['requests_per_round']:.1f} requests per launch, max diff {diff:.2e}")
+    return rep
+
+
 def cells_leg(torch, envpot, synth, steps, warmup):
     """The paper's own form of the environment: 19 nuclei and 268,398
     point-charge cells.  Batched throughput (131,072 points per call) and the
@@ -222,6 +286,8 @@ def main():
                     help="skip the cell-sum leg (the paper's own form of the environment)")
     ap.add_argument("--no-field", action="store_true",
                     help="skip the field leg (E = -grad V with V on the same workload)")
+    ap.add_argument("--no-shared", action="store_true",
+                    help="skip the shared-GPU leg (client processes feeding one server)")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the learned-surrogate leg (1000-atom surrogate workload)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -286,6 +352,9 @@ def main():
     if not args.no_cells:
         cells = cells_leg(torch, envpot, synth, args.steps, args.warmup)
         paths["cells"] = cells["report"]
+
+    if not args.no_shared:
+        paths["shared"] = shared_leg(torch, envpot, synth)
 
     sur = None
     if not args.no_surrogate and "fp32c" in args.paths.split(","):
