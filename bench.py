@@ -346,6 +346,18 @@ def main():
             fields[prec] = fout.cpu().numpy()
             log(f"[bench] {prec} field: {fms:.3f} ms/step, {n * npairs / (fms * 1e-3):.4g} pp/s, "
                 f"{fflops / (fms * 1e-3) / 1e12:.1f} TFLOP/s algorithmic")
+        # a new density with the same blocks (each fragment block rescaled),
+        # refolded on the device, against building the handle again
+        rowp, col, val = env.density_csr(None)
+        P2 = (rowp, col, val * 1.05)
+        t_upd = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            E.update_density(P2)
+            t_upd.append(time.perf_counter() - t0)
+        paths[prec]["density_update_ms"] = float(np.median(t_upd)) * 1e3
+        log(f"[bench] {prec} density update: {paths[prec]['density_update_ms']:.1f} ms "
+            f"(create {t_create * 1e3:.0f} ms)")
         E.close()
 
     cells = None

@@ -160,6 +160,22 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
 env_status env_potential_eval(env_potential* h, const double* points, int64_t n,
                               double* out, void* stream);
 
+/* Replace the environment's density matrix, keeping its geometry and basis
+ * (an environment whose density changes from step to step, e.g. the
+ * self-consistent fragment densities of FMO, Sec. II.A).  The pair list
+ * (screening, order, same-centre clusters, splits) does not depend on the
+ * density values, so the device refolds every pair's Hermite density and
+ * far-field coefficients from the new P in place; with ENV_NEUTRALIZE the
+ * per-fragment scaling is recomputed.  P: dense or CSR as at create, same
+ * nbf; every nonzero block must be one that was nonzero at create (blocks
+ * may become zero).  Synchronous on `stream`; no evaluation of h may run
+ * meanwhile.  env_info.electrons is updated; screened_bound keeps the
+ * create-time value.
+ * Errors: ENV_E_ARG (nbf, format, non-finite or asymmetric P, a new
+ * nonzero block), ENV_E_STATE (build-only handle), ENV_E_UNSUPPORTED (more
+ * than 32767 primitives in a shell), ENV_E_DEVICE. */
+env_status env_potential_update_density(env_potential* h, const env_density* P, void* stream);
+
 /* The field E = -grad V together with V (an extension of the paper's
  * quantity, Sec. II.B, Eq. ElectrostaticField: the force on a unit positive
  * charge, whose negative is the electron's drift term).  For a pair the

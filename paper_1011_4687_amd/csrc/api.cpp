@@ -36,6 +36,8 @@ void free_device(env_potential* h) {
     (void)hipFree(h->d_boys);
     (void)hipFree(h->d_boys_field);
     h->d_boys_field = nullptr;
+    free_update_state(h->upd);
+    h->upd = nullptr;
     h->d_rec = nullptr;
     h->d_segs = nullptr;
     h->d_split = nullptr;
@@ -151,8 +153,9 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
     h->device = device;
     h->precision = opt.precision;
     env_status st;
+    PairSources src;  // kept for the density update tables of device handles
     try {
-        st = build_pair_list(nuclei, n_nuclei, shells, n_shells, P, opt, h->host);
+        st = build_pair_list(nuclei, n_nuclei, shells, n_shells, P, opt, h->host, build_only ? nullptr : &src);
     } catch (const std::bad_alloc&) {
         st = ENV_E_NOMEM;
     } catch (...) {
@@ -187,8 +190,9 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
     }
     const bool fp64 = h->precision == ENV_PREC_FP64;
     Layout lay;
+    LayoutMap lmap;
     try {
-        pack_layout(pl, fp64, h->bp, (opt.flags & ENV_NO_MERGE) == 0, lay);
+        pack_layout(pl, fp64, h->bp, (opt.flags & ENV_NO_MERGE) == 0, lay, build_only ? nullptr : &lmap);
     } catch (const std::bad_alloc&) {
         delete h;
         return ENV_E_NOMEM;
@@ -228,6 +232,14 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
         if (st == ENV_OK) {
             if (fp64) st = upload(tf64, reinterpret_cast<double**>(&h->d_boys_field), h->device_bytes);
             else st = upload(tf32, reinterpret_cast<float**>(&h->d_boys_field), h->device_bytes);
+        }
+        if (st == ENV_OK) {
+            try {
+                h->upd = make_update_state(pl, src, lmap, &st);
+            } catch (const std::bad_alloc&) {
+                st = ENV_E_NOMEM;
+            }
+            if (h->upd) h->device_bytes += h->upd->device_bytes;
         }
     }
     if (st != ENV_OK) {

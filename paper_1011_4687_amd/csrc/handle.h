@@ -5,6 +5,7 @@
 
 #include "envpot_internal.h"
 #include "field_internal.h"
+#include "update_internal.h"
 
 struct env_potential {
     int device = -1;
@@ -22,6 +23,7 @@ struct env_potential {
     void* d_boys = nullptr;
     void* d_boys_field = nullptr;       // Boys table of the field (one order more)
     envpot::FieldParams fp{};
+    envpot::UpdateState* upd = nullptr;  // density update tables (device)
     int64_t seg_off[envpot::kMaxSplitLog2 + 1] = {};    // per split factor 2^k: first segment
     int64_t split_off[envpot::kMaxSplitLog2 + 1] = {};  // per split factor 2^k: first offset
     int64_t device_bytes = 0;

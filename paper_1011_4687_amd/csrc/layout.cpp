@@ -14,6 +14,7 @@
 #include <utility>
 
 #include "envpot_internal.h"
+#include "update_internal.h"
 
 namespace envpot {
 
@@ -84,7 +85,17 @@ struct Cluster {
 }  // namespace
 
 void pack_layout(const PairList& pl, bool fp64, const BoysParams& bp, bool merge, Layout& out) {
+    pack_layout(pl, fp64, bp, merge, out, nullptr);
+}
+
+void pack_layout(const PairList& pl, bool fp64, const BoysParams& bp, bool merge, Layout& out,
+                 LayoutMap* map) {
     const double* w = fp64 ? kCost64 : kCost32;
+    if (map) {
+        *map = LayoutMap();
+        map->pair_word.assign(pl.L.size(), -1);
+        map->cl_begin.push_back(0);
+    }
     out.rec.clear();
     out.base.clear();
     out.unit_cost.clear();
@@ -152,7 +163,10 @@ void pack_layout(const PairList& pl, bool fp64, const BoysParams& bp, bool merge
             s.L = pl.L[ord[i]];
             s.n_pairs = int32_t(j - i);
             s.rec_off = int64_t(out.rec.size());
-            for (size_t q = i; q < j; ++q) append_pair(pl, ord[q], fp64, bp, out.rec);
+            for (size_t q = i; q < j; ++q) {
+                if (map) map->pair_word[ord[q]] = int64_t(out.rec.size());
+                append_pair(pl, ord[q], fp64, bp, out.rec);
+            }
             out.base.push_back(s);
             out.unit_cost.push_back(w[s.L]);
             i = j;
@@ -204,6 +218,12 @@ void pack_layout(const PairList& pl, bool fp64, const BoysParams& bp, bool merge
                     for (int L = 0; L <= kLMax; ++L) mask |= cnt[L] ? (1u << L) : 0u;
                     const int64_t k0 = c.members[0];
                     const size_t o = out.rec.size();
+                    if (map) {
+                        map->cl_word.push_back(int64_t(o));
+                        map->cl_L.push_back(Lc);
+                        map->cl_members.insert(map->cl_members.end(), c.members.begin(), c.members.end());
+                        map->cl_begin.push_back(int64_t(map->cl_members.size()));
+                    }
                     if (fp64) {
                         out.rec.resize(o + cl64_words(Lc), 0u);
                         double* r = reinterpret_cast<double*>(&out.rec[o]);
@@ -240,9 +260,12 @@ void pack_layout(const PairList& pl, bool fp64, const BoysParams& bp, bool merge
                 i = j;
             }
             for (const Cluster& c : clusters)
-                for (int64_t k : c.members) append_pair(pl, k, fp64, bp, out.rec);
+                for (int64_t k : c.members) {
+                    if (map) map->pair_word[k] = int64_t(out.rec.size());
+                    append_pair(pl, k, fp64, bp, out.rec);
+                }
             if (out.rec.size() > size_t(UINT32_MAX)) {  // member offsets are 32-bit words
-                pack_layout(pl, fp64, bp, false, out);
+                pack_layout(pl, fp64, bp, false, out, map);
                 return;
             }
         }

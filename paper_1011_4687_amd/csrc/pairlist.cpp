@@ -22,6 +22,7 @@
 #include <xmmintrin.h>
 
 #include "envpot_internal.h"
+#include "update_internal.h"
 
 namespace envpot {
 namespace {
@@ -99,6 +100,7 @@ struct Block {   // one unordered shell pair I <= J with its density block
 struct Bucket {  // pairs of one group and one L, appended in build order
     std::vector<double> rec;  // per pair: Px, Py, Pz, p, D[ncomp(L)]
     std::vector<int32_t> atom;  // per pair: the atom of both shells, or -1 (two centres)
+    std::vector<int32_t> src;   // per pair (when sources are kept): block, ia, ib
     int64_t n = 0;
 };
 
@@ -107,6 +109,7 @@ struct GroupOut {
     int64_t n_unscreened = 0;
     double screened_bound = 0.0;
     double dropped_charge = 0.0;  // electron count of screened-out pairs
+    std::vector<int32_t> drop;    // screened-out pairs (when sources are kept): block, ia, ib
 };
 
 bool finite(double x) { return std::isfinite(x); }
@@ -131,6 +134,13 @@ const HIndex& hidx() {
 env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
                            const env_shell* shells, int32_t n_shells,
                            const env_density* P, const env_options& opt, PairList& out) {
+    return build_pair_list(nuclei, n_nuclei, shells, n_shells, P, opt, out, nullptr);
+}
+
+env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
+                           const env_shell* shells, int32_t n_shells,
+                           const env_density* P, const env_options& opt, PairList& out,
+                           PairSources* src) {
     const char* tenv = std::getenv("ENVPOT_TIMING");
     const bool timing = tenv && *tenv && *tenv != '0';
     auto tlast = std::chrono::steady_clock::now();
@@ -349,6 +359,7 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
                     hermite_coefs(lI, lJ, a, b, A[0], Bc[0], Ex);
                     hermite_coefs(lI, lJ, a, b, A[1], Bc[1], Ey);
                     hermite_coefs(lI, lJ, a, b, A[2], Bc[2], Ez);
+                    if (drop && src) go.drop.insert(go.drop.end(), {int32_t(bk), int32_t(ia), int32_t(ib)});
                     if (drop) {  // only its charge: sum P c N c N E_0 E_0 E_0 (pi/p)^{3/2}
                         double q = 0.0;
                         for (int x = 0; x < nI; ++x)
@@ -388,6 +399,7 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
                         bu.rec.push_back((a * A[2] + b * Bc[2]) / p);
                     }
                     bu.atom.push_back(one_centre ? SI.atom : -1);
+                    if (src) bu.src.insert(bu.src.end(), {int32_t(bk), int32_t(ia), int32_t(ib)});
                     bu.rec.push_back(p);
                     for (int k = 0; k < nc; ++k) bu.rec.push_back(D[k] * sc);
                     ++bu.n;
@@ -485,6 +497,11 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
     out.D.resize(gd[n_groups]);
     out.d_off[npairs] = gd[n_groups];
     std::vector<double> qg(n_groups, 0.0);
+    if (src) {
+        src->pair_blk.resize(npairs);
+        src->pair_ia.resize(npairs);
+        src->pair_ib.resize(npairs);
+    }
     lap("allocate");
     {
         std::atomic<int> next{0};
@@ -510,12 +527,18 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
                             out.p[k] = r[3];
                             out.atom1[k] = bu.atom[j];
                             out.d_off[k] = d;
+                            if (src) {
+                                src->pair_blk[k] = bu.src[3 * j];
+                                src->pair_ia[k] = bu.src[3 * j + 1];
+                                src->pair_ib[k] = bu.src[3 * j + 2];
+                            }
                             for (int c = 0; c < kNComp[L]; ++c) out.D[d + c] = r[4 + c];
                             d += kNComp[L];
                             q += r[4];
                         }
                         std::vector<double>().swap(bu.rec);
                         std::vector<int32_t>().swap(bu.atom);
+                        std::vector<int32_t>().swap(bu.src);
                     }
                     qg[g] = q;
                 }
@@ -523,6 +546,42 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
         for (auto& t : th) t.join();
     }
     for (int g = 0; g < n_groups; ++g) out.electrons += qg[g];
+    if (src) {
+        src->neutralize = neutralize;
+        src->blk_I.resize(blocks.size());
+        src->blk_J.resize(blocks.size());
+        for (size_t k = 0; k < blocks.size(); ++k) {
+            src->blk_I[k] = blocks[k].I;
+            src->blk_J[k] = blocks[k].J;
+        }
+        for (int g = 0; g < n_groups; ++g) {
+            const std::vector<int32_t>& dr = gout[g].drop;
+            for (size_t j = 0; j + 2 < dr.size(); j += 3) {
+                src->drop_blk.push_back(dr[j]);
+                src->drop_ia.push_back(dr[j + 1]);
+                src->drop_ib.push_back(dr[j + 2]);
+                src->drop_group.push_back(g);
+            }
+        }
+        src->shell_l.resize(n_shells);
+        src->shell_atom.resize(n_shells);
+        src->bf0.assign(bf0.begin(), bf0.end());
+        for (int s2 = 0; s2 < n_shells; ++s2) {
+            src->shell_l[s2] = shells[s2].l;
+            src->shell_atom[s2] = shells[s2].atom;
+        }
+        src->poff.assign(poff.begin(), poff.end());
+        src->noff.assign(noff.begin(), noff.end());
+        src->cscale = cscale;
+        src->cnorm = cnorm;
+        src->exps.resize(poff[n_shells]);
+        for (int s2 = 0; s2 < n_shells; ++s2)
+            for (int k = 0; k < shells[s2].nprim; ++k) src->exps[poff[s2] + k] = shells[s2].exponents[k];
+        src->atom_xyz.resize(3 * size_t(n_nuclei));
+        for (int a = 0; a < n_nuclei; ++a)
+            for (int c = 0; c < 3; ++c) src->atom_xyz[3 * size_t(a) + c] = nuclei[a].xyz[c];
+        src->group_charge = zg;
+    }
     lap("order");
     return ENV_OK;
 }

@@ -140,6 +140,8 @@ def lib():
         L.env_potential_eval.restype = c_int32
         L.env_potential_eval_field.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]
         L.env_potential_eval_field.restype = c_int32
+        L.env_potential_update_density.argtypes = [c_void_p, POINTER(env_density), c_void_p]
+        L.env_potential_update_density.restype = c_int32
         L.env_potential_eval_batched.argtypes = [POINTER(c_void_p), c_int32, POINTER(c_void_p),
                                                  POINTER(c_int64), POINTER(c_void_p), c_void_p]
         L.env_potential_eval_batched.restype = c_int32
@@ -364,23 +366,8 @@ class Environment:
             sh[s].atom, sh[s].l, sh[s].nprim = int(atom), int(l), int(ex.shape[0])
             sh[s].exponents, sh[s].coefs = _dp(ex), _dp(co)
         nbf = int(sum((l + 1) * (l + 2) // 2 for (_, l, _, _) in shells))
-        dens = env_density()
-        dens.nbf = nbf
-        if isinstance(P, tuple):
-            rowp, col, val = P
-            rowp = np.ascontiguousarray(rowp, dtype=np.int64)
-            col = np.ascontiguousarray(col, dtype=np.int32)
-            val = np.ascontiguousarray(val, dtype=np.float64)
-            self._keep += [rowp, col, val]
-            dens.format = ENV_DENSITY_CSR
-            dens.values = _dp(val)
-            dens.row_ptr = rowp.ctypes.data_as(POINTER(c_int64))
-            dens.col = col.ctypes.data_as(POINTER(c_int32))
-        else:
-            Pd = np.ascontiguousarray(P, dtype=np.float64)
-            self._keep.append(Pd)
-            dens.format = ENV_DENSITY_DENSE
-            dens.values = _dp(Pd)
+        self.nbf = nbf
+        dens = _density(P, nbf, self._keep)
         opt = env_options_default()
         opt.precision = PRECISIONS[precision]
         opt.device = int(device)
@@ -390,6 +377,24 @@ class Environment:
         self.precision = precision
         self.handle = env_potential_create(nuc, K, sh, len(shells), dens, opt)
         self._keep = None
+
+    def update_density(self, P, stream=None):
+        """Replace the density matrix (same nbf, no new nonzero blocks): the
+        device refolds every pair's Hermite density in place."""
+        keep = []
+        dens = _density(P, self.nbf, keep)
+        s = 0
+        if stream is not None:
+            s = stream.cuda_stream
+        else:
+            try:
+                import torch
+                s = torch.cuda.current_stream().cuda_stream
+            except Exception:
+                s = 0
+        st = lib().env_potential_update_density(c_void_p(self.handle), ctypes.byref(dens), c_void_p(s))
+        if st != ENV_OK:
+            raise EnvError(st, "env_potential_update_density")
 
     @classmethod
     def from_synth(cls, env, scale=None, **kw) -> "Environment":
@@ -723,6 +728,29 @@ def fourier_matrix(seed: int = 0, sigma: float = 1.0) -> np.ndarray:
     """64 frequency vectors b ~ N(0, sigma^2 I) (1/bohr)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.standard_normal((64, 3)) * sigma
+
+
+def _density(P, nbf: int, keep: list) -> "env_density":
+    """env_density of a dense (nbf, nbf) array or a CSR triple; the arrays
+    are appended to ``keep`` (they must live until the call returns)."""
+    dens = env_density()
+    dens.nbf = nbf
+    if isinstance(P, tuple):
+        rowp, col, val = P
+        rowp = np.ascontiguousarray(rowp, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        keep += [rowp, col, val]
+        dens.format = ENV_DENSITY_CSR
+        dens.values = _dp(val)
+        dens.row_ptr = rowp.ctypes.data_as(POINTER(c_int64))
+        dens.col = col.ctypes.data_as(POINTER(c_int32))
+    else:
+        Pd = np.ascontiguousarray(P, dtype=np.float64)
+        keep.append(Pd)
+        dens.format = ENV_DENSITY_DENSE
+        dens.values = _dp(Pd)
+    return dens
 
 
 class Server:

@@ -193,3 +193,11 @@ def test_server_and_client_argument_errors(tmp_path):
     with pytest.raises(E.EnvError) as ei:
         Server([h], "bad/name")
     assert ei.value.status == E.ENV_E_ARG
+
+
+def test_update_density_needs_device_handle():
+    env, shells = _tiny_args()
+    h = _build_only(env, shells, env.density_dense([1.0]))
+    with pytest.raises(E.EnvError) as ei:
+        h.update_density(env.density_dense([0.5]))
+    assert ei.value.status == E.ENV_E_STATE

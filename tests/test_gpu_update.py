@@ -1,0 +1,151 @@
+"""Incremental density update on the device (env_potential_update_density):
+after an update a handle evaluates exactly what a handle freshly created
+with the new density evaluates (to rounding), for both precisions, with
+same-centre clusters, with ENV_NEUTRALIZE, through a batched plan built
+before the update, and in the field; and the FP64 result matches the oracle."""
+import time
+
+import numpy as np
+import pytest
+
+from common import sample_indices
+
+pytestmark = pytest.mark.gpu
+
+_cache = {}
+
+
+def _mid():
+    if "mid" not in _cache:
+        from paper_1011_4687_amd import synth
+        env, pts = synth.workload("mid", n_points=8192)
+        _cache["mid"] = (env, pts)
+    return _cache["mid"]
+
+
+def _shells(env):
+    return [(s.atom, s.l, s.exponents, s.coefs) for s in env.shells]
+
+
+def _gpu(E, pts):
+    import torch
+    v = E.eval(torch.from_numpy(np.ascontiguousarray(pts)).cuda())
+    torch.cuda.synchronize()
+    return v.cpu().numpy()
+
+
+def _perturbed(env, seed):
+    """A new density with the same nonzero blocks: each fragment block rescaled
+    and a symmetric perturbation on its nonzero elements."""
+    from oracle import oracle as O
+    rng = np.random.default_rng(seed)
+    sc = O.neutral_scales(env) * rng.uniform(0.8, 1.2, env.n_fragments)
+    P = env.density_dense(sc)
+    mask = P != 0.0
+    N = rng.normal(size=P.shape)
+    N = 0.5 * (N + N.T)
+    return P + 0.02 * np.abs(P).max() * N * mask
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_update_matches_fresh_handle(precision):
+    from oracle import oracle as O
+    from paper_1011_4687_amd.envpot import Environment
+    print(f"[update] fresh vs updated {precision}", flush=True)
+    env, pts = _mid()
+    P1 = env.density_dense(O.neutral_scales(env))
+    P2 = _perturbed(env, 3)
+    E = Environment(env.xyz, env.Z, env.fragment, _shells(env), P1, precision=precision)
+    V1 = _gpu(E, pts)
+    t0 = time.perf_counter()
+    E.update_density(P2)
+    t_upd = time.perf_counter() - t0
+    V2 = _gpu(E, pts)
+    t0 = time.perf_counter()
+    F = Environment(env.xyz, env.Z, env.fragment, _shells(env), P2, precision=precision)
+    t_new = time.perf_counter() - t0
+    print(f"[update] {precision}: update {t_upd * 1e3:.1f} ms, create {t_new * 1e3:.1f} ms", flush=True)
+    assert F.info()["n_pairs"] == E.info()["n_pairs"]
+    assert abs(E.info()["electrons"] - F.info()["electrons"]) <= 1e-10 * F.info()["electrons"]
+    Vf = _gpu(F, pts)
+    d = np.abs(V2 - Vf).max()
+    print(f"[update] {precision}: max |updated - fresh| {d:.3e}", flush=True)
+    assert d <= (1e-11 if precision == "fp64" else 2e-6), d
+    assert np.abs(V2 - V1).max() > 1e-3  # the density did change
+    idx = sample_indices(len(pts), 8)
+    screen = precision == "fp64"
+    Vo, _, _, A = O.potential_raw(env.xyz, env.Z, env.shell_arrays(), P2, pts[idx], screen=screen)
+    if precision == "fp64":
+        assert np.all(np.abs(V2[idx] - Vo) <= 1e-12 * A), (np.abs(V2[idx] - Vo) / A).max()
+    else:
+        assert np.abs(V2[idx] - Vo).max() <= 1e-5
+    # and back
+    E.update_density(P1)
+    V3 = _gpu(E, pts)
+    assert np.abs(V3 - V1).max() <= (1e-11 if precision == "fp64" else 2e-6)
+    E.close()
+    F.close()
+
+
+def test_update_neutralize_batched_plan_and_field():
+    import torch
+    from oracle import oracle as O
+    from paper_1011_4687_amd import envpot
+    from paper_1011_4687_amd.envpot import Environment
+    print("[update] neutralize, batched plan, field", flush=True)
+    env, pts = _mid()
+    P1 = env.density_dense(np.ones(env.n_fragments))
+    P2 = _perturbed(env, 4)
+    E = Environment(env.xyz, env.Z, env.fragment, _shells(env), P1, precision="fp64", neutralize=True)
+    x = torch.from_numpy(pts).cuda()
+    out = torch.empty(len(pts), dtype=torch.float64, device="cuda")
+    plan = envpot.Batch([E])
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    plan.eval([x], [out], stream=stream)
+    stream.synchronize()
+    E.update_density(P2)
+    assert abs(E.info()["electrons"] - env.Z.sum()) <= 1e-9 * env.Z.sum()
+    F = Environment(env.xyz, env.Z, env.fragment, _shells(env), P2, precision="fp64", neutralize=True)
+    Vf = _gpu(F, pts)
+    plan.eval([x], [out], stream=stream)
+    stream.synchronize()
+    assert np.abs(out.cpu().numpy() - Vf).max() <= 1e-11
+    fld = E.eval_field(x).cpu().numpy()
+    assert np.abs(fld[:, 0] - Vf).max() <= 1e-11
+    ff = F.eval_field(x).cpu().numpy()
+    assert np.abs(fld - ff).max() <= 1e-11
+    plan.close()
+    E.close()
+    F.close()
+
+
+def test_update_errors():
+    from oracle import oracle as O
+    from paper_1011_4687_amd.envpot import ENV_E_ARG, Environment, EnvError
+    print("[update] errors", flush=True)
+    env, pts = _mid()
+    P1 = env.density_dense(O.neutral_scales(env))
+    E = Environment(env.xyz, env.Z, env.fragment, _shells(env), P1, precision="fp32c")
+    bad = P1.copy()
+    i, j = 0, env.nbf - 1  # first and last basis functions: different fragments
+    bad[i, j] = bad[j, i] = 1e-3
+    with pytest.raises(EnvError) as ei:
+        E.update_density(bad)  # a block the build never saw
+    assert ei.value.status == ENV_E_ARG
+    asym = P1.copy()
+    nz = np.argwhere(P1 != 0)
+    a, b = next((p, q) for p, q in nz if p != q)
+    asym[a, b] += 0.1
+    with pytest.raises(EnvError) as ei:
+        E.update_density(asym)
+    assert ei.value.status == ENV_E_ARG
+    with pytest.raises(EnvError) as ei:
+        E.update_density(P1[:-1, :-1])
+    assert ei.value.status == ENV_E_ARG
+    # the handle still evaluates the old density
+    V = _gpu(E, pts[:256])
+    F = Environment(env.xyz, env.Z, env.fragment, _shells(env), P1, precision="fp32c")
+    assert np.abs(V - _gpu(F, pts[:256])).max() <= 2e-6
+    E.close()
+    F.close()
