@@ -2,7 +2,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -148,12 +150,27 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
         if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return ENV_E_DEVICE;
     }
 
+    const char* tenv = std::getenv("ENVPOT_TIMING");
+    const bool timing = tenv && *tenv && *tenv != '0';
+    auto tlast = std::chrono::steady_clock::now();
+    auto lap = [&](const char* what) {
+        if (!timing) return;
+        const auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[envpot create] %-22s %8.3f s\n", what,
+                     std::chrono::duration<double>(now - tlast).count());
+        tlast = now;
+    };
     env_potential* h = new (std::nothrow) env_potential();
     if (!h) return ENV_E_NOMEM;
     h->device = device;
     h->precision = opt.precision;
     env_status st;
     PairSources src;  // kept for the density update tables of device handles
+    // device handles fold the density on the device (the update kernels)
+    // unless a shell has more primitives than the update tables index
+    bool fits = true;
+    for (int32_t s = 0; s < n_shells && shells; ++s) fits = fits && shells[s].nprim <= 32767;
+    src.device_fold = !build_only && fits;
     try {
         st = build_pair_list(nuclei, n_nuclei, shells, n_shells, P, opt, h->host, build_only ? nullptr : &src);
     } catch (const std::bad_alloc&) {
@@ -165,6 +182,7 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
         delete h;
         return st;
     }
+    lap("pair list");
     const PairList& pl = h->host;
     env_info& in = h->info;
     in.nbf = pl.nbf;
@@ -197,6 +215,7 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
         delete h;
         return ENV_E_NOMEM;
     }
+    lap("layout");
     in.n_clusters = lay.n_clusters;
     in.n_cluster_members = lay.n_members;
     std::vector<Segment> allsegs;
@@ -211,6 +230,7 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
         allsplit.insert(allsplit.end(), split.begin(), split.end());
         if (k == 0) in.n_segments = int32_t(segs.size());
     }
+    lap("splits");
     if (build_only) {
         *out = h;
         return ENV_OK;
@@ -233,6 +253,7 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
             if (fp64) st = upload(tf64, reinterpret_cast<double**>(&h->d_boys_field), h->device_bytes);
             else st = upload(tf32, reinterpret_cast<float**>(&h->d_boys_field), h->device_bytes);
         }
+        lap("upload");
         if (st == ENV_OK) {
             try {
                 h->upd = make_update_state(pl, src, lmap, &st);
@@ -240,7 +261,12 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
                 st = ENV_E_NOMEM;
             }
             if (h->upd) h->device_bytes += h->upd->device_bytes;
+            else if (st == ENV_OK && src.device_fold) st = ENV_E_DEVICE;
         }
+        lap("update tables");
+        // the first fold of the density, on the device
+        if (st == ENV_OK && src.device_fold) st = env_potential_update_density(h, P, nullptr);
+        lap("device fold");
     }
     if (st != ENV_OK) {
         free_device(h);

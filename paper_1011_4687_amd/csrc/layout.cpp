@@ -101,6 +101,12 @@ void pack_layout(const PairList& pl, bool fp64, const BoysParams& bp, bool merge
     out.unit_cost.clear();
     out.n_clusters = out.n_members = 0;
     const int64_t npairs = int64_t(pl.L.size());
+    {
+        // every pair record once, plus room for the cluster records
+        int64_t words = 0;
+        for (int64_t k = 0; k < npairs; ++k) words += fp64 ? rec64_words(pl.L[k]) : rec32_words(pl.L[k]);
+        out.rec.reserve(size_t(words + words / 8 + 64));
+    }
 
     // band edges of log(r2far) over all one-centre pairs
     double lo = std::numeric_limits<double>::infinity(), hi = -lo;
@@ -148,9 +154,16 @@ void pack_layout(const PairList& pl, bool fp64, const BoysParams& bp, bool merge
                 }
             }
         }
-        std::sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) {
-            return pl.L[x] != pl.L[y] ? pl.L[x] < pl.L[y] : x < y;
-        });
+        {
+            // order by (L, index): mark the group's ordinary pairs, then one
+            // pass per L in index order
+            std::vector<uint8_t> in_ord(size_t(e - b), 0);
+            for (int64_t k : ord) in_ord[size_t(k - b)] = 1;
+            ord.clear();
+            for (int L = 0; L <= kLMax; ++L)
+                for (int64_t k = b; k < e; ++k)
+                    if (in_ord[size_t(k - b)] && pl.L[k] == L) ord.push_back(k);
+        }
         std::stable_sort(clusters.begin(), clusters.end(),
                          [](const Cluster& x, const Cluster& y) { return x.L < y.L; });
 

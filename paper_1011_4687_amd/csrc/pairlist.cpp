@@ -322,6 +322,9 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
     lap("symmetry, grouping");
     std::vector<GroupOut> gout(n_groups);
     const bool neutralize = (opt.flags & ENV_NEUTRALIZE) != 0;
+    // the fold into D (and the charges of screened-out pairs) is left to the
+    // device: D stays zero here
+    const bool device_fold = src && src->device_fold;
     const HIndex& HX = hidx();
     auto work = [&](int g) {
         GroupOut& go = gout[g];
@@ -356,10 +359,13 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
                     const bool drop = screen && bound < thr;
                     if (drop) go.screened_bound += w * B.maxabs * bound;
                     if (drop && !neutralize) continue;
-                    hermite_coefs(lI, lJ, a, b, A[0], Bc[0], Ex);
-                    hermite_coefs(lI, lJ, a, b, A[1], Bc[1], Ey);
-                    hermite_coefs(lI, lJ, a, b, A[2], Bc[2], Ez);
                     if (drop && src) go.drop.insert(go.drop.end(), {int32_t(bk), int32_t(ia), int32_t(ib)});
+                    if (drop && device_fold) continue;
+                    if (!device_fold) {
+                        hermite_coefs(lI, lJ, a, b, A[0], Bc[0], Ex);
+                        hermite_coefs(lI, lJ, a, b, A[1], Bc[1], Ey);
+                        hermite_coefs(lI, lJ, a, b, A[2], Bc[2], Ez);
+                    }
                     if (drop) {  // only its charge: sum P c N c N E_0 E_0 E_0 (pi/p)^{3/2}
                         double q = 0.0;
                         for (int x = 0; x < nI; ++x)
@@ -370,7 +376,7 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
                         continue;
                     }
                     for (int k = 0; k < nc; ++k) D[k] = 0.0;
-                    for (int x = 0; x < nI; ++x) {
+                    for (int x = 0; x < (device_fold ? 0 : nI); ++x) {
                         for (int y = 0; y < nJ; ++y) {
                             const double pw = B.w[x][y];
                             if (pw == 0.0) continue;

@@ -31,6 +31,7 @@ struct PairSources {
     std::vector<double> cscale, exps, cnorm, atom_xyz;
     std::vector<double> group_charge;  // nuclear charge per group
     bool neutralize = false;
+    bool device_fold = false;  // set by the caller: leave D (and charges) to the device
 };
 
 // Where each pair's record sits in a Layout, and the clusters' members.
