@@ -232,21 +232,29 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
     std::unordered_map<uint64_t, int> bidx;
     std::vector<std::array<double, 36>> raw;
     std::vector<std::pair<int, int>> rawkey;
+    uint64_t last_key = ~uint64_t(0);
+    int last_k = -1;  // consecutive elements of a row mostly share a block
     auto put = [&](int mu, int nu, double v) -> bool {
         if (!finite(v)) return false;
         if (v == 0.0) return true;
         const int I = shell_of_bf[mu], J = shell_of_bf[nu];
         const uint64_t key = (uint64_t(uint32_t(I)) << 32) | uint32_t(J);
-        auto it = bidx.find(key);
         int k;
-        if (it == bidx.end()) {
-            k = int(raw.size());
-            bidx.emplace(key, k);
-            raw.emplace_back();
-            raw.back().fill(0.0);
-            rawkey.emplace_back(I, J);
+        if (key == last_key) {
+            k = last_k;
         } else {
-            k = it->second;
+            auto it = bidx.find(key);
+            if (it == bidx.end()) {
+                k = int(raw.size());
+                bidx.emplace(key, k);
+                raw.emplace_back();
+                raw.back().fill(0.0);
+                rawkey.emplace_back(I, J);
+            } else {
+                k = it->second;
+            }
+            last_key = key;
+            last_k = k;
         }
         raw[k][(mu - bf0[I]) * 6 + (nu - bf0[J])] += v;
         return true;
