@@ -58,9 +58,9 @@ env_status env_potential_eval_field(env_potential* h, const double* points, int6
     if (!points || !out) return ENV_E_ARG;
     if (!h->on_device) return ENV_E_STATE;
     DeviceGuard g(h->device);
-    // points per lane at four waves per SIMD (mid workload: FP32C 51 ms with
-    // two against 63 ms with one; FP64 the same 84 ms with either)
-    int np = h->precision == ENV_PREC_FP64 ? 1 : 2;
+    // two points per lane at four waves per SIMD (mid workload: FP32C 46 ms
+    // against 53 ms with one; FP64 79 against 81 ms)
+    int np = 2;
     if (const char* e = std::getenv("ENVPOT_FIELD_NP")) {  // tuning override
         const int v = std::atoi(e);
         if (v == 1 || v == 2) np = v;

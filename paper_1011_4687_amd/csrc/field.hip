@@ -152,11 +152,38 @@ __device__ __forceinline__ void near_f64(const GLB uint32_t* __restrict__ r, dou
 }
 
 // FP32C pairs of one L; ge[k] += (v, g) of every pair at point k.
+// The part of a pair record the far field needs.
+template <int L>
+struct FHead {
+    double px, py, pz;
+    float r2far;
+    float h[kNComp[L]];
+};
+
+template <int L>
+__device__ __forceinline__ void load_fhead(const GLB uint32_t* __restrict__ r, FHead<L>& o) {
+    const GLB double* rd = reinterpret_cast<const GLB double*>(r);
+    const GLB float* rf = reinterpret_cast<const GLB float*>(r + 6);
+    o.px = rd[0];
+    o.py = rd[1];
+    o.pz = rd[2];
+    o.r2far = rf[0];
+#pragma unroll
+    for (int c = 0; c < kNComp[L]; ++c) o.h[c] = rf[3 + c];
+}
+
+// Prefetch the next head while two heads fit in SGPRs (L <= 2).
+template <int L>
+constexpr bool kFPipelined = L <= 2;
+
 template <int L, int NP>
 __device__ __forceinline__ void pairs_f32(const GLB uint32_t* __restrict__ rec, int npairs, const double* cx,
                                           const double* cy, const double* cz, const float* tab, float ratio,
                                           double (*ge)[4]) {
     constexpr int RW = rec32_words(L);
+    if (npairs <= 0) return;
+    FHead<L> cur;
+    if constexpr (kFPipelined<L>) load_fhead<L>(rec, cur);
     for (int i0 = 0; i0 < npairs; i0 += kFTile) {
         const int i1 = min(i0 + kFTile, npairs);
         float t[NP][4];
@@ -166,13 +193,12 @@ __device__ __forceinline__ void pairs_f32(const GLB uint32_t* __restrict__ rec, 
             for (int c = 0; c < 4; ++c) t[k][c] = 0.0f;
         for (int i = i0; i < i1; ++i) {
             const GLB uint32_t* r = rec + (int64_t)i * RW;
-            const GLB double* rd = reinterpret_cast<const GLB double*>(r);
-            const GLB float* rf = reinterpret_cast<const GLB float*>(r + 6);
-            const double px = rd[0], py = rd[1], pz = rd[2];
-            const float r2f = rf[0] * ratio;
-            float h[kNComp[L]];
-#pragma unroll
-            for (int c = 0; c < kNComp[L]; ++c) h[c] = rf[3 + c];
+            FHead<L> nxt;
+            if constexpr (kFPipelined<L>) load_fhead<L>(rec + (int64_t)min(i + 1, npairs - 1) * RW, nxt);
+            else load_fhead<L>(r, cur);
+            const double px = cur.px, py = cur.py, pz = cur.pz;
+            const float r2f = cur.r2far * ratio;
+            const float* h = cur.h;
             float X[NP], Y[NP], Z[NP], r2[NP];
             bool nearp = false;
 #pragma unroll
@@ -199,6 +225,7 @@ __device__ __forceinline__ void pairs_f32(const GLB uint32_t* __restrict__ rec, 
                     }
                 }
             }
+            if constexpr (kFPipelined<L>) cur = nxt;
         }
 #pragma unroll
         for (int k = 0; k < NP; ++k)
@@ -207,19 +234,40 @@ __device__ __forceinline__ void pairs_f32(const GLB uint32_t* __restrict__ rec, 
     }
 }
 
+template <int L>
+struct FHead64 {
+    double px, py, pz, r2far;
+    double h[kNComp[L]];
+};
+
+template <int L>
+__device__ __forceinline__ void load_fhead64(const GLB uint32_t* __restrict__ r, FHead64<L>& o) {
+    const GLB double* rd = reinterpret_cast<const GLB double*>(r);
+    o.px = rd[0];
+    o.py = rd[1];
+    o.pz = rd[2];
+    o.r2far = rd[3];
+#pragma unroll
+    for (int c = 0; c < kNComp[L]; ++c) o.h[c] = rd[kRec64Head + c];
+}
+
 template <int L, int NP>
 __device__ __forceinline__ void pairs_f64(const GLB uint32_t* __restrict__ rec, int npairs, const double* cx,
                                           const double* cy, const double* cz, const GLB double* __restrict__ tab,
                                           double ratio, double (*ge)[4]) {
     constexpr int RW = rec64_words(L);
+    constexpr bool kPipe = L <= 1;  // two FP64 heads fit in SGPRs
+    if (npairs <= 0) return;
+    FHead64<L> cur;
+    if constexpr (kPipe) load_fhead64<L>(rec, cur);
     for (int i = 0; i < npairs; ++i) {
         const GLB uint32_t* r = rec + (int64_t)i * RW;
-        const GLB double* rd = reinterpret_cast<const GLB double*>(r);
-        const double px = rd[0], py = rd[1], pz = rd[2];
-        const double r2f = rd[3] * ratio;
-        double h[kNComp[L]];
-#pragma unroll
-        for (int c = 0; c < kNComp[L]; ++c) h[c] = rd[kRec64Head + c];
+        FHead64<L> nxt;
+        if constexpr (kPipe) load_fhead64<L>(rec + (int64_t)min(i + 1, npairs - 1) * RW, nxt);
+        else load_fhead64<L>(r, cur);
+        const double px = cur.px, py = cur.py, pz = cur.pz;
+        const double r2f = cur.r2far * ratio;
+        const double* h = cur.h;
         double X[NP], Y[NP], Z[NP], r2[NP];
         bool nearp = false;
 #pragma unroll
@@ -246,6 +294,7 @@ __device__ __forceinline__ void pairs_f64(const GLB uint32_t* __restrict__ rec, 
                 }
             }
         }
+        if constexpr (kPipe) cur = nxt;
     }
 }
 
