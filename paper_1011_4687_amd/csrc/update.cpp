@@ -325,16 +325,22 @@ env_status env_potential_update_density(env_potential* h, const env_density* P, 
     A.rec = h->d_rec;
     A.charge = u->d_charge;
     A.fp64 = h->precision == ENV_PREC_FP64 ? 1 : 0;
+    // host buffers below are read or written by copies on `st`: every exit
+    // waits for the stream first
+    auto fail = [&]() {
+        (void)hipStreamSynchronize(st);
+        return ENV_E_DEVICE;
+    };
     if (!W.empty() && hipMemcpyAsync(u->d_W, W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice, st) !=
                           hipSuccess)
-        return ENV_E_DEVICE;
+        return fail();
     // electron counts per group; with ENV_NEUTRALIZE the scale to the group's
     // nuclear charge (screened-out pairs included, as at create)
     std::vector<double> q(size_t(u->n_pairs + u->n_drop));
-    if (launch_update_charges(A, stream) != 0) return ENV_E_DEVICE;
+    if (launch_update_charges(A, stream) != 0) return fail();
     if (!q.empty() && hipMemcpyAsync(q.data(), u->d_charge, q.size() * sizeof(double), hipMemcpyDeviceToHost, st) !=
                           hipSuccess)
-        return ENV_E_DEVICE;
+        return fail();
     if (hipStreamSynchronize(st) != hipSuccess) return ENV_E_DEVICE;
     lap("upload, charges");
     std::vector<double> qkept(u->n_groups, 0.0), qall(u->n_groups, 0.0), scale(std::max(u->n_groups, 1), 1.0);
@@ -349,10 +355,10 @@ env_status env_potential_update_density(env_potential* h, const env_density* P, 
     }
     if (hipMemcpyAsync(u->d_scale, scale.data(), scale.size() * sizeof(double), hipMemcpyHostToDevice, st) !=
         hipSuccess)
-        return ENV_E_DEVICE;
-    if (launch_update_pairs(A, stream) != 0) return ENV_E_DEVICE;
-    if (launch_update_members(A, stream) != 0) return ENV_E_DEVICE;
-    if (launch_update_clusters(A, stream) != 0) return ENV_E_DEVICE;
+        return fail();
+    if (launch_update_pairs(A, stream) != 0) return fail();
+    if (launch_update_members(A, stream) != 0) return fail();
+    if (launch_update_clusters(A, stream) != 0) return fail();
     if (hipStreamSynchronize(st) != hipSuccess) return ENV_E_DEVICE;
     lap("scale, records");
     h->info.electrons = electrons;
