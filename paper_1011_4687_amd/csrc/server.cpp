@@ -26,6 +26,7 @@
 #include <cerrno>
 #include <chrono>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <thread>
@@ -102,6 +103,9 @@ struct env_server {
     std::thread worker;
     std::atomic<bool> running{false};
     std::atomic<int64_t> rounds{0}, requests{0}, points{0}, busy_ns{0}, errors{0};
+    // batched plans by request set ((slot, environment) per request): a set
+    // that comes back with the same point counts replays its captured graph
+    std::map<std::vector<int64_t>, env_batch*> plans;
 };
 
 struct env_client {
@@ -152,8 +156,20 @@ void serve_round(env_server* S, std::vector<int>& ready) {
         ids.push_back(s);
     }
     if (ids.empty()) return;
-    env_status st = env_potential_eval_batched(hs.data(), int32_t(hs.size()), pts.data(), ns.data(), outs.data(),
-                                               S->stream);
+    std::vector<int64_t> key(ids.size());
+    for (size_t k = 0; k < ids.size(); ++k) key[k] = (int64_t(ids[k]) << 32) | slot_at(S->base, h, ids[k])->env;
+    auto it = S->plans.find(key);
+    env_status st = ENV_OK;
+    if (it == S->plans.end()) {
+        if (S->plans.size() >= 256) {  // bounded cache
+            for (auto& kv : S->plans) env_batch_destroy(kv.second);
+            S->plans.clear();
+        }
+        env_batch* b = nullptr;
+        st = env_batch_create(hs.data(), int32_t(hs.size()), &b);
+        if (st == ENV_OK) it = S->plans.emplace(key, b).first;
+    }
+    if (st == ENV_OK) st = env_batch_eval(it->second, pts.data(), ns.data(), outs.data(), S->stream);
     for (size_t k = 0; k < ids.size(); ++k) {
         SlotHeader* sl = slot_at(S->base, h, ids[k]);
         if (st == ENV_OK && hipMemcpyAsync(slot_out(sl, maxp), outs[k], size_t(ns[k]) * sizeof(double),
@@ -352,6 +368,8 @@ void env_server_destroy(env_server* S) {
     if (!S) return;
     S->running.store(false, std::memory_order_release);
     if (S->worker.joinable()) S->worker.join();
+    for (auto& kv : S->plans) env_batch_destroy(kv.second);
+    S->plans.clear();
     // requests still waiting get an error and clients see the server gone
     for (int s = 0; s < S->hdr->n_slots; ++s) {
         SlotHeader* sl = slot_at(S->base, S->hdr, s);
