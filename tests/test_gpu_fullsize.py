@@ -15,7 +15,9 @@ pytestmark = pytest.mark.gpu
 def test_large_full_size():
     """5000 atoms (500 neutral fragments, ~9e6 screened pairs), 1,048,576
     points: FP32C within 1e-5 Ha of the unscreened oracle and FP64 within
-    1e-12 A of the screened oracle on 24 sampled points."""
+    1e-12 A of the screened oracle on 24 sampled points; the field of the
+    same launch size within 1e-6 AE (FP32C) and 1e-12 AE (FP64) of the field
+    oracle on 8 of them."""
     import torch
     from oracle import oracle as O
     from paper_1011_4687_amd.envpot import Environment
@@ -36,7 +38,19 @@ def test_large_full_size():
         print(f"[fullsize] large {prec}: create {t1 - t0:.1f}s eval {time.time() - t1:.1f}s "
               f"pairs {E.info()['n_pairs']}", flush=True)
         res[prec] = V.cpu().numpy()
+        t2 = time.time()
+        F = E.eval_field(x)
+        torch.cuda.synchronize()
+        print(f"[fullsize] large {prec}: field {time.time() - t2:.1f}s", flush=True)
+        res["field_" + prec] = F.cpu().numpy()[idx]
         E.close()
+    # the field at full size: 8 of the sampled points against the field oracle
+    fi = idx[:8]
+    Eo, AE = O.field(env, pts[fi], P=P, screen=True)
+    for prec, tol in (("fp32c", 1e-6), ("fp64", 1e-12)):
+        dE = np.abs(res["field_" + prec][:8, 1:] - Eo).max(axis=1)
+        print(f"[fullsize] large field {prec}: max |dE|/AE {(dE / AE).max():.3e}", flush=True)
+        assert np.all(dE <= tol * AE)
     Vs, _, _, A = O.potential(env, pts[idx], P=P, screen=True)
     Vf, _, _, _ = O.potential(env, pts[idx], P=P, screen=False)
     e32 = np.abs(res["fp32c"][idx] - Vf)
