@@ -13,6 +13,7 @@
 
 #include "handle.h"
 #include "probe.h"
+#include "sort_internal.h"
 
 using namespace envpot;
 
@@ -101,6 +102,10 @@ EvalArgs make_args(const env_potential* h, const double* points, int64_t n, doub
 }
 
 }  // namespace envpot
+
+namespace {
+env_status eval_core(env_potential* h, const double* points, int64_t n, double* out, void* stream);
+}  // namespace
 
 extern "C" {
 
@@ -287,6 +292,32 @@ env_status env_potential_eval(env_potential* h, const double* points, int64_t n,
     if (!points || !out) return ENV_E_ARG;
     if (!h->on_device) return ENV_E_STATE;
     DeviceGuard g(h->device);
+    if (n < kSortMinPoints || n > int64_t(INT32_MAX) || env_int("ENVPOT_NO_SORT", 0) != 0)
+        return eval_core(h, points, n, out, stream);
+    // large calls: evaluate the points in Morton order, then restore the caller's order
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *spts = nullptr, *sout = nullptr;
+    uint32_t* order = nullptr;
+    if (hipMallocAsync(reinterpret_cast<void**>(&spts), size_t(n) * 3 * sizeof(double), st) != hipSuccess)
+        return ENV_E_NOMEM;
+    env_status rc = ENV_OK;
+    if (hipMallocAsync(reinterpret_cast<void**>(&sout), size_t(n) * sizeof(double), st) != hipSuccess ||
+        hipMallocAsync(reinterpret_cast<void**>(&order), size_t(n) * sizeof(uint32_t), st) != hipSuccess)
+        rc = ENV_E_NOMEM;
+    if (rc == ENV_OK && sort_points(points, n, spts, order, stream) != 0) rc = ENV_E_DEVICE;
+    if (rc == ENV_OK) rc = eval_core(h, spts, n, sout, stream);
+    if (rc == ENV_OK && scatter_values(sout, order, n, out, stream) != 0) rc = ENV_E_DEVICE;
+    (void)hipFreeAsync(order, st);
+    (void)hipFreeAsync(sout, st);
+    (void)hipFreeAsync(spts, st);
+    return rc;
+}
+
+}  // extern "C"
+
+namespace {
+
+env_status eval_core(env_potential* h, const double* points, int64_t n, double* out, void* stream) {
     int np, k;
     choose_shape(h, n, &np, &k);
     const int S = 1 << k;
@@ -305,6 +336,10 @@ env_status env_potential_eval(env_potential* h, const double* points, int64_t n,
     (void)hipFreeAsync(part, st);
     return rc == 0 ? ENV_OK : ENV_E_DEVICE;
 }
+
+}  // namespace
+
+extern "C" {
 
 env_status env_potential_autotune(env_potential* h, const double* points, int64_t n, void* stream) {
     if (!h || n <= 0 || !points) return ENV_E_ARG;

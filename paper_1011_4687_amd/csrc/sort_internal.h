@@ -1,0 +1,18 @@
+// Spatial ordering of evaluation points (sortpts.hip).  Not part of the C ABI.
+#pragma once
+
+#include <cstdint>
+
+namespace envpot {
+
+// Points with at least this many entries are evaluated in Morton order.
+constexpr int64_t kSortMinPoints = 32768;
+
+// sorted[i] = points[order[i]] with order by Morton key (0.25-bohr grid);
+// stream-ordered, temporary buffers from the stream's pool.  n < 2^31.
+int sort_points(const double* points, int64_t n, double* sorted, uint32_t* order, void* stream);
+
+// out[order[i]] = v[i].
+int scatter_values(const double* v, const uint32_t* order, int64_t n, double* out, void* stream);
+
+}  // namespace envpot
