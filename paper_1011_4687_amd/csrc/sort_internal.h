@@ -15,4 +15,7 @@ int sort_points(const double* points, int64_t n, double* sorted, uint32_t* order
 // out[order[i]] = v[i].
 int scatter_values(const double* v, const uint32_t* order, int64_t n, double* out, void* stream);
 
+// Rows of 4: out[4 order[i] + c] = v[4 i + c].
+int scatter_rows4(const double* v, const uint32_t* order, int64_t n, double* out, void* stream);
+
 }  // namespace envpot

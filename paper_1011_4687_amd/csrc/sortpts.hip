@@ -62,6 +62,16 @@ __global__ __launch_bounds__(kSortBlock) void k_scatter(const double* __restrict
     out[order[i]] = v[i];
 }
 
+__global__ __launch_bounds__(kSortBlock) void k_scatter4(const double* __restrict__ v,
+                                                         const uint32_t* __restrict__ order, int64_t n,
+                                                         double* __restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * kSortBlock + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j = order[i];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) out[4 * j + c] = v[4 * i + c];
+}
+
 unsigned blocks(int64_t n) { return unsigned((n + kSortBlock - 1) / kSortBlock); }
 
 }  // namespace
@@ -102,6 +112,17 @@ int scatter_values(const double* v, const uint32_t* order, int64_t n, double* ou
     if (n <= 0) return 0;
     hipLaunchKernelGGL(k_scatter, dim3(blocks(n)), dim3(kSortBlock), 0, static_cast<hipStream_t>(stream), v, order,
                        n, out);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace envpot
+
+namespace envpot {
+
+int scatter_rows4(const double* v, const uint32_t* order, int64_t n, double* out, void* stream) {
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_scatter4, dim3(blocks(n)), dim3(kSortBlock), 0, static_cast<hipStream_t>(stream), v,
+                       order, n, out);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
