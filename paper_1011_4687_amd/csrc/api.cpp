@@ -294,7 +294,8 @@ env_status env_potential_eval(env_potential* h, const double* points, int64_t n,
     if (!points || !out) return ENV_E_ARG;
     if (!h->on_device) return ENV_E_STATE;
     DeviceGuard g(h->device);
-    if (n < kSortMinPoints || n > int64_t(INT32_MAX) || env_int("ENVPOT_NO_SORT", 0) != 0)
+    if (n < kSortMinPoints || n > int64_t(INT32_MAX) || env_int("ENVPOT_NO_SORT", 0) != 0 ||
+        stream_capturing(stream))
         return eval_core(h, points, n, out, stream);
     // large calls: evaluate the points in Morton order, then restore the caller's order
     hipStream_t st = static_cast<hipStream_t>(stream);

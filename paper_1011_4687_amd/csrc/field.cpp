@@ -64,7 +64,7 @@ env_status env_potential_eval_field(env_potential* h, const double* points, int6
     if (!h->on_device) return ENV_E_STATE;
     DeviceGuard g(h->device);
     const char* ns = std::getenv("ENVPOT_NO_SORT");
-    if (n < kSortMinPoints || n > int64_t(INT32_MAX) || (ns && std::atoi(ns) != 0))
+    if (n < kSortMinPoints || n > int64_t(INT32_MAX) || (ns && std::atoi(ns) != 0) || stream_capturing(stream))
         return field_core(h, points, n, out, stream);
     // large calls: evaluate the points in Morton order, then restore the caller's order
     hipStream_t st = static_cast<hipStream_t>(stream);

@@ -5,8 +5,13 @@
 
 namespace envpot {
 
-// Points with at least this many entries are evaluated in Morton order.
+// Points with at least this many entries are evaluated in Morton order
+// (not while the stream is being captured into a graph: the sort library
+// may record memory-set nodes).
 constexpr int64_t kSortMinPoints = 32768;
+
+// True when `stream` is capturing (or its state cannot be read).
+bool stream_capturing(void* stream);
 
 // sorted[i] = points[order[i]] with order by Morton key (0.25-bohr grid);
 // stream-ordered, temporary buffers from the stream's pool.  n < 2^31.

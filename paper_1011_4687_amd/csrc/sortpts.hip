@@ -108,6 +108,13 @@ int sort_points(const double* pts, int64_t n, double* sorted, uint32_t* order, v
     return rc;
 }
 
+bool stream_capturing(void* stream) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (!stream) return false;  // the null stream is never captured here
+    if (hipStreamIsCapturing(static_cast<hipStream_t>(stream), &cap) != hipSuccess) return true;
+    return cap != hipStreamCaptureStatusNone;
+}
+
 int scatter_values(const double* v, const uint32_t* order, int64_t n, double* out, void* stream) {
     if (n <= 0) return 0;
     hipLaunchKernelGGL(k_scatter, dim3(blocks(n)), dim3(kSortBlock), 0, static_cast<hipStream_t>(stream), v, order,
