@@ -157,7 +157,7 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
  * n = 0 is a no-op.  A point exactly on a nucleus gives +inf.
  * Calls of 32,768 points or more evaluate the points in a spatial (Morton)
  * order and write out in the caller's order (off while the stream is being
- * captured, or with ENVPOT_NO_SORT=1); the same call is bitwise repeatable. */
+ * captured, or with ENVPOT_NO_SORT=1); the same call is bitwise repeatable.
  * Errors: ENV_E_ARG (NULL with n > 0, n < 0), ENV_E_STATE (ENV_BUILD_ONLY
  * handle), ENV_E_DEVICE (launch failure), ENV_E_NOMEM (workspace). */
 env_status env_potential_eval(env_potential* h, const double* points, int64_t n,
