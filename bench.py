@@ -294,7 +294,7 @@ def main():
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(points would be sharded across GPUs with no communication)", file=sys.stderr)
         sys.exit(2)
 

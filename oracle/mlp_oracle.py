@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY: called by the test suite, never by the library.
 
 The surrogate is not part of the paper (which has no learned component); it
-is this build's stand-in for V(r) inside the QM region.  The network:
+is the library's stand-in for V(r) inside the QM region.  The network:
 
     gamma(r)  = [cos(2 pi B r), sin(2 pi B r)]          B: n_freq x 3, 2 n_freq inputs
     H_0       = bf16(gamma)

@@ -1,7 +1,7 @@
 // Host driver of the coordinate-MLP surrogate (env_surrogate_*): training on
 // samples of the exact kernel, a validated voxel gate, and gated evaluation
 // that sends every point outside the gate to the exact kernel.  The learned
-// model is this build's addition; the paper has none.
+// model is an addition to the paper's method, which has none.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
