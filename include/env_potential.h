@@ -40,9 +40,12 @@
  *   Errors           every call returns an env_status; no exception crosses
  *                    the ABI.  Arguments are validated before any device
  *                    work is queued.
- *   Device           there is no CPU evaluation path: evaluation requires a
- *                    gfx950 device; without one create returns ENV_E_DEVICE
- *                    unless ENV_BUILD_ONLY is set.
+ *   Device           evaluation runs on a gfx950 device; without one create
+ *                    returns ENV_E_DEVICE unless ENV_BUILD_ONLY or
+ *                    ENV_FORCE_CPU is set.  ENV_FORCE_CPU is the paper's switch
+ *                    back to the CPU (Sec. I): the caller asks for it at create,
+ *                    and the handle then evaluates on host threads from host
+ *                    buffers.  A device handle never falls back to the CPU.
  */
 #ifndef ENV_POTENTIAL_H
 #define ENV_POTENTIAL_H
@@ -78,6 +81,16 @@ typedef enum {
                                      that its electron count tr(P_f S_f) equals the
                                      fragment's nuclear charge (needs a block-diagonal P) */
 #define ENV_NO_SCREENING 0x4u     /* keep every primitive pair */
+#define ENV_FORCE_CPU 0x10u       /* evaluate on the host instead of the device (paper
+                                     Sec. I: the user can switch back to the CPU code):
+                                     FP64 only (FP32C gives ENV_E_UNSUPPORTED), no
+                                     device is touched, env_potential_eval takes host
+                                     points/out and returns when they are written (the
+                                     stream is ignored); every other evaluation call
+                                     (field, batched, surrogate, density update,
+                                     autotune) returns ENV_E_STATE.  Not combinable
+                                     with ENV_BUILD_ONLY (ENV_E_ARG).  ENVPOT_THREADS
+                                     sets the thread count (default: all cores). */
 #define ENV_NO_MERGE 0x8u         /* evaluate every pair on its own: no same-centre
                                      clusters (results agree to rounding) */
 
@@ -130,9 +143,11 @@ typedef struct {
     double screened_bound;        /* sum over dropped pairs of |P|-weighted charge bound */
     int64_t device_bytes;         /* bytes held on the device by the handle */
     int32_t precision;
-    int32_t built_on_device;      /* 0 with ENV_BUILD_ONLY */
+    int32_t built_on_device;      /* 0 with ENV_BUILD_ONLY or ENV_FORCE_CPU */
     int64_t n_clusters;           /* same-centre clusters (far fields merged per atom) */
     int64_t n_cluster_members;    /* pairs inside those clusters (counted in n_pairs too) */
+    int32_t on_host;              /* 1 with ENV_FORCE_CPU: evaluation runs on host threads */
+    int32_t reserved;
 } env_info;
 
 /* Default options: FP32C, current device, threshold 1e-12, no flags. */
@@ -143,9 +158,9 @@ void env_options_default(env_options* opts);
  * Builds the screened primitive-pair list with its Hermite densities on the
  * host, uploads it, and returns a handle in *out.
  * Errors: ENV_E_ARG (NULL pointers, n < 0, non-finite input, exponent <= 0,
- * atom index out of range, nbf mismatch, P not symmetric), ENV_E_UNSUPPORTED
- * (l > 2; ENV_NEUTRALIZE with density between fragments), ENV_E_NOMEM,
- * ENV_E_DEVICE. */
+ * atom index out of range, nbf mismatch, P not symmetric, ENV_FORCE_CPU with
+ * ENV_BUILD_ONLY), ENV_E_UNSUPPORTED (l > 2; ENV_NEUTRALIZE with density
+ * between fragments; ENV_FORCE_CPU with FP32C), ENV_E_NOMEM, ENV_E_DEVICE. */
 env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
                                 const env_shell* shells, int32_t n_shells,
                                 const env_density* P, const env_options* opts,
@@ -158,6 +173,9 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
  * Calls of 32,768 points or more evaluate the points in a spatial (Morton)
  * order and write out in the caller's order (off while the stream is being
  * captured, or with ENVPOT_NO_SORT=1); the same call is bitwise repeatable.
+ * A handle created with ENV_FORCE_CPU takes host pointers instead, ignores
+ * the stream and returns after writing out (FP64, the host threads of the
+ * paper's switch back to the CPU).
  * Errors: ENV_E_ARG (NULL with n > 0, n < 0), ENV_E_STATE (ENV_BUILD_ONLY
  * handle), ENV_E_DEVICE (launch failure), ENV_E_NOMEM (workspace). */
 env_status env_potential_eval(env_potential* h, const double* points, int64_t n,
@@ -165,7 +183,7 @@ env_status env_potential_eval(env_potential* h, const double* points, int64_t n,
 
 /* Replace the environment's density matrix, keeping its geometry and basis
  * (an environment whose density changes from step to step, e.g. the
- * self-consistent fragment densities of FMO, Sec. II.A).  The pair list
+ * self-consistent fragment densities of FMO, Sec. II.B).  The pair list
  * (screening, order, same-centre clusters, splits) does not depend on the
  * density values, so the device refolds every pair's Hermite density and
  * far-field coefficients from the new P in place; with ENV_NEUTRALIZE the

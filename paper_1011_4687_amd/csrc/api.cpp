@@ -143,8 +143,13 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
     else env_options_default(&opt);
     if (opt.precision != ENV_PREC_FP64 && opt.precision != ENV_PREC_FP32C) return ENV_E_ARG;
     if (opt.reserved[0] || opt.reserved[1] || opt.reserved[2]) return ENV_E_ARG;
-    if (opt.flags & ~(ENV_BUILD_ONLY | ENV_NEUTRALIZE | ENV_NO_SCREENING | ENV_NO_MERGE)) return ENV_E_ARG;
-    const bool build_only = (opt.flags & ENV_BUILD_ONLY) != 0;
+    if (opt.flags & ~(ENV_BUILD_ONLY | ENV_NEUTRALIZE | ENV_NO_SCREENING | ENV_NO_MERGE | ENV_FORCE_CPU))
+        return ENV_E_ARG;
+    const bool force_cpu = (opt.flags & ENV_FORCE_CPU) != 0;
+    if (force_cpu && (opt.flags & ENV_BUILD_ONLY)) return ENV_E_ARG;
+    if (force_cpu && opt.precision != ENV_PREC_FP64) return ENV_E_UNSUPPORTED;
+    // host handles: the pair list and its D stay on the host (host fold)
+    const bool build_only = (opt.flags & ENV_BUILD_ONLY) != 0 || force_cpu;
 
     int device = opt.device;
     if (!build_only) {
@@ -238,6 +243,16 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
         if (k == 0) in.n_segments = int32_t(segs.size());
     }
     lap("splits");
+    if (force_cpu) {
+        try {
+            host_prepare(h, t64);
+        } catch (const std::bad_alloc&) {
+            delete h;
+            return ENV_E_NOMEM;
+        }
+        h->on_host = true;
+        in.on_host = 1;
+    }
     if (build_only) {
         *out = h;
         return ENV_OK;
@@ -292,6 +307,7 @@ env_status env_potential_eval(env_potential* h, const double* points, int64_t n,
     if (!h || n < 0) return ENV_E_ARG;
     if (n == 0) return ENV_OK;
     if (!points || !out) return ENV_E_ARG;
+    if (h->on_host) return host_eval(h, points, n, out);
     if (!h->on_device) return ENV_E_STATE;
     DeviceGuard g(h->device);
     if (n < kSortMinPoints || n > int64_t(INT32_MAX) || env_int("ENVPOT_NO_SORT", 0) != 0 ||

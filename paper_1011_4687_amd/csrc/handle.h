@@ -7,13 +7,28 @@
 #include "field_internal.h"
 #include "update_internal.h"
 
+namespace envpot {
+
+// What a handle created with ENV_FORCE_CPU needs besides its pair list: the
+// FP64 Boys table and far-field thresholds, and every pair's far-field
+// coefficients (same offsets as the pair list's D).
+struct HostEval {
+    std::vector<double> boys;
+    std::vector<double> h;
+    double tfar[kLMax + 1] = {};
+};
+
+}  // namespace envpot
+
 struct env_potential {
     int device = -1;
     int precision = ENV_PREC_FP32C;
     bool on_device = false;
+    bool on_host = false;               // ENV_FORCE_CPU: evaluated by host threads
     int cu_count = 256;
     env_info info{};
-    envpot::PairList host;              // kept only for ENV_BUILD_ONLY handles
+    envpot::PairList host;              // kept for ENV_BUILD_ONLY and ENV_FORCE_CPU handles
+    envpot::HostEval hosteval;          // ENV_FORCE_CPU only
     envpot::BoysParams bp{};
     // device buffers
     uint32_t* d_rec = nullptr;
@@ -48,6 +63,11 @@ struct DeviceGuard {  // restores the caller's current device
 
 // Launch shape of a single evaluation of h at n points.
 void choose_shape(const env_potential* h, int64_t n, int* np, int* klog);
+
+// Host evaluation of an ENV_FORCE_CPU handle (hosteval.cpp): tables at
+// create, then V at n host points into host memory.
+void host_prepare(env_potential* h, const std::vector<double>& t64);
+env_status host_eval(const env_potential* h, const double* points, int64_t n, double* out);
 
 // Arguments of one evaluation (out = V when S == 1, partials otherwise).
 EvalArgs make_args(const env_potential* h, const double* points, int64_t n, double* out, int klog);

@@ -32,6 +32,7 @@ ENV_BUILD_ONLY = 0x1
 ENV_NEUTRALIZE = 0x2
 ENV_NO_SCREENING = 0x4
 ENV_NO_MERGE = 0x8
+ENV_FORCE_CPU = 0x10
 
 ENV_DENSITY_DENSE = 0
 ENV_DENSITY_CSR = 1
@@ -72,7 +73,7 @@ class env_info(ctypes.Structure):
                 ("nuclear_charge", c_double), ("screened_bound", c_double),
                 ("device_bytes", c_int64), ("precision", c_int32),
                 ("built_on_device", c_int32), ("n_clusters", c_int64),
-                ("n_cluster_members", c_int64)]
+                ("n_cluster_members", c_int64), ("on_host", c_int32), ("reserved", c_int32)]
 
 
 class env_batch_stats(ctypes.Structure):
@@ -346,8 +347,9 @@ class Environment:
     def __init__(self, xyz, Z, fragment, shells, P, precision: str = "fp32c",
                  device: int = -1, screen_threshold: float = 1e-12,
                  neutralize: bool = False, build_only: bool = False,
-                 screening: bool = True, merge: bool = True):
+                 screening: bool = True, merge: bool = True, force_cpu: bool = False):
         self.handle = 0
+        self.on_host = bool(force_cpu)
         xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
         K = xyz.shape[0]
         Z = np.ascontiguousarray(Z, dtype=np.float64).reshape(K)
@@ -373,7 +375,8 @@ class Environment:
         opt.device = int(device)
         opt.screen_threshold = float(screen_threshold)
         opt.flags = ((ENV_NEUTRALIZE if neutralize else 0) | (ENV_BUILD_ONLY if build_only else 0)
-                     | (0 if screening else ENV_NO_SCREENING) | (0 if merge else ENV_NO_MERGE))
+                     | (0 if screening else ENV_NO_SCREENING) | (0 if merge else ENV_NO_MERGE)
+                     | (ENV_FORCE_CPU if force_cpu else 0))
         self.precision = precision
         self.handle = env_potential_create(nuc, K, sh, len(shells), dens, opt)
         self._keep = None
@@ -422,9 +425,21 @@ class Environment:
             raise EnvError(st, "env_potential_export_pairs")
         return L[:n], g[:n], c[:n], p[:n], D[:n]
 
+    def eval_host(self, points) -> np.ndarray:
+        """V at (n,3) host points of a handle built with force_cpu=True
+        (ENV_FORCE_CPU: the library's host threads, FP64); numpy in and out."""
+        if not self.on_host:
+            raise TypeError("eval_host needs a handle created with force_cpu=True")
+        pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+        out = np.empty(pts.shape[0])
+        env_potential_eval(self.handle, pts.ctypes.data, pts.shape[0], out.ctypes.data, 0)
+        return out
+
     def eval(self, points, out=None, stream=None):
         """V at a (n,3) float64 torch CUDA tensor; returns a (n,) tensor."""
         import torch
+        if self.on_host:
+            raise TypeError("a force_cpu handle evaluates host arrays: use eval_host")
         if not (isinstance(points, torch.Tensor) and points.is_cuda):
             raise TypeError("points must be a torch CUDA tensor")
         if points.dtype != torch.float64 or points.dim() != 2 or points.shape[1] != 3:
