@@ -325,6 +325,17 @@ void env_client_detach(env_client* c);
  * Errors: ENV_E_ARG, ENV_E_STATE, ENV_E_NOMEM, ENV_E_DEVICE. */
 env_status env_potential_autotune(env_potential* h, const double* points, int64_t n, void* stream);
 
+/* Measurement support (not part of the method): with timing on, every later
+ * env_potential_eval of h records a pair of HIP events on its stream around
+ * the potential kernel alone (not the point ordering or the split sums), up
+ * to 2048 launches; env_potential_kernel_timing(h, 1) also clears the list.
+ * env_potential_kernel_times waits for the recorded events and writes the
+ * kernel durations (ms) of the first min(cap, count) launches in call order;
+ * *count receives the number recorded.  Not for concurrent evaluations of h.
+ * Errors: ENV_E_ARG, ENV_E_STATE (host or build-only handle), ENV_E_DEVICE. */
+env_status env_potential_kernel_timing(env_potential* h, int32_t on);
+env_status env_potential_kernel_times(env_potential* h, float* ms, int32_t cap, int32_t* count);
+
 /* Statistics of the built pair list. */
 env_status env_potential_info(const env_potential* h, env_info* info);
 
@@ -448,6 +459,32 @@ env_status env_surrogate_eval(env_surrogate* s, const double* points, int64_t n,
  * normalised).  Synchronous. */
 env_status env_surrogate_loss_grad(env_surrogate* s, const double* points, const float* targets,
                                    int64_t n, float* grad_host, double* loss, void* stream);
+
+/* Diagnostic: one forward and backward pass at n device points with device
+ * targets t (float32, normalised), as env_surrogate_loss_grad, copying the
+ * intermediate tensors to host buffers so that each layer can be checked on
+ * its own.  Every pointer may be NULL (that tensor is skipped); row-major,
+ * rows = points:
+ *   H    (layers + 1) x n x 128   H_0 = the BF16 features, H_l = bf16(silu(Z_l)), as float
+ *   Z    layers x n x 128         FP32 pre-activations Z_l = H_{l-1} bf16(W_l)^T + b_l
+ *   y    n                        FP32 outputs H_4 . w_out + b_out
+ *   dy   n                        dL/dy = 2 (y - t) / n as used by the backward pass
+ *   dH   layers x n x 128         FP32 dL/dH_l, l = 1..4 (the input of each SiLU backward)
+ *   dZ   layers x n x 128         bf16(dL/dH_l * silu'(Z_l)) fed to the weight products, as float
+ *   grad 66,177                   the gradient in the parameter layout
+ * Synchronous.  Errors: ENV_E_ARG, ENV_E_NOMEM, ENV_E_DEVICE. */
+typedef struct {
+    float* H;
+    float* Z;
+    float* y;
+    float* dy;
+    float* dH;
+    float* dZ;
+    float* grad;
+    double loss;
+} env_surrogate_trace;
+env_status env_surrogate_trace_step(env_surrogate* s, const double* points, const float* targets, int64_t n,
+                                    env_surrogate_trace* tr, void* stream);
 
 /* Current parameters (host, 66,177 floats), baseline coefficients and sigma;
  * any pointer may be NULL. */

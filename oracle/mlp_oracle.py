@@ -79,6 +79,39 @@ def features(points, B):
     return np.concatenate([np.cos(phi), np.sin(phi)], axis=1)
 
 
+def hidden_pre(Hprev, W, b):
+    """Pre-activation of one hidden layer from given inputs (FP64):
+    Hprev bf16(W)^T + b, with its conditioning scale |Hprev| |bf16(W)|^T + |b|."""
+    Wr = bf16(W)
+    return Hprev @ Wr.T + b, np.abs(Hprev) @ np.abs(Wr).T + np.abs(b)
+
+
+def hidden_act(Z):
+    """H = bf16(silu(Z)) of given pre-activations."""
+    return bf16(silu(np.asarray(Z, dtype=np.float64)))
+
+
+def output(H4, w_out, b_out):
+    """y = H4 . w_out + b_out (FP64) and its scale |H4| |w_out| + |b_out|."""
+    return H4 @ w_out + b_out, np.abs(H4) @ np.abs(w_out) + abs(b_out)
+
+
+def dz_of(dH, Z):
+    """dL/dZ = dL/dH silu'(Z) (FP64, before any rounding)."""
+    return dH * dsilu(np.asarray(Z, dtype=np.float64))
+
+
+def weight_grad(dZr, Hprev):
+    """dL/dW = dZ_r^T Hprev (dZ_r as fed to the product) and its scale."""
+    return dZr.T @ Hprev, np.abs(dZr).T @ np.abs(Hprev)
+
+
+def input_grad(dZr, W):
+    """dL/dHprev = dZ_r bf16(W) and its scale."""
+    Wr = bf16(W)
+    return dZr @ Wr, np.abs(dZr) @ np.abs(Wr)
+
+
 def forward(params, points, B, rounding=True):
     layers, w_out, b_out = unpack(params)
     r = bf16 if rounding else (lambda x: np.asarray(x, dtype=np.float64))

@@ -336,6 +336,29 @@ env_status env_potential_eval(env_potential* h, const double* points, int64_t n,
 
 namespace {
 
+// The next event of the kernel-timing list (created on first use), or null.
+hipEvent_t next_event(env_potential* h) {
+    if (!h->ktime || h->kev_used >= 4096) return nullptr;
+    if (h->kev_used == h->kev.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        h->kev.push_back(e);
+    }
+    return h->kev[h->kev_used++];
+}
+
+// The potential kernel, with a pair of timing events around it when on.
+int timed_launch(env_potential* h, const EvalArgs& a, int S, int np, void* stream) {
+    hipEvent_t e0 = next_event(h), e1 = e0 ? next_event(h) : nullptr;
+    if (e0 && !e1) --h->kev_used;
+    const bool on = e0 && e1;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (on && hipEventRecord(e0, st) != hipSuccess) return -1;
+    const int rc = launch_potential(a, S, h->precision, np, stream);
+    if (on && rc == 0 && hipEventRecord(e1, st) != hipSuccess) return -1;
+    return rc;
+}
+
 env_status eval_core(env_potential* h, const double* points, int64_t n, double* out, void* stream) {
     int np, k;
     choose_shape(h, n, &np, &k);
@@ -343,14 +366,14 @@ env_status eval_core(env_potential* h, const double* points, int64_t n, double* 
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (S == 1) {
         const EvalArgs a = make_args(h, points, n, out, 0);
-        return launch_potential(a, 1, h->precision, np, stream) == 0 ? ENV_OK : ENV_E_DEVICE;
+        return timed_launch(h, a, 1, np, stream) == 0 ? ENV_OK : ENV_E_DEVICE;
     }
     double* part = nullptr;
     if (hipMallocAsync(reinterpret_cast<void**>(&part), size_t(S) * size_t(n) * sizeof(double), st) !=
         hipSuccess)
         return ENV_E_NOMEM;
     const EvalArgs a = make_args(h, points, n, part, k);
-    int rc = launch_potential(a, S, h->precision, np, stream);
+    int rc = timed_launch(h, a, S, np, stream);
     if (rc == 0) rc = launch_sum_splits(part, S, n, out, stream);
     (void)hipFreeAsync(part, st);
     return rc == 0 ? ENV_OK : ENV_E_DEVICE;
@@ -413,6 +436,28 @@ env_status env_potential_autotune(env_potential* h, const double* points, int64_
     return rc;
 }
 
+env_status env_potential_kernel_timing(env_potential* h, int32_t on) {
+    if (!h) return ENV_E_ARG;
+    if (!h->on_device) return ENV_E_STATE;
+    h->ktime = on != 0;
+    h->kev_used = 0;
+    return ENV_OK;
+}
+
+env_status env_potential_kernel_times(env_potential* h, float* ms, int32_t cap, int32_t* count) {
+    if (!h || cap < 0 || (cap > 0 && !ms)) return ENV_E_ARG;
+    if (!h->on_device) return ENV_E_STATE;
+    DeviceGuard g(h->device);
+    const int32_t pairs = int32_t(h->kev_used / 2);
+    for (int32_t i = 0; i < pairs && i < cap; ++i) {
+        if (hipEventSynchronize(h->kev[2 * i + 1]) != hipSuccess ||
+            hipEventElapsedTime(&ms[i], h->kev[2 * i], h->kev[2 * i + 1]) != hipSuccess)
+            return ENV_E_DEVICE;
+    }
+    if (count) *count = pairs;
+    return ENV_OK;
+}
+
 env_status env_potential_info(const env_potential* h, env_info* info) {
     if (!h || !info) return ENV_E_ARG;
     *info = h->info;
@@ -458,6 +503,10 @@ env_status env_potential_export_pairs(const env_potential* h, int64_t cap, int32
 
 void env_potential_destroy(env_potential* h) {
     if (!h) return;
+    if (!h->kev.empty()) {
+        DeviceGuard g(h->device);
+        for (hipEvent_t e : h->kev) (void)hipEventDestroy(e);
+    }
     free_device(h);
     delete h;
 }

@@ -25,6 +25,7 @@ struct env_potential {
     int precision = ENV_PREC_FP32C;
     bool on_device = false;
     bool on_host = false;               // ENV_FORCE_CPU: evaluated by host threads
+    uint64_t density_gen = 0;           // bumped whenever a density fold rewrites the records
     int cu_count = 256;
     env_info info{};
     envpot::PairList host;              // kept for ENV_BUILD_ONLY and ENV_FORCE_CPU handles
@@ -42,6 +43,11 @@ struct env_potential {
     int64_t seg_off[envpot::kMaxSplitLog2 + 1] = {};    // per split factor 2^k: first segment
     int64_t split_off[envpot::kMaxSplitLog2 + 1] = {};  // per split factor 2^k: first offset
     int64_t device_bytes = 0;
+    // kernel timing (env_potential_kernel_timing): event pairs around each
+    // potential-kernel launch, in call order
+    bool ktime = false;
+    std::vector<hipEvent_t> kev;
+    size_t kev_used = 0;
     // tuned launch shapes: (point count, points per lane, split log2)
     struct Tuned { int64_t n; int np; int klog; };
     std::vector<Tuned> tuned;

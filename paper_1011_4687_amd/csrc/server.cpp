@@ -92,6 +92,10 @@ void sleep_us(int us) {
 struct env_server {
     std::vector<env_potential*> hs;
     int device = -1;
+    // the segment's geometry as the server created it: the header in shared
+    // memory is writable by clients, so the server never reads it back
+    int32_t n_slots = 0;
+    int64_t max_points = 0, slot_off = 0, slot_stride = 0;
     std::string name;
     void* base = nullptr;
     ShmHeader* hdr = nullptr;
@@ -118,46 +122,58 @@ struct env_client {
 
 namespace {
 
-// One round: evaluate every ready slot in one batched launch.
+SlotHeader* server_slot(const env_server* S, int s) {
+    return reinterpret_cast<SlotHeader*>(static_cast<char*>(S->base) + S->slot_off + int64_t(s) * S->slot_stride);
+}
+
+// One round: evaluate every ready slot in one batched launch.  A slot's
+// request (environment, point count) is read once, after its READY state
+// was observed with acquire, and only those copies are validated and used:
+// a client that rewrites its slot meanwhile cannot move the server out of
+// bounds.
 void serve_round(env_server* S, std::vector<int>& ready) {
-    ShmHeader* h = S->hdr;
-    const int64_t maxp = h->max_points;
+    const int64_t maxp = S->max_points;
+    const int32_t n_env = int32_t(S->hs.size());
     std::vector<env_potential*> hs;
     std::vector<const double*> pts;
     std::vector<double*> outs;
     std::vector<int64_t> ns;
     std::vector<int> ids;
+    std::vector<int32_t> envs;
     for (int s : ready) {
-        SlotHeader* sl = slot_at(S->base, h, s);
-        if (sl->env < 0 || sl->env >= h->n_env || sl->n < 0 || sl->n > maxp) {
+        SlotHeader* sl = server_slot(S, s);
+        const int32_t env = __atomic_load_n(&sl->env, __ATOMIC_RELAXED);
+        const int64_t n = __atomic_load_n(&sl->n, __ATOMIC_RELAXED);
+        if (env < 0 || env >= n_env || n < 0 || n > maxp) {
             sl->status = ENV_E_ARG;
             S->errors.fetch_add(1);
             sl->state.store(kError, std::memory_order_release);
             continue;
         }
-        if (sl->n == 0) {
+        if (n == 0) {
             sl->status = ENV_OK;
             sl->state.store(kDone, std::memory_order_release);
             continue;
         }
         double* dp = S->d_pts + int64_t(s) * 3 * maxp;
         double* dout = S->d_out + int64_t(s) * maxp;
-        if (hipMemcpyAsync(dp, slot_points(sl), size_t(sl->n) * 3 * sizeof(double), hipMemcpyHostToDevice,
+        if (hipMemcpyAsync(dp, slot_points(sl), size_t(n) * 3 * sizeof(double), hipMemcpyHostToDevice,
                            S->stream) != hipSuccess) {
             sl->status = ENV_E_DEVICE;
             S->errors.fetch_add(1);
             sl->state.store(kError, std::memory_order_release);
             continue;
         }
-        hs.push_back(S->hs[sl->env]);
+        hs.push_back(S->hs[env]);
         pts.push_back(dp);
         outs.push_back(dout);
-        ns.push_back(sl->n);
+        ns.push_back(n);
         ids.push_back(s);
+        envs.push_back(env);
     }
     if (ids.empty()) return;
     std::vector<int64_t> key(ids.size());
-    for (size_t k = 0; k < ids.size(); ++k) key[k] = (int64_t(ids[k]) << 32) | slot_at(S->base, h, ids[k])->env;
+    for (size_t k = 0; k < ids.size(); ++k) key[k] = (int64_t(ids[k]) << 32) | envs[k];
     auto it = S->plans.find(key);
     env_status st = ENV_OK;
     if (it == S->plans.end()) {
@@ -171,7 +187,7 @@ void serve_round(env_server* S, std::vector<int>& ready) {
     }
     if (st == ENV_OK) st = env_batch_eval(it->second, pts.data(), ns.data(), outs.data(), S->stream);
     for (size_t k = 0; k < ids.size(); ++k) {
-        SlotHeader* sl = slot_at(S->base, h, ids[k]);
+        SlotHeader* sl = server_slot(S, ids[k]);
         if (st == ENV_OK && hipMemcpyAsync(slot_out(sl, maxp), outs[k], size_t(ns[k]) * sizeof(double),
                                            hipMemcpyDeviceToHost, S->stream) != hipSuccess)
             st = ENV_E_DEVICE;
@@ -179,7 +195,7 @@ void serve_round(env_server* S, std::vector<int>& ready) {
     if (st == ENV_OK && hipStreamSynchronize(S->stream) != hipSuccess) st = ENV_E_DEVICE;
     int64_t npts = 0;
     for (size_t k = 0; k < ids.size(); ++k) {
-        SlotHeader* sl = slot_at(S->base, h, ids[k]);
+        SlotHeader* sl = server_slot(S, ids[k]);
         sl->status = st;
         npts += ns[k];
         sl->state.store(st == ENV_OK ? kDone : kError, std::memory_order_release);
@@ -192,13 +208,12 @@ void serve_round(env_server* S, std::vector<int>& ready) {
 
 void serve(env_server* S) {
     (void)hipSetDevice(S->device);
-    ShmHeader* h = S->hdr;
     std::vector<int> ready;
     int idle_spins = 0;
     while (S->running.load(std::memory_order_acquire)) {
         ready.clear();
-        for (int s = 0; s < h->n_slots; ++s)
-            if (slot_at(S->base, h, s)->state.load(std::memory_order_acquire) == kReady) ready.push_back(s);
+        for (int s = 0; s < S->n_slots; ++s)
+            if (server_slot(S, s)->state.load(std::memory_order_acquire) == kReady) ready.push_back(s);
         if (ready.empty()) {
             // poll quickly right after work, then back off to 50 us
             sleep_us(idle_spins < 100 ? 2 : 50);
@@ -210,8 +225,8 @@ void serve(env_server* S) {
             // let other clients' requests of this step arrive, then take them all
             sleep_us(S->gather_us);
             ready.clear();
-            for (int s = 0; s < h->n_slots; ++s)
-                if (slot_at(S->base, h, s)->state.load(std::memory_order_acquire) == kReady) ready.push_back(s);
+            for (int s = 0; s < S->n_slots; ++s)
+                if (server_slot(S, s)->state.load(std::memory_order_acquire) == kReady) ready.push_back(s);
         }
         const auto t0 = std::chrono::steady_clock::now();
         serve_round(S, ready);
@@ -291,6 +306,10 @@ env_status env_server_create(env_potential* const* hs, int32_t n_env, const char
     S->base = base;
     S->bytes = bytes;
     S->gather_us = gather_us;
+    S->n_slots = n_slots;
+    S->max_points = max_points;
+    S->slot_off = off;
+    S->slot_stride = stride;
     ShmHeader* h = new (base) ShmHeader;
     h->magic = kMagic;
     h->version = kVersion;
@@ -358,8 +377,8 @@ env_status env_server_get_stats(const env_server* S, env_server_stats* st) {
     st->busy_seconds = double(S->busy_ns.load()) * 1e-9;
     st->errors = S->errors.load();
     int attached = 0;
-    for (int s = 0; s < S->hdr->n_slots; ++s)
-        if (slot_at(S->base, S->hdr, s)->owner.load() != 0) ++attached;
+    for (int s = 0; s < S->n_slots; ++s)
+        if (server_slot(S, s)->owner.load() != 0) ++attached;
     st->clients = attached;
     return ENV_OK;
 }
@@ -371,8 +390,8 @@ void env_server_destroy(env_server* S) {
     for (auto& kv : S->plans) env_batch_destroy(kv.second);
     S->plans.clear();
     // requests still waiting get an error and clients see the server gone
-    for (int s = 0; s < S->hdr->n_slots; ++s) {
-        SlotHeader* sl = slot_at(S->base, S->hdr, s);
+    for (int s = 0; s < S->n_slots; ++s) {
+        SlotHeader* sl = server_slot(S, s);
         if (sl->state.load(std::memory_order_acquire) == kReady) {
             sl->status = ENV_E_STATE;
             sl->state.store(kError, std::memory_order_release);

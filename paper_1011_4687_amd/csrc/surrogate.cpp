@@ -110,6 +110,7 @@ int64_t round32(int64_t n) { return std::max<int64_t>(32, (n + 31) / 32 * 32); }
 
 struct env_surrogate {
     env_potential* fallback = nullptr;
+    uint64_t fallback_gen = 0;   // the fallback's density generation when the network was trained
     int device = -1;
     double radius = 6.0;
     int degree = 0;
@@ -160,15 +161,33 @@ void forward(env_surrogate* s, const double* pts, int64_t n, int64_t Np, bool tr
     sg_out_fwd(w.H[kLayers], s->d_params + kOutOffset, s->d_params + kOutOffset + kHidden, Np, w.y, st);
 }
 
+// Host copies of the intermediate tensors of one training step (see
+// env_surrogate_trace_step); every copy is queued on the step's stream.
+struct TraceCopies {
+    env_surrogate_trace* tr = nullptr;
+    int64_t n = 0;
+    std::vector<uint16_t> dzb;   // staging of the BF16 dZ of every layer
+    bool ok = true;
+    void copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
+        if (ok && dst && hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st) != hipSuccess) ok = false;
+    }
+};
+
 // Loss partials and the full gradient into d_grad (forward must have run with train = true).
-void backward(env_surrogate* s, const float* t, int64_t n, int64_t Np, void* st) {
+void backward(env_surrogate* s, const float* t, int64_t n, int64_t Np, void* st, TraceCopies* tc = nullptr) {
     Workspace& w = s->ws;
+    hipStream_t hst = static_cast<hipStream_t>(st);
     sg_loss(w.y, t, n, Np, w.dy, w.losspart, w.dypart, st);
+    if (tc) tc->copy(tc->tr->dy, w.dy, size_t(n) * sizeof(float), hst);
     const int nb = int((Np + kRowsPerBlock - 1) / kRowsPerBlock);
     for (int l = kLayers - 1; l >= 0; --l) {
         const bool top = l == kLayers - 1;
+        if (tc && !top) tc->copy(tc->tr->dH ? tc->tr->dH + size_t(l) * n * kHidden : nullptr, w.dH,
+                                 size_t(n) * kHidden * sizeof(float), hst);
         sg_dsilu(top ? nullptr : w.dH, w.dy, s->d_params + kOutOffset, w.Z[l], w.H[kLayers], Np, w.dZb, w.dZT,
                  Np, w.colb, w.colo, st);
+        if (tc && tc->tr->dZ)
+            tc->copy(tc->dzb.data() + size_t(l) * n * kHidden, w.dZb, size_t(n) * kHidden * sizeof(uint16_t), hst);
         float* gl = s->d_grad + size_t(l) * kLayerStride;
         sg_reduce_rows(w.colb, nb, kHidden, gl + kHidden * kHidden, st);
         if (top) {
@@ -344,6 +363,7 @@ env_status env_surrogate_predict(env_surrogate* s, const double* points, int64_t
     if (!s || n < 0) return ENV_E_ARG;
     if (n == 0) return ENV_OK;
     if (!points || !out) return ENV_E_ARG;
+    if (s->d_pass && s->fallback->density_gen != s->fallback_gen) return ENV_E_STATE;  // trained on an old density
     DeviceGuard g(s->device);
     return predict(s, points, n, out, stream);
 }
@@ -368,6 +388,55 @@ env_status env_surrogate_loss_grad(env_surrogate* s, const double* points, const
     double L = 0.0;
     for (double v : lp) L += v;
     if (loss) *loss = L / double(n);
+    return ENV_OK;
+}
+
+env_status env_surrogate_trace_step(env_surrogate* s, const double* points, const float* targets, int64_t n,
+                                    env_surrogate_trace* tr, void* stream) {
+    if (!s || n <= 0 || !points || !targets || !tr) return ENV_E_ARG;
+    DeviceGuard g(s->device);
+    const int64_t Np = round32(n);
+    if (!ws_ensure(s->ws, Np, true)) return ENV_E_NOMEM;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Workspace& w = s->ws;
+    TraceCopies tc;
+    tc.tr = tr;
+    tc.n = n;
+    std::vector<uint16_t> hb(tr->H ? size_t(kLayers + 1) * n * kHidden : 0);
+    if (tr->dZ) tc.dzb.assign(size_t(kLayers) * n * kHidden, 0);
+    forward(s, points, n, Np, true, stream);
+    for (int l = 0; l <= kLayers && tr->H; ++l)
+        tc.copy(hb.data() + size_t(l) * n * kHidden, w.H[l], size_t(n) * kHidden * sizeof(uint16_t), st);
+    for (int l = 0; l < kLayers && tr->Z; ++l)
+        tc.copy(tr->Z + size_t(l) * n * kHidden, w.Z[l], size_t(n) * kHidden * sizeof(float), st);
+    tc.copy(tr->y, w.y, size_t(n) * sizeof(float), st);
+    backward(s, targets, n, Np, stream, &tc);
+    tc.copy(tr->grad, s->d_grad, kNParams * sizeof(float), st);
+    std::vector<double> lp((Np + 255) / 256);
+    tc.copy(lp.data(), w.losspart, lp.size() * sizeof(double), st);
+    if (sg_last_error() != 0 || !tc.ok || hipStreamSynchronize(st) != hipSuccess) return ENV_E_DEVICE;
+    auto widen = [](uint16_t b) {
+        const uint32_t u = uint32_t(b) << 16;
+        float f;
+        std::memcpy(&f, &u, 4);
+        return f;
+    };
+    for (size_t i = 0; i < hb.size(); ++i) tr->H[i] = widen(hb[i]);
+    for (size_t i = 0; i < tc.dzb.size(); ++i) tr->dZ[i] = widen(tc.dzb[i]);
+    if (tr->dH) {
+        // dL/dH of the top layer is dy w_out^T, formed inside the SiLU backward
+        std::vector<float> dy(n), wo(kHidden);
+        if (hipMemcpy(dy.data(), w.dy, size_t(n) * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(wo.data(), s->d_params + kOutOffset, kHidden * sizeof(float), hipMemcpyDeviceToHost) !=
+                hipSuccess)
+            return ENV_E_DEVICE;
+        float* top = tr->dH + size_t(kLayers - 1) * n * kHidden;
+        for (int64_t r = 0; r < n; ++r)
+            for (int c = 0; c < kHidden; ++c) top[r * kHidden + c] = dy[r] * wo[c];
+    }
+    double L = 0.0;
+    for (double v : lp) L += v;
+    tr->loss = L / double(n);
     return ENV_OK;
 }
 
@@ -556,6 +625,7 @@ env_status env_surrogate_train(env_surrogate* s, env_potential* teacher, const e
     const auto t3 = std::chrono::steady_clock::now();
     cleanup();
     if (rc != ENV_OK) return rc;
+    s->fallback_gen = s->fallback->density_gen;
     s->info.sigma = s->sigma;
     s->info.poly_degree = s->degree;
     s->info.baseline_rms = rms;
@@ -573,6 +643,7 @@ env_status env_surrogate_eval(env_surrogate* s, const double* points, int64_t n,
     if (n == 0) return ENV_OK;
     if (!points || !out) return ENV_E_ARG;
     if (!s->d_pass) return ENV_E_STATE;  // no gate before training
+    if (s->fallback->density_gen != s->fallback_gen) return ENV_E_STATE;  // trained on an old density
     DeviceGuard g(s->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int nb = int((n + 255) / 256);

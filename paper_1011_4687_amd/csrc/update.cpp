@@ -356,6 +356,9 @@ env_status env_potential_update_density(env_potential* h, const env_density* P, 
     if (hipMemcpyAsync(u->d_scale, scale.data(), scale.size() * sizeof(double), hipMemcpyHostToDevice, st) !=
         hipSuccess)
         return fail();
+    // from here on the records change: anything derived from the old density
+    // (a trained surrogate) is out of date, even if a launch below fails
+    ++h->density_gen;
     if (launch_update_pairs(A, stream) != 0) return fail();
     if (launch_update_members(A, stream) != 0) return fail();
     if (launch_update_clusters(A, stream) != 0) return fail();

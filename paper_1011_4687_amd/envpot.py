@@ -112,6 +112,12 @@ class env_surrogate_info(ctypes.Structure):
                 ("gate_tol", c_double), ("last_eval_n", c_int64), ("last_eval_fallback", c_int64)]
 
 
+class env_surrogate_trace(ctypes.Structure):
+    _fields_ = [("H", POINTER(ctypes.c_float)), ("Z", POINTER(ctypes.c_float)), ("y", POINTER(ctypes.c_float)),
+                ("dy", POINTER(ctypes.c_float)), ("dH", POINTER(ctypes.c_float)), ("dZ", POINTER(ctypes.c_float)),
+                ("grad", POINTER(ctypes.c_float)), ("loss", c_double)]
+
+
 class EnvError(RuntimeError):
     def __init__(self, status: int, what: str = ""):
         self.status = status
@@ -158,6 +164,10 @@ def lib():
         L.env_potential_destroy.restype = None
         L.env_potential_autotune.argtypes = [c_void_p, c_void_p, c_int64, c_void_p]
         L.env_potential_autotune.restype = c_int32
+        L.env_potential_kernel_timing.argtypes = [c_void_p, c_int32]
+        L.env_potential_kernel_timing.restype = c_int32
+        L.env_potential_kernel_times.argtypes = [c_void_p, POINTER(ctypes.c_float), c_int32, POINTER(c_int32)]
+        L.env_potential_kernel_times.restype = c_int32
         L.env_batch_create.argtypes = [POINTER(c_void_p), c_int32, POINTER(c_void_p)]
         L.env_batch_create.restype = c_int32
         L.env_batch_eval.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_int64),
@@ -180,6 +190,9 @@ def lib():
         L.env_surrogate_loss_grad.argtypes = [c_void_p, c_void_p, c_void_p, c_int64,
                                               POINTER(ctypes.c_float), POINTER(c_double), c_void_p]
         L.env_surrogate_loss_grad.restype = c_int32
+        L.env_surrogate_trace_step.argtypes = [c_void_p, c_void_p, c_void_p, c_int64,
+                                               POINTER(env_surrogate_trace), c_void_p]
+        L.env_surrogate_trace_step.restype = c_int32
         L.env_surrogate_get_params.argtypes = [c_void_p, POINTER(ctypes.c_float), POINTER(c_double),
                                                POINTER(c_double)]
         L.env_surrogate_get_params.restype = c_int32
@@ -476,6 +489,21 @@ class Environment:
                                  stream.cuda_stream)
         return out
 
+    def kernel_timing(self, on: bool = True):
+        """Record HIP events around every later potential-kernel launch."""
+        _check(lib().env_potential_kernel_timing(c_void_p(self.handle), int(bool(on))),
+               "env_potential_kernel_timing")
+
+    def kernel_times(self) -> list:
+        """Durations (ms) of the potential-kernel launches recorded so far."""
+        cnt = c_int32()
+        _check(lib().env_potential_kernel_times(c_void_p(self.handle), None, 0, ctypes.byref(cnt)),
+               "env_potential_kernel_times")
+        ms = (ctypes.c_float * max(cnt.value, 1))()
+        _check(lib().env_potential_kernel_times(c_void_p(self.handle), ms, cnt.value, ctypes.byref(cnt)),
+               "env_potential_kernel_times")
+        return [float(ms[i]) for i in range(cnt.value)]
+
     def autotune(self, points, stream=None):
         """Time the launch shapes at these (n,3) device points; keep the best."""
         import torch
@@ -620,6 +648,28 @@ class Surrogate:
                                              ctypes.byref(loss), c_void_p(st)),
                "env_surrogate_loss_grad")
         return loss.value, g
+
+    def trace_step(self, points, targets, stream=None) -> dict:
+        """One forward/backward pass with every intermediate tensor copied out
+        (env_surrogate_trace_step): H (5,n,128), Z (4,n,128), y, dy, dH
+        (4,n,128), dZ (4,n,128), grad, loss."""
+        import torch
+        points = points.contiguous()
+        targets = targets.to(torch.float32).contiguous()
+        n = points.shape[0]
+        out = {"H": np.zeros((5, n, 128), np.float32), "Z": np.zeros((4, n, 128), np.float32),
+               "y": np.zeros(n, np.float32), "dy": np.zeros(n, np.float32),
+               "dH": np.zeros((4, n, 128), np.float32), "dZ": np.zeros((4, n, 128), np.float32),
+               "grad": np.zeros(N_SURROGATE_PARAMS, np.float32)}
+        tr = env_surrogate_trace()
+        for k in ("H", "Z", "y", "dy", "dH", "dZ", "grad"):
+            setattr(tr, k, out[k].ctypes.data_as(POINTER(ctypes.c_float)))
+        st = (stream or torch.cuda.current_stream()).cuda_stream
+        _check(lib().env_surrogate_trace_step(c_void_p(self.handle), c_void_p(points.data_ptr()),
+                                              c_void_p(targets.data_ptr()), n, ctypes.byref(tr), c_void_p(st)),
+               "env_surrogate_trace_step")
+        out["loss"] = tr.loss
+        return out
 
     def params(self):
         p = np.zeros(N_SURROGATE_PARAMS, dtype=np.float32)

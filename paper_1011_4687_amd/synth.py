@@ -129,6 +129,33 @@ class Environment:
         return h.hexdigest()
 
 
+def subset(env: Environment, fragments, name: Optional[str] = None) -> Environment:
+    """The environment made of the given fragments only (their nuclei, shells
+    and density blocks, in the original order).  Every fragment's block is
+    kept as it is, so the fragments of a partition of an environment add up
+    to the whole."""
+    keep = np.zeros(env.n_fragments, dtype=bool)
+    keep[np.asarray(list(fragments), dtype=np.int64)] = True
+    atoms = np.nonzero(keep[env.fragment])[0]
+    new_atom = -np.ones(env.n_nuclei, dtype=np.int64)
+    new_atom[atoms] = np.arange(len(atoms))
+    frag_ids = np.nonzero(keep)[0]
+    new_frag = -np.ones(env.n_fragments, dtype=np.int64)
+    new_frag[frag_ids] = np.arange(len(frag_ids))
+    shells = [Shell(int(new_atom[s.atom]), s.l, s.exponents, s.coefs)
+              for s in env.shells if keep[env.fragment[s.atom]]]
+    bf_lo, bf_hi, blocks, o = [], [], [], 0
+    for f in frag_ids:
+        n = int(env.bf_hi[f] - env.bf_lo[f])
+        bf_lo.append(o)
+        bf_hi.append(o + n)
+        blocks.append(env.blocks[f])
+        o += n
+    return Environment(name or f"{env.name}-subset", env.xyz[atoms].copy(), env.Z[atoms].copy(),
+                       new_frag[env.fragment[atoms]].astype(np.int32), shells,
+                       np.array(bf_lo, dtype=np.int64), np.array(bf_hi, dtype=np.int64), blocks, env.r_qm)
+
+
 def ncart(l: int) -> int:
     """Number of Cartesian components of a shell of angular momentum l."""
     return (l + 1) * (l + 2) // 2

@@ -164,3 +164,41 @@ def test_rounded_loss_close_to_unrounded():
     # BF16 keeps 8 significant bits: the output moves by far less than its scale
     assert np.max(np.abs(y1 - y0)) < 0.05 * (np.max(np.abs(y0)) + 1.0)
     assert np.max(np.abs(y1 - y0)) > 0.0
+
+
+def test_layer_helpers_chain_to_the_pinned_passes():
+    """The per-layer steps (hidden_pre, hidden_act, output, dz_of,
+    weight_grad, input_grad) chained together give exactly the forward pass
+    and the gradient of loss_and_grads, which the tests above pin against
+    torch autograd and central differences; their scales bound the terms."""
+    from oracle import mlp_oracle as M
+    rng = np.random.default_rng(21)
+    p = rng.standard_normal(M.n_params()) * 0.1
+    B = rng.standard_normal((64, 3)) * 0.3
+    pts = rng.standard_normal((40, 3)) * 2.0
+    t = rng.standard_normal(40)
+    layers, w_out, b_out = M.unpack(p)
+    H = [M.bf16(M.features(pts, B))]
+    Z = []
+    for W, b in layers:
+        z, sc = M.hidden_pre(H[-1], W, b)
+        assert np.all(np.abs(z) <= sc * (1 + 1e-12))
+        Z.append(z)
+        H.append(M.hidden_act(z))
+    y, _ = M.output(H[-1], w_out, b_out)
+    y_ref, _ = M.forward(p, pts, B, rounding=True)
+    assert np.array_equal(y, y_ref)
+    dy = 2.0 * (y - t) / len(t)
+    dH = np.outer(dy, w_out)
+    grads = []
+    for l in range(3, -1, -1):
+        dz = M.dz_of(dH, Z[l])
+        gW, _ = M.weight_grad(M.bf16(dz), H[l])
+        grads.append((l, gW, dz.sum(axis=0)))
+        if l > 0:
+            dH, _ = M.input_grad(M.bf16(dz), layers[l][0])
+    _, g_ref = M.loss_and_grads(p, pts, t, B, rounding=True)
+    for l, gW, gb in grads:
+        o = l * (128 * 128 + 128)
+        assert np.allclose(g_ref[o:o + 128 * 128], gW.ravel(), rtol=1e-12, atol=1e-15)
+        assert np.allclose(g_ref[o + 128 * 128:o + 128 * 128 + 128], gb, rtol=1e-12, atol=1e-15)
