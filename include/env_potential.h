@@ -212,6 +212,25 @@ env_status env_potential_update_density(env_potential* h, const env_density* P, 
 env_status env_potential_eval_field(env_potential* h, const double* points, int64_t n,
                                     double* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same values
+ * as env_potential_eval, with no device allocation and no Morton ordering
+ * (the points are evaluated in the caller's order, as env_potential_eval
+ * does below 32,768 points).  The split-pair partial sums go to a fixed
+ * 64 MiB device array (2^23 float64) that the library holds on each device
+ * it runs this call on until the process ends; the split factor is lowered
+ * until split x n fits it.  Every call on one device shares that array, so
+ * two calls whose executions overlap on one device (different streams, or
+ * different handles on the same device) race and give wrong values: order
+ * them on one stream or with events.  points, out, stream: as
+ * env_potential_eval.  n = 0 is a no-op.
+ * Errors: ENV_E_ARG (NULL with n > 0, n < 0, n above
+ * env_potential_noalloc_max_points() = 8,388,608), ENV_E_STATE (host or
+ * build-only handle), ENV_E_DEVICE (launch failure, symbol lookup). */
+env_status env_potential_eval_noalloc(env_potential* h, const double* points, int64_t n,
+                                      double* out, void* stream);
+int64_t env_potential_noalloc_max_points(void);
+
 /* Several independent evaluations in one persistent launch (convenience
  * form of the env_batch calls below): instance i evaluates handle hs[i] at
  * points[i] (n[i] x 3) into out[i] (n[i]).  All handles must be on the same

@@ -145,6 +145,10 @@ def lib():
         L.env_potential_create.restype = c_int32
         L.env_potential_eval.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]
         L.env_potential_eval.restype = c_int32
+        L.env_potential_eval_noalloc.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]
+        L.env_potential_eval_noalloc.restype = c_int32
+        L.env_potential_noalloc_max_points.argtypes = []
+        L.env_potential_noalloc_max_points.restype = c_int64
         L.env_potential_eval_field.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]
         L.env_potential_eval_field.restype = c_int32
         L.env_potential_update_density.argtypes = [c_void_p, POINTER(env_density), c_void_p]
@@ -257,6 +261,18 @@ def env_potential_eval(handle: int, points_ptr: int, n: int, out_ptr: int,
                                   c_void_p(out_ptr), c_void_p(stream))
     if st != ENV_OK:
         raise EnvError(st, "env_potential_eval")
+
+
+def env_potential_eval_noalloc(handle: int, points_ptr: int, n: int, out_ptr: int,
+                               stream: int = 0) -> None:
+    st = lib().env_potential_eval_noalloc(c_void_p(handle), c_void_p(points_ptr), int(n),
+                                          c_void_p(out_ptr), c_void_p(stream))
+    if st != ENV_OK:
+        raise EnvError(st, "env_potential_eval_noalloc")
+
+
+def env_potential_noalloc_max_points() -> int:
+    return int(lib().env_potential_noalloc_max_points())
 
 
 def env_potential_eval_field(handle: int, points_ptr: int, n: int, out_ptr: int,
@@ -467,6 +483,22 @@ class Environment:
             stream = torch.cuda.current_stream(points.device)
         env_potential_eval(self.handle, points.data_ptr(), n, out.data_ptr(),
                            stream.cuda_stream)
+        return out
+
+    def eval_noalloc(self, points, out, stream=None):
+        """env_potential_eval_noalloc: V at a (n,3) float64 CUDA tensor into the
+        caller's (n,) float64 tensor `out`, with no device allocation."""
+        import torch
+        if not (isinstance(points, torch.Tensor) and points.is_cuda and points.is_contiguous()):
+            raise TypeError("points must be a contiguous torch CUDA tensor")
+        if points.dtype != torch.float64 or points.dim() != 2 or points.shape[1] != 3:
+            raise TypeError("points must be float64 of shape (n, 3)")
+        n = points.shape[0]
+        if out.dtype != torch.float64 or out.numel() != n or not out.is_contiguous():
+            raise TypeError("out must be a contiguous float64 tensor of n elements")
+        if stream is None:
+            stream = torch.cuda.current_stream(points.device)
+        env_potential_eval_noalloc(self.handle, points.data_ptr(), n, out.data_ptr(), stream.cuda_stream)
         return out
 
     def eval_field(self, points, out=None, stream=None):
