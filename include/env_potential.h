@@ -256,10 +256,15 @@ typedef struct env_batch env_batch;
 typedef struct {
     int64_t n_items;          /* work items of the current shape */
     int32_t grid;             /* workgroups of the persistent launch */
-    int32_t reserved;
+    int32_t np;               /* points per lane of the current shape */
     int64_t launches;         /* direct launches */
     int64_t captures;         /* graph captures */
     int64_t graph_launches;   /* graph replays */
+    int32_t granularity;      /* work items per workgroup's fair share of the work */
+    int32_t reserved;
+    int64_t sorted_points;    /* points of the instances evaluated in Morton order */
+    int64_t sorts;            /* evaluations that sorted points */
+    int64_t autotunes;        /* env_batch_autotune calls */
 } env_batch_stats;
 
 /* Errors: ENV_E_ARG (NULL, n_inst <= 0, mixed device/precision), ENV_E_STATE
@@ -267,9 +272,24 @@ typedef struct {
 env_status env_batch_create(env_potential* const* hs, int32_t n_inst, env_batch** out);
 
 /* points[i]: device n[i] x 3 float64; out[i]: device n[i] float64.
- * Asynchronous on `stream` except when the pointers or counts changed. */
+ * Asynchronous on `stream` except when the pointers or counts changed.
+ * Instances of 32,768 points or more are evaluated in Morton order (their
+ * points are sorted into the plan's buffers before each launch; the values
+ * are written back in the caller's order), as env_potential_eval does.
+ * While `stream` is being captured by the caller, the launch is recorded
+ * into the caller's graph without the sort (the plan's pointers and counts
+ * must then be the ones of an earlier call: ENV_E_STATE otherwise). */
 env_status env_batch_eval(env_batch* b, const double* const* points, const int64_t* n,
                           double* const* out, void* stream);
+
+/* Pick the plan's launch shape for these pointers and counts: every pair of
+ * points per lane (FP32C 2 or 4, FP64 1 or 2) and split granularity (4, 8 or
+ * 16 work items per workgroup's fair share) is timed over two graph
+ * replays; the fastest is kept for later calls with the same counts.
+ * Writes out as env_batch_eval does.  Synchronous; stream must not be NULL.
+ * Errors: as env_batch_eval, ENV_E_ARG for a NULL stream. */
+env_status env_batch_autotune(env_batch* b, const double* const* points, const int64_t* n,
+                              double* const* out, void* stream);
 
 env_status env_batch_get_stats(const env_batch* b, env_batch_stats* stats);
 
@@ -466,12 +486,31 @@ env_status env_surrogate_predict(env_surrogate* s, const double* points, int64_t
                                  void* stream);
 
 /* Gated evaluation: points outside the ball or in a failed voxel are
- * evaluated by the exact fallback handle (the same values env_potential_eval
- * gives for the compacted list of those points); used_fallback (device, n
- * bytes, may be NULL) receives 1 for them.  Synchronises the stream once (to
- * size the fallback launch).  ENV_E_STATE before training. */
+ * evaluated by the exact fallback handle; used_fallback (device, n bytes,
+ * may be NULL) receives 1 for them.  Asynchronous: the gated-out points are
+ * compacted on the device and one persistent launch of the fallback's
+ * kernel reads their count there and picks its split factor from it, so the
+ * host never waits (the fallback values equal env_potential_eval's at the
+ * compacted points to rounding: the split factor may differ and no Morton
+ * ordering is applied).  With an exact part set (env_surrogate_set_near)
+ * every other point gets network + baseline + the exact part's V.  Calls
+ * on one surrogate must not overlap (they share its workspace).
+ * ENV_E_STATE before training, after the fallback's density was updated
+ * (env_potential_update_density), or when the exact part left the device. */
 env_status env_surrogate_eval(env_surrogate* s, const double* points, int64_t n, double* out,
                               uint8_t* used_fallback, void* stream);
+
+/* Split surrogate: the network stands in for the potential of part of the
+ * environment only (the fragments far from the region, whose potential is
+ * smooth there), and `near`, an exact handle of the remaining fragments (the
+ * fragments of FMO, Sec. II.B, nearest the QM region), is evaluated at every
+ * point and added.  Train such a surrogate with the far fragments' handle
+ * as teacher; the fallback stays the handle of the whole environment, so a
+ * gated-out point gets the whole environment's exact value.  near: a device
+ * handle on the surrogate's device, or NULL to remove the exact part; it
+ * must outlive its use.  Errors: ENV_E_ARG (s NULL), ENV_E_STATE (near not
+ * a device handle of that device). */
+env_status env_surrogate_set_near(env_surrogate* s, env_potential* near);
 
 /* Diagnostic: loss mean((y - t)^2) and its gradient (host, 66,177 floats) for
  * the current parameters at n device points with device targets t (float32,
@@ -510,6 +549,8 @@ env_status env_surrogate_trace_step(env_surrogate* s, const double* points, cons
 env_status env_surrogate_get_params(const env_surrogate* s, float* params, double* poly,
                                     double* sigma);
 
+/* Statistics; last_eval_fallback is the gated-out count of the last
+ * env_surrogate_eval, read after waiting for that call's stream. */
 env_status env_surrogate_get_info(const env_surrogate* s, env_surrogate_info* info);
 
 void env_surrogate_destroy(env_surrogate* s);

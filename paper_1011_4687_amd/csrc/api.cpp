@@ -103,6 +103,32 @@ EvalArgs make_args(const env_potential* h, const double* points, int64_t n, doub
     return a;
 }
 
+env_status eval_devsized(env_potential* h, const double* points, const int64_t* m, int64_t n_max, double* out,
+                         double* part, int64_t part_cap, unsigned long long* counter, void* stream) {
+    if (!h->on_device) return ENV_E_STATE;
+    if (n_max <= 0) return ENV_OK;
+    if (part_cap < n_max) return ENV_E_ARG;
+    const bool fp64 = h->precision == ENV_PREC_FP64;
+    const int np = fp64 ? 2 : 4;
+    DevSizedArgs d;
+    d.a = make_args(h, points, 0, part, 0);
+    d.m = m;
+    d.segs_all = h->d_segs;
+    d.split_all = h->d_split;
+    for (int k = 0; k <= kMaxSplitLog2; ++k) {
+        d.seg_off[k] = h->seg_off[k];
+        d.split_off[k] = h->split_off[k];
+    }
+    d.part_cap = part_cap;
+    d.want_waves = int64_t(h->cu_count) * 4 * (fp64 ? 48 : 24);
+    d.counter = counter;
+    DeviceGuard g(h->device);
+    if (launch_potential_devsized(d, devsized_grid(h->precision, h->cu_count), h->precision, np, stream) != 0 ||
+        launch_sum_devsized(d, np, n_max, out, stream) != 0)
+        return ENV_E_DEVICE;
+    return ENV_OK;
+}
+
 }  // namespace envpot
 
 namespace {
@@ -121,7 +147,12 @@ void env_options_default(env_options* o) {
 }
 
 const char* env_status_string(env_status s) {
-    switch (s) {
+    // any int may arrive through the C ABI; an out-of-range value must not be
+    // read as an env_status, so the bytes are read as an int
+    static_assert(sizeof(env_status) == sizeof(int32_t), "env_status is int-sized");
+    int32_t v;
+    std::memcpy(&v, &s, sizeof v);
+    switch (v) {
         case ENV_OK: return "ok";
         case ENV_E_ARG: return "invalid argument";
         case ENV_E_UNSUPPORTED: return "unsupported input or option";

@@ -115,6 +115,24 @@ struct BatchArgs {
     int32_t pad;
 };
 
+// A single evaluation whose point count is known only on the device (the
+// gated-out points of a surrogate evaluation).  The persistent kernel reads
+// m, picks the split factor 2^k from it (the rule of the host launcher's
+// default shape, capped so that 2^k * m partials fit part_cap), and drains
+// the (point block, split) items of that shape through a work counter; the
+// sum kernel recomputes the same k and adds the partials.
+struct DevSizedArgs {
+    EvalArgs a;                    // pts, rec, nuc, boys, bp; out = partials [2^k][m]; n ignored
+    const int64_t* m;              // device: number of points
+    const Segment* segs_all;       // every split factor's segment table
+    const int32_t* split_all;
+    int64_t seg_off[kMaxSplitLog2 + 1];
+    int64_t split_off[kMaxSplitLog2 + 1];
+    int64_t part_cap;              // float64 elements of a.out
+    int64_t want_waves;            // waves the split factor aims for
+    unsigned long long* counter;   // zeroed by a kernel before the launch
+};
+
 struct SumDesc {                  // fixed-order sum of S partials of one instance
     const double* part;
     double* out;
@@ -182,5 +200,9 @@ int launch_sum_splits(const double* partial, int S, int64_t n, double* out, void
 int launch_persistent(const BatchArgs& b, int grid, int precision, int np, void* stream);
 int launch_sum_multi(const SumDesc* d, int n_desc, int64_t max_n, void* stream);
 int persistent_grid(int precision, int np, int cu_count);
+int launch_potential_devsized(const DevSizedArgs& d, int grid, int precision, int np, void* stream);
+int launch_sum_devsized(const DevSizedArgs& d, int np, int64_t n_max, double* out, void* stream);
+int devsized_klog(int64_t m, int np, int64_t want_waves, int64_t part_cap);
+int devsized_grid(int precision, int cu_count);
 
 }  // namespace envpot

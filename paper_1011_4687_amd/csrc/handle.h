@@ -75,6 +75,13 @@ void choose_shape(const env_potential* h, int64_t n, int* np, int* klog);
 void host_prepare(env_potential* h, const std::vector<double>& t64);
 env_status host_eval(const env_potential* h, const double* points, int64_t n, double* out);
 
+// Exact evaluation of h at the first *m of n_max device points (count known
+// only on the device) into out[0, *m), asynchronous: one persistent launch
+// plus the fixed-order split sum.  part: part_cap float64 elements (at least
+// n_max) for the split partials; counter: one device word.
+env_status eval_devsized(env_potential* h, const double* points, const int64_t* m, int64_t n_max, double* out,
+                         double* part, int64_t part_cap, unsigned long long* counter, void* stream);
+
 // Arguments of one evaluation (out = V when S == 1, partials otherwise).
 EvalArgs make_args(const env_potential* h, const double* points, int64_t n, double* out, int klog);
 

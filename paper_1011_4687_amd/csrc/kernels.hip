@@ -585,6 +585,57 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     }
 }
 
+// Split factor 2^k of a device-sized evaluation of m points (host and
+// device use this one rule, so both kernels agree on k).
+__host__ __device__ __forceinline__ int devsized_k(int64_t m, int np, int64_t want_waves, int64_t part_cap) {
+    const int64_t waves = (m + 64 * np - 1) / (64 * np);
+    int k = 0;
+    while (k < kMaxSplitLog2 && (waves << k) < want_waves && (m << (k + 1)) <= part_cap) ++k;
+    return k;
+}
+
+// Persistent kernel of a device-sized evaluation: the items (point block,
+// split) of the shape chosen from m are numbered it = pblock * 2^k + s and
+// taken from the counter until it reaches their count; every workgroup
+// reaches that exit test, so the grid drains (also for m = 0).
+template <int NP, bool F64>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_potential_devsized(DevSizedArgs d) {
+    __shared__ float tab32[F64 ? 1 : kBoysMaxRowsF32 * kBoysRowF32];
+    __shared__ unsigned long long item_sh;
+    load_boys_lds<F64>(d.a.boys, d.a.bp.rows32, tab32);
+    const int64_t m = *d.m;
+    const int k = devsized_k(m, NP, d.want_waves, d.part_cap);
+    const int64_t n_items = ((m + (int64_t)kBlock * NP - 1) / ((int64_t)kBlock * NP)) << k;
+    EvalArgs a = d.a;
+    a.n = m;
+    a.segs = d.segs_all + d.seg_off[k];
+    a.split = d.split_all + d.split_off[k];
+    for (;;) {
+        if (threadIdx.x == 0) item_sh = atomicAdd(d.counter, 1ull);
+        __syncthreads();
+        const unsigned long long it_v = item_sh;
+        __syncthreads();
+        const int64_t it = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(it_v >> 32)) << 32) |
+                                     (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)it_v));
+        if (it >= n_items) break;
+        block_work<NP, F64>(a, it >> k, (int)(it & ((1 << k) - 1)), tab32);
+    }
+}
+
+// Fixed-order sum of the 2^k partials of a device-sized evaluation into
+// out[0, m); the grid covers the largest possible m.
+__global__ __launch_bounds__(kBlock) void k_sum_devsized(const double* __restrict__ part, const int64_t* m_ptr,
+                                                         int np, int64_t want_waves, int64_t part_cap,
+                                                         double* __restrict__ out) {
+    const int64_t m = *m_ptr;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= m) return;
+    const int S = 1 << devsized_k(m, np, want_waves, part_cap);
+    double s = 0.0;
+    for (int k = 0; k < S; ++k) s += part[(int64_t)k * m + i];
+    out[i] = s;
+}
+
 __global__ void k_reset_counter(unsigned long long* c) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0ull;
 }
@@ -638,6 +689,41 @@ int launch_persistent(const BatchArgs& b, int grid, int precision, int np, void*
         else if (np == 2) hipLaunchKernelGGL((k_potential_persistent<2, false>), dim3(grid), dim3(kBlock), 0, st, b);
         else hipLaunchKernelGGL((k_potential_persistent<4, false>), dim3(grid), dim3(kBlock), 0, st, b);
     }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int devsized_klog(int64_t m, int np, int64_t want_waves, int64_t part_cap) {
+    return devsized_k(m, np, want_waves, part_cap);
+}
+
+int devsized_grid(int precision, int cu_count) {
+    int per_cu = 0;
+    const hipError_t e =
+        precision == ENV_PREC_FP64
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_potential_devsized<2, true>, kBlock, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_potential_devsized<4, false>, kBlock, 0);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    return per_cu * cu_count;
+}
+
+int launch_potential_devsized(const DevSizedArgs& d, int grid, int precision, int np, void* stream) {
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, d.counter);
+    if (precision == ENV_PREC_FP64) {
+        if (np != 2) return -1;
+        hipLaunchKernelGGL((k_potential_devsized<2, true>), dim3(grid), dim3(kBlock), 0, st, d);
+    } else {
+        if (np != 4) return -1;
+        hipLaunchKernelGGL((k_potential_devsized<4, false>), dim3(grid), dim3(kBlock), 0, st, d);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_sum_devsized(const DevSizedArgs& d, int np, int64_t n_max, double* out, void* stream) {
+    if (n_max <= 0) return 0;
+    const dim3 grid((unsigned)((n_max + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(k_sum_devsized, grid, dim3(kBlock), 0, static_cast<hipStream_t>(stream), d.a.out, d.m, np,
+                       d.want_waves, d.part_cap, out);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -20,6 +20,17 @@ int sort_points(const double* points, int64_t n, double* sorted, uint32_t* order
 // out[order[i]] = v[i].
 int scatter_values(const double* v, const uint32_t* order, int64_t n, double* out, void* stream);
 
+// One instance of a multi-instance scatter: out[order[i]] = v[i], i < n.
+struct ScatterDesc {
+    const double* v;
+    const uint32_t* order;
+    double* out;
+    int64_t n;
+};
+
+// The scatters of n_desc instances in one launch (grid.y = instance).
+int scatter_values_multi(const ScatterDesc* d, int n_desc, int64_t max_n, void* stream);
+
 // Rows of 4: out[4 order[i] + c] = v[4 i + c].
 int scatter_rows4(const double* v, const uint32_t* order, int64_t n, double* out, void* stream);
 

@@ -72,6 +72,13 @@ __global__ __launch_bounds__(kSortBlock) void k_scatter4(const double* __restric
     for (int c = 0; c < 4; ++c) out[4 * j + c] = v[4 * i + c];
 }
 
+__global__ __launch_bounds__(kSortBlock) void k_scatter_multi(const ScatterDesc* __restrict__ d) {
+    const ScatterDesc q = d[blockIdx.y];
+    const int64_t i = int64_t(blockIdx.x) * kSortBlock + threadIdx.x;
+    if (i >= q.n) return;
+    q.out[q.order[i]] = q.v[i];
+}
+
 unsigned blocks(int64_t n) { return unsigned((n + kSortBlock - 1) / kSortBlock); }
 
 }  // namespace
@@ -119,6 +126,13 @@ int scatter_values(const double* v, const uint32_t* order, int64_t n, double* ou
     if (n <= 0) return 0;
     hipLaunchKernelGGL(k_scatter, dim3(blocks(n)), dim3(kSortBlock), 0, static_cast<hipStream_t>(stream), v, order,
                        n, out);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int scatter_values_multi(const ScatterDesc* d, int n_desc, int64_t max_n, void* stream) {
+    if (n_desc <= 0 || max_n <= 0) return 0;
+    hipLaunchKernelGGL(k_scatter_multi, dim3(blocks(max_n), unsigned(n_desc)), dim3(kSortBlock), 0,
+                       static_cast<hipStream_t>(stream), d);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -110,6 +110,7 @@ int64_t round32(int64_t n) { return std::max<int64_t>(32, (n + 31) / 32 * 32); }
 
 struct env_surrogate {
     env_potential* fallback = nullptr;
+    env_potential* near = nullptr;   // exactly evaluated part added to the network (may be null)
     uint64_t fallback_gen = 0;   // the fallback's density generation when the network was trained
     int device = -1;
     double radius = 6.0;
@@ -128,7 +129,10 @@ struct env_surrogate {
     double* d_coef = nullptr;
     int8_t* d_mono = nullptr;
     uint8_t* d_pass = nullptr;
+    int64_t* d_nfb = nullptr;              // gated-out count of the last evaluation
+    unsigned long long* d_counter = nullptr;  // work counter of the fallback launch
     int G = 0;
+    void* eval_stream = nullptr;           // stream of the last evaluation
     int64_t step = 0;
     Workspace ws;
     env_surrogate_info info{};
@@ -203,8 +207,10 @@ void backward(env_surrogate* s, const float* t, int64_t n, int64_t Np, void* st,
     }
 }
 
-// Surrogate values (baseline + network) at n points, in chunks.
-env_status predict(env_surrogate* s, const double* pts, int64_t n, double* out, void* st) {
+// Surrogate values (baseline + network, plus add[i] when add is not null) at
+// n points, in chunks.
+env_status predict(env_surrogate* s, const double* pts, int64_t n, double* out, void* st,
+                   const double* add = nullptr) {
     const int64_t chunk = 65536;
     if (!ws_ensure(s->ws, std::min(round32(n), chunk), s->ws.train)) return ENV_E_NOMEM;
     for (int64_t o = 0; o < n; o += chunk) {
@@ -212,7 +218,7 @@ env_status predict(env_surrogate* s, const double* pts, int64_t n, double* out, 
         const int64_t Np = round32(m);
         forward(s, pts + 3 * o, m, Np, false, st);
         sg_finish(pts + 3 * o, s->ws.y, m, s->d_coef, s->d_mono, int(s->mono.size() / 3), 1.0 / s->radius,
-                  s->sigma, out + o, st);
+                  s->sigma, add ? add + o : nullptr, out + o, st);
     }
     return sg_last_error() == 0 ? ENV_OK : ENV_E_DEVICE;
 }
@@ -281,6 +287,8 @@ void destroy(env_surrogate* s) {
     (void)hipFree(s->d_coef);
     (void)hipFree(s->d_mono);
     (void)hipFree(s->d_pass);
+    (void)hipFree(s->d_nfb);
+    (void)hipFree(s->d_counter);
     delete s;
 }
 
@@ -326,7 +334,8 @@ env_status env_surrogate_create(env_potential* fallback, const env_surrogate_spe
     bool ok = dalloc(&s->d_B, 3 * kFreq) && dalloc(&s->d_params, kNParams) && dalloc(&s->d_grad, kNParams) &&
               dalloc(&s->d_m, kNParams) && dalloc(&s->d_v, kNParams) &&
               dalloc(&s->d_W, size_t(kLayers) * kHidden * kHidden) &&
-              dalloc(&s->d_WT, size_t(kLayers) * kHidden * kHidden);
+              dalloc(&s->d_WT, size_t(kLayers) * kHidden * kHidden) && dalloc(&s->d_nfb, 1) &&
+              dalloc(&s->d_counter, 1);
     if (!ok) {
         destroy(s);
         return ENV_E_NOMEM;
@@ -334,7 +343,8 @@ env_status env_surrogate_create(env_potential* fallback, const env_surrogate_spe
     if (hipMemcpy(s->d_B, spec->B, 3 * kFreq * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(s->d_params, spec->params, kNParams * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(s->d_m, 0, kNParams * sizeof(float)) != hipSuccess ||
-        hipMemset(s->d_v, 0, kNParams * sizeof(float)) != hipSuccess) {
+        hipMemset(s->d_v, 0, kNParams * sizeof(float)) != hipSuccess ||
+        hipMemset(s->d_nfb, 0, sizeof(int64_t)) != hipSuccess) {
         destroy(s);
         return ENV_E_DEVICE;
     }
@@ -637,6 +647,13 @@ env_status env_surrogate_train(env_surrogate* s, env_potential* teacher, const e
     return ENV_OK;
 }
 
+env_status env_surrogate_set_near(env_surrogate* s, env_potential* near) {
+    if (!s) return ENV_E_ARG;
+    if (near && (!near->on_device || near->device != s->device)) return ENV_E_STATE;
+    s->near = near;
+    return ENV_OK;
+}
+
 env_status env_surrogate_eval(env_surrogate* s, const double* points, int64_t n, double* out,
                               uint8_t* used_fallback, void* stream) {
     if (!s || n < 0) return ENV_E_ARG;
@@ -644,51 +661,45 @@ env_status env_surrogate_eval(env_surrogate* s, const double* points, int64_t n,
     if (!points || !out) return ENV_E_ARG;
     if (!s->d_pass) return ENV_E_STATE;  // no gate before training
     if (s->fallback->density_gen != s->fallback_gen) return ENV_E_STATE;  // trained on an old density
+    if (s->near && (!s->near->on_device || s->near->device != s->device)) return ENV_E_STATE;
     DeviceGuard g(s->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int nb = int((n + 255) / 256);
+    // the gated-out count stays on the device: the compacted list is sized
+    // for all n points and the fallback launch reads the count itself
+    const int64_t part_cap = std::max<int64_t>(n, int64_t(1) << 23);
     uint8_t* flag = nullptr;
     int32_t* counts = nullptr;
-    int64_t *offs = nullptr, *total = nullptr, *idx = nullptr;
-    double *cpts = nullptr, *vals = nullptr;
-    bool ok = hipMallocAsync(reinterpret_cast<void**>(&flag), size_t(n), st) == hipSuccess &&
-              hipMallocAsync(reinterpret_cast<void**>(&counts), size_t(nb) * 4, st) == hipSuccess &&
-              hipMallocAsync(reinterpret_cast<void**>(&offs), size_t(nb) * 8, st) == hipSuccess &&
-              hipMallocAsync(reinterpret_cast<void**>(&total), 8, st) == hipSuccess;
+    int64_t *offs = nullptr, *idx = nullptr;
+    double *cpts = nullptr, *vals = nullptr, *part = nullptr, *add = nullptr;
+    auto amalloc = [&](auto** p, size_t bytes) {
+        return hipMallocAsync(reinterpret_cast<void**>(p), std::max<size_t>(bytes, 8), st) == hipSuccess;
+    };
+    bool ok = amalloc(&flag, size_t(n)) && amalloc(&counts, size_t(nb) * 4) && amalloc(&offs, size_t(nb) * 8) &&
+              amalloc(&idx, size_t(n) * 8) && amalloc(&cpts, size_t(n) * 24) && amalloc(&vals, size_t(n) * 8) &&
+              amalloc(&part, size_t(part_cap) * 8) && (!s->near || amalloc(&add, size_t(n) * 8));
     env_status rc = ok ? ENV_OK : ENV_E_NOMEM;
-    int64_t m = 0;
     if (rc == ENV_OK) {
         sg_gate_flags(points, n, s->d_pass, s->G, s->radius, flag, counts, stream);
-        sg_scan_counts(counts, nb, offs, total, stream);
-        if (hipMemcpyAsync(&m, total, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess)
-            rc = ENV_E_DEVICE;
+        sg_scan_counts(counts, nb, offs, s->d_nfb, stream);
+        if (s->near) rc = env_potential_eval(s->near, points, n, add, stream);
     }
-    if (rc == ENV_OK) rc = predict(s, points, n, out, stream);
-    if (rc == ENV_OK && m > 0) {
-        if (hipMallocAsync(reinterpret_cast<void**>(&idx), size_t(m) * 8, st) != hipSuccess ||
-            hipMallocAsync(reinterpret_cast<void**>(&cpts), size_t(m) * 24, st) != hipSuccess ||
-            hipMallocAsync(reinterpret_cast<void**>(&vals), size_t(m) * 8, st) != hipSuccess) {
-            rc = ENV_E_NOMEM;
-        } else {
-            sg_compact(points, n, flag, offs, idx, cpts, stream);
-            rc = env_potential_eval(s->fallback, cpts, m, vals, stream);
-            if (rc == ENV_OK) sg_scatter(vals, idx, m, out, stream);
-        }
+    if (rc == ENV_OK) rc = predict(s, points, n, out, stream, add);
+    if (rc == ENV_OK) {
+        sg_compact(points, n, flag, offs, idx, cpts, stream);
+        rc = eval_devsized(s->fallback, cpts, s->d_nfb, n, vals, part, part_cap, s->d_counter, stream);
     }
+    if (rc == ENV_OK) sg_scatter(vals, idx, s->d_nfb, n, out, stream);
     if (rc == ENV_OK && used_fallback &&
         hipMemcpyAsync(used_fallback, flag, size_t(n), hipMemcpyDeviceToDevice, st) != hipSuccess)
         rc = ENV_E_DEVICE;
     if (rc == ENV_OK && sg_last_error() != 0) rc = ENV_E_DEVICE;
-    (void)hipFreeAsync(flag, st);
-    (void)hipFreeAsync(counts, st);
-    (void)hipFreeAsync(offs, st);
-    (void)hipFreeAsync(total, st);
-    if (idx) (void)hipFreeAsync(idx, st);
-    if (cpts) (void)hipFreeAsync(cpts, st);
-    if (vals) (void)hipFreeAsync(vals, st);
+    for (void* p : {static_cast<void*>(flag), static_cast<void*>(counts), static_cast<void*>(offs),
+                    static_cast<void*>(idx), static_cast<void*>(cpts), static_cast<void*>(vals),
+                    static_cast<void*>(part), static_cast<void*>(add)})
+        if (p) (void)hipFreeAsync(p, st);
     s->info.last_eval_n = n;
-    s->info.last_eval_fallback = m;
+    s->eval_stream = stream;
     return rc;
 }
 
@@ -705,6 +716,16 @@ env_status env_surrogate_get_params(const env_surrogate* s, float* params, doubl
 env_status env_surrogate_get_info(const env_surrogate* s, env_surrogate_info* info) {
     if (!s || !info) return ENV_E_ARG;
     *info = s->info;
+    if (s->info.last_eval_n > 0) {
+        // the last evaluation's gated-out count, read once that call is done
+        DeviceGuard g(s->device);
+        int64_t m = 0;
+        hipStream_t st = static_cast<hipStream_t>(s->eval_stream);
+        if (hipStreamSynchronize(st) != hipSuccess ||
+            hipMemcpy(&m, s->d_nfb, sizeof(m), hipMemcpyDeviceToHost) != hipSuccess)
+            return ENV_E_DEVICE;
+        info->last_eval_fallback = m;
+    }
     return ENV_OK;
 }
 

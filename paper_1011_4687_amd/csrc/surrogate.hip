@@ -217,11 +217,13 @@ __global__ __launch_bounds__(256) void k_pack(const float* __restrict__ params, 
     WT[(int64_t)l * kHidden * kHidden + i * kHidden + o] = b;
 }
 
-// V = poly(r/R) + sigma * y (FP64).
+// V = poly(r/R) + sigma * y (FP64), plus add[i] when add is not null (the
+// exactly evaluated part of a split surrogate).
 __global__ __launch_bounds__(256) void k_finish(const double* __restrict__ pts, const float* __restrict__ y,
                                                 int64_t n, const double* __restrict__ coef,
                                                 const int8_t* __restrict__ mono, int nmono, double inv_r,
-                                                double sigma, double* __restrict__ out) {
+                                                double sigma, const double* __restrict__ add,
+                                                double* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     double px[kMaxPolyDegree + 1], py[kMaxPolyDegree + 1], pz[kMaxPolyDegree + 1];
@@ -234,7 +236,8 @@ __global__ __launch_bounds__(256) void k_finish(const double* __restrict__ pts, 
     }
     double v = 0.0;
     for (int k = 0; k < nmono; ++k) v += coef[k] * px[mono[3 * k]] * py[mono[3 * k + 1]] * pz[mono[3 * k + 2]];
-    out[i] = v + sigma * (double)y[i];
+    v += sigma * (double)y[i];
+    out[i] = add ? v + add[i] : v;
 }
 
 // Residual targets t = (V - poly(r/R)) / sigma.
@@ -398,10 +401,12 @@ __global__ __launch_bounds__(256) void k_compact(const double* __restrict__ pts,
     }
 }
 
+// out[idx[k]] = vals[k] for k < *m (the count is read on the device; the
+// grid covers the largest possible count).
 __global__ __launch_bounds__(256) void k_scatter(const double* __restrict__ vals, const int64_t* __restrict__ idx,
-                                                 int64_t m, double* __restrict__ out) {
+                                                 const int64_t* __restrict__ m, double* __restrict__ out) {
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (k < m) out[idx[k]] = vals[k];
+    if (k < *m) out[idx[k]] = vals[k];
 }
 
 // max |a - b| per voxel (m consecutive samples per voxel), FP64.
@@ -471,8 +476,8 @@ void sg_pack(const float* params, uint16_t* W, uint16_t* WT, void* st) {
 }
 
 void sg_finish(const double* pts, const float* y, int64_t n, const double* coef, const int8_t* mono, int nmono,
-               double inv_r, double sigma, double* out, void* st) {
-    SG_LAUNCH(k_finish, dim3(blocks(n)), dim3(256), st, pts, y, n, coef, mono, nmono, inv_r, sigma, out);
+               double inv_r, double sigma, const double* add, double* out, void* st) {
+    SG_LAUNCH(k_finish, dim3(blocks(n)), dim3(256), st, pts, y, n, coef, mono, nmono, inv_r, sigma, add, out);
 }
 
 void sg_residual(const double* pts, const double* V, int64_t n, const double* coef, const int8_t* mono,
@@ -508,8 +513,9 @@ void sg_compact(const double* pts, int64_t n, const uint8_t* flag, const int64_t
     SG_LAUNCH(k_compact, dim3(blocks(n)), dim3(256), st, pts, n, flag, offsets, idx, cpts);
 }
 
-void sg_scatter(const double* vals, const int64_t* idx, int64_t m, double* out, void* st) {
-    SG_LAUNCH(k_scatter, dim3(blocks(m)), dim3(256), st, vals, idx, m, out);
+void sg_scatter(const double* vals, const int64_t* idx, const int64_t* m, int64_t n_max, double* out, void* st) {
+    if (n_max <= 0) return;
+    SG_LAUNCH(k_scatter, dim3(blocks(n_max)), dim3(256), st, vals, idx, m, out);
 }
 
 void sg_voxel_maxerr(const double* a, const double* b, int64_t nv, int m, double* err, void* st) {

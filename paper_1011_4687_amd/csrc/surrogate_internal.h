@@ -31,7 +31,7 @@ void sg_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, 
              float bc1, float bc2, void* st);
 void sg_pack(const float* params, uint16_t* W, uint16_t* WT, void* st);
 void sg_finish(const double* pts, const float* y, int64_t n, const double* coef, const int8_t* mono, int nmono,
-               double inv_r, double sigma, double* out, void* st);
+               double inv_r, double sigma, const double* add, double* out, void* st);
 void sg_residual(const double* pts, const double* V, int64_t n, const double* coef, const int8_t* mono,
                  int nmono, double inv_r, double inv_sigma, float* t, void* st);
 void sg_sample_ball(uint64_t seed, int64_t n, double R, double* pts, void* st);
@@ -43,7 +43,7 @@ int sg_gate_flags(const double* pts, int64_t n, const uint8_t* pass, int G, doub
 void sg_scan_counts(const int32_t* counts, int nb, int64_t* offsets, int64_t* total, void* st);
 void sg_compact(const double* pts, int64_t n, const uint8_t* flag, const int64_t* offsets, int64_t* idx,
                 double* cpts, void* st);
-void sg_scatter(const double* vals, const int64_t* idx, int64_t m, double* out, void* st);
+void sg_scatter(const double* vals, const int64_t* idx, const int64_t* m, int64_t n_max, double* out, void* st);
 void sg_voxel_maxerr(const double* a, const double* b, int64_t nv, int m, double* err, void* st);
 int sg_last_error();
 

@@ -77,8 +77,10 @@ class env_info(ctypes.Structure):
 
 
 class env_batch_stats(ctypes.Structure):
-    _fields_ = [("n_items", c_int64), ("grid", c_int32), ("reserved", c_int32),
-                ("launches", c_int64), ("captures", c_int64), ("graph_launches", c_int64)]
+    _fields_ = [("n_items", c_int64), ("grid", c_int32), ("np", c_int32),
+                ("launches", c_int64), ("captures", c_int64), ("graph_launches", c_int64),
+                ("granularity", c_int32), ("reserved", c_int32), ("sorted_points", c_int64),
+                ("sorts", c_int64), ("autotunes", c_int64)]
 
 
 class env_server_stats(ctypes.Structure):
@@ -177,6 +179,9 @@ def lib():
         L.env_batch_eval.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_int64),
                                      POINTER(c_void_p), c_void_p]
         L.env_batch_eval.restype = c_int32
+        L.env_batch_autotune.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_int64),
+                                         POINTER(c_void_p), c_void_p]
+        L.env_batch_autotune.restype = c_int32
         L.env_batch_get_stats.argtypes = [c_void_p, POINTER(env_batch_stats)]
         L.env_batch_get_stats.restype = c_int32
         L.env_batch_destroy.argtypes = [c_void_p]
@@ -194,6 +199,8 @@ def lib():
         L.env_surrogate_loss_grad.argtypes = [c_void_p, c_void_p, c_void_p, c_int64,
                                               POINTER(ctypes.c_float), POINTER(c_double), c_void_p]
         L.env_surrogate_loss_grad.restype = c_int32
+        L.env_surrogate_set_near.argtypes = [c_void_p, c_void_p]
+        L.env_surrogate_set_near.restype = c_int32
         L.env_surrogate_trace_step.argtypes = [c_void_p, c_void_p, c_void_p, c_int64,
                                                POINTER(env_surrogate_trace), c_void_p]
         L.env_surrogate_trace_step.restype = c_int32
@@ -578,6 +585,20 @@ class Batch:
                        [o.data_ptr() for o in outs], stream.cuda_stream)
         return outs
 
+    def autotune(self, points: Sequence, outs: Sequence, stream=None):
+        """env_batch_autotune: time the plan's launch shapes on these buffers
+        and keep the fastest (synchronous; writes outs)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        n = len(points)
+        pp = (c_void_p * n)(*[p.data_ptr() for p in points])
+        nn = (c_int64 * n)(*[p.shape[0] for p in points])
+        oo = (c_void_p * n)(*[o.data_ptr() for o in outs])
+        _check(lib().env_batch_autotune(c_void_p(self.handle), pp, nn, oo, c_void_p(stream.cuda_stream)),
+               "env_batch_autotune")
+        return outs
+
     def stats(self) -> dict:
         return env_batch_get_stats(self.handle)
 
@@ -628,6 +649,14 @@ class Surrogate:
                                           ctypes.byref(h)), "env_surrogate_create")
         self.handle = h.value
         self.radius = radius
+        self.near = None
+
+    def set_near(self, near: Optional[Environment]):
+        """Exact part added to the network (env_surrogate_set_near): the
+        handle of the fragments the network does not cover, or None."""
+        _check(lib().env_surrogate_set_near(c_void_p(self.handle), c_void_p(near.handle if near else None)),
+               "env_surrogate_set_near")
+        self.near = near
 
     @staticmethod
     def default_opts(**kw) -> env_train_opts:
@@ -644,28 +673,35 @@ class Surrogate:
         _check(lib().env_surrogate_train(c_void_p(self.handle), c_void_p(teacher.handle),
                                          ctypes.byref(o), c_void_p(st)), "env_surrogate_train")
 
-    def predict(self, points, stream=None):
+    def predict(self, points, stream=None, out=None):
+        """Network + baseline (no gate, no exact part) at (n,3) float64
+        device points."""
         import torch
         points = points.contiguous()
-        out = torch.empty(points.shape[0], dtype=torch.float64, device=points.device)
+        if out is None:
+            out = torch.empty(points.shape[0], dtype=torch.float64, device=points.device)
         st = (stream or torch.cuda.current_stream()).cuda_stream
         _check(lib().env_surrogate_predict(c_void_p(self.handle), c_void_p(points.data_ptr()),
                                            points.shape[0], c_void_p(out.data_ptr()), c_void_p(st)),
                "env_surrogate_predict")
         return out
 
-    def eval(self, points, stream=None):
-        """(V, used_fallback) at (n,3) float64 device points."""
+    def eval(self, points, stream=None, out=None, used=None):
+        """(V, used_fallback) at (n,3) float64 device points; asynchronous."""
         import torch
         points = points.contiguous()
         n = points.shape[0]
-        out = torch.empty(n, dtype=torch.float64, device=points.device)
-        fb = torch.empty(n, dtype=torch.uint8, device=points.device)
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=points.device)
+        if used is None:
+            used = torch.empty(n, dtype=torch.uint8, device=points.device)
+        if out.dtype != torch.float64 or out.numel() != n or used.dtype != torch.uint8 or used.numel() != n:
+            raise TypeError("out must be float64 and used uint8, n elements each")
         st = (stream or torch.cuda.current_stream()).cuda_stream
         _check(lib().env_surrogate_eval(c_void_p(self.handle), c_void_p(points.data_ptr()), n,
-                                        c_void_p(out.data_ptr()), c_void_p(fb.data_ptr()),
+                                        c_void_p(out.data_ptr()), c_void_p(used.data_ptr()),
                                         c_void_p(st)), "env_surrogate_eval")
-        return out, fb
+        return out, used
 
     def loss_grad(self, points, targets, stream=None):
         import torch
@@ -831,20 +867,28 @@ def _density(P, nbf: int, keep: list) -> "env_density":
     """env_density of a dense (nbf, nbf) array or a CSR triple; the arrays
     are appended to ``keep`` (they must live until the call returns)."""
     dens = env_density()
-    dens.nbf = nbf
+    # the size passed is the array's own, so the library reads within it and
+    # rejects a size that does not match the basis (ENV_E_ARG)
     if isinstance(P, tuple):
         rowp, col, val = P
         rowp = np.ascontiguousarray(rowp, dtype=np.int64)
         col = np.ascontiguousarray(col, dtype=np.int32)
         val = np.ascontiguousarray(val, dtype=np.float64)
+        if rowp.ndim != 1 or rowp.shape[0] < 1 or col.shape != val.shape or col.ndim != 1 or \
+                int(rowp[-1]) > val.shape[0] or int(rowp.min()) < 0:
+            raise ValueError("CSR density: row_ptr (nbf+1), col and values (nnz) do not fit together")
         keep += [rowp, col, val]
+        dens.nbf = rowp.shape[0] - 1
         dens.format = ENV_DENSITY_CSR
         dens.values = _dp(val)
         dens.row_ptr = rowp.ctypes.data_as(POINTER(c_int64))
         dens.col = col.ctypes.data_as(POINTER(c_int32))
     else:
         Pd = np.ascontiguousarray(P, dtype=np.float64)
+        if Pd.ndim != 2 or Pd.shape[0] != Pd.shape[1]:
+            raise ValueError("dense density must be a square (nbf, nbf) array")
         keep.append(Pd)
+        dens.nbf = Pd.shape[0]
         dens.format = ENV_DENSITY_DENSE
         dens.values = _dp(Pd)
     return dens

@@ -154,3 +154,113 @@ def test_autotune_keeps_results(precision):
     else:
         assert np.abs(V[idx] - Vo).max() <= 1e-5
     E.close()
+
+
+def _large_instances(precision):
+    """Three instances, one of 40,000 points (evaluated in Morton order by
+    the plan) and two small ones."""
+    from oracle import oracle as O
+    from paper_1011_4687_amd.envpot import Environment
+    out = []
+    for k, (na, npts) in enumerate(((70, 40000), (50, 3000), (90, 777))):
+        rng = np.random.Generator(np.random.PCG64(5100 + k))
+        env = synth.make_fragmented(na, rng)
+        pts = synth.points_in_ball(rng, npts, env.r_qm)
+        P = env.density_csr(O.neutral_scales(env))
+        shells = [(s.atom, s.l, s.exponents, s.coefs) for s in env.shells]
+        out.append((env, pts, P, Environment(env.xyz, env.Z, env.fragment, shells, P, precision=precision)))
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp32c", "fp64"])
+def test_batch_morton_instance_and_autotune(precision):
+    """An instance of 40,000 points is sorted into the plan's buffers and
+    scattered back: the plan matches single evaluations (which order those
+    points the same way, with their own split factors) to rounding and the
+    oracle on sampled points; env_batch_autotune keeps the values and
+    records its choice; replays stay bitwise equal."""
+    import torch
+    from oracle import oracle as O
+    from paper_1011_4687_amd.envpot import Batch
+    print(f"[batched] morton + autotune {precision}", flush=True)
+    insts = _large_instances(precision)
+    hs = [E for *_, E in insts]
+    pts = [torch.from_numpy(p).cuda() for _, p, _, _ in insts]
+    outs = [torch.zeros(p.shape[0], dtype=torch.float64, device="cuda") for p in pts]
+    s = torch.cuda.Stream()
+    B = Batch(hs)
+    with torch.cuda.stream(s):
+        B.eval(pts, outs, stream=s)
+    s.synchronize()
+    st = B.stats()
+    assert st["sorted_points"] == 40000 and st["sorts"] == 1
+    tol = 2e-6 if precision == "fp32c" else 1e-11
+    first = [o.cpu().numpy() for o in outs]
+    for k, ((env, p, P, E), got) in enumerate(zip(insts, first)):
+        single = E.eval(pts[k]).cpu().numpy()
+        assert np.abs(got - single).max() <= tol, k
+        idx = np.unique(np.linspace(0, len(got) - 1, 8).astype(int))
+        Vo, _, _, A = O.potential(env, p[idx], P=P, screen=True)
+        if precision == "fp64":
+            assert np.all(np.abs(got[idx] - Vo) <= 1e-12 * A), k
+        else:
+            assert np.abs(got[idx] - Vo).max() <= 1e-5, k
+    with torch.cuda.stream(s):
+        B.autotune(pts, outs, stream=s)
+    st = B.stats()
+    assert st["autotunes"] == 1 and st["np"] in ((2, 4) if precision == "fp32c" else (1, 2))
+    assert st["granularity"] in (4, 8, 16)
+    tuned = None
+    for rep in range(3):
+        for o in outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            B.eval(pts, outs, stream=s)
+        s.synchronize()
+        cur = [o.cpu().numpy() for o in outs]
+        if tuned is None:
+            tuned = cur
+        for a, b, c in zip(cur, tuned, first):
+            assert np.array_equal(a, b), rep
+            assert np.abs(a - c).max() <= tol
+    B.close()
+    for *_, E in insts:
+        E.close()
+
+
+def test_batch_recorded_into_callers_graph():
+    """A plan evaluated while the caller captures its stream is recorded into
+    the caller's graph (direct table, no sort); every replay, with eager work
+    and synchronisation between replays, equals the plan's own evaluation to
+    rounding (the 40,000-point instance is in caller order there)."""
+    import torch
+    from paper_1011_4687_amd.envpot import Batch
+    print("[batched] caller's graph", flush=True)
+    insts = _large_instances("fp32c")
+    hs = [E for *_, E in insts]
+    pts = [torch.from_numpy(p).cuda() for _, p, _, _ in insts]
+    outs = [torch.zeros(p.shape[0], dtype=torch.float64, device="cuda") for p in pts]
+    B = Batch(hs)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        B.eval(pts, outs, stream=s)       # sets up the tables outside the capture
+    s.synchronize()
+    ref = [o.clone() for o in outs]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        B.eval(pts, outs, stream=torch.cuda.current_stream())
+    for rep in range(3):
+        for o in outs:
+            o.fill_(float("nan"))
+        junk = torch.randn(4096, device="cuda").sum()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, r in zip(outs, ref):
+            d = (o - r).abs().max().item()
+            assert d <= 2e-6, (rep, d)
+        del junk
+    B.close()
+    for *_, E in insts:
+        E.close()

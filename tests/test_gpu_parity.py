@@ -44,22 +44,56 @@ def test_tiny_all_points(precision):
     E.close()
 
 
+def _golden(name, env, pts):
+    """Stored oracle values (tests/golden/<name>, written by
+    tests/golden/make_goldens.py from the oracle alone) for this workload."""
+    import os
+    from paper_1011_4687_amd import synth
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} not written yet")
+    g = dict(np.load(path))
+    assert str(g["env_digest"]) == env.digest() and str(g["points_digest"]) == synth.digest(pts)
+    return g
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
 def test_mid_full_size_sampled(precision):
     """The mid workload at its full size (131072 points, the benchmark's
-    launch configuration); the oracle checks 256 sampled points."""
+    launch configuration) against the stored screened-oracle values at
+    16,384 seeded-random points; FP32C also against the unscreened oracle on
+    32 of them (the screening error is inside the 1e-5 Ha budget)."""
     from oracle import oracle as O
     print(f"[parity] mid {precision}", flush=True)
     E, env, pts, P = _env("mid", precision)
     V = _gpu(E, pts)
-    idx = sample_indices(len(pts), 256)
+    g = _golden("mid_oracle_16384.npz", env, pts)
+    idx, Vo, A = g["idx"], g["V"], g["A"]
+    err = np.abs(V[idx] - Vo)
+    print(f"[parity] mid {precision}: max {err.max():.3e} Ha, rms {np.sqrt(np.mean(err ** 2)):.3e}, "
+          f"max/A {(err / A).max():.3e} on {len(idx)} points", flush=True)
     if precision == "fp64":
-        Vo, _, _, A = O.potential(env, pts[idx], P=P, screen=True)
-        assert np.all(np.abs(V[idx] - Vo) <= FP64_REL * A), (np.abs(V[idx] - Vo) / A).max()
+        assert np.all(err <= FP64_REL * A), (err / A).max()
     else:
-        Vo, _, _, A = O.potential(env, pts[idx], P=P, screen=False)
-        assert np.abs(V[idx] - Vo).max() <= FP32_TOL
+        assert err.max() <= FP32_TOL
+        sub = idx[:: len(idx) // 32][:32]
+        Vf, _, _, _ = O.potential(env, pts[sub], P=P, screen=False)
+        assert np.abs(V[sub] - Vf).max() <= FP32_TOL
     E.close()
+
+
+def test_mid_fp32c_against_fp64_every_point():
+    """Every point of the full mid launch: FP32C against the FP64 kernel
+    (which the oracle pins at 1e-12 A), so the FP32C error tail is seen on all
+    131,072 points, not only on the oracle's sample."""
+    print("[parity] mid fp32c vs fp64, all points", flush=True)
+    E32, env, pts, P = _env("mid", "fp32c")
+    E64, _, _, _ = _env("mid", "fp64")
+    d = np.abs(_gpu(E32, pts) - _gpu(E64, pts))
+    print(f"[parity] mid fp32c - fp64: max {d.max():.3e}, rms {np.sqrt(np.mean(d ** 2)):.3e}", flush=True)
+    assert d.max() <= FP32_TOL
+    E32.close()
+    E64.close()
 
 
 @pytest.mark.parametrize("n", [1, 63, 255, 257, 1000, 4097])
