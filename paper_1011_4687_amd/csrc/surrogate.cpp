@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <random>
@@ -131,6 +132,7 @@ struct env_surrogate {
     uint8_t* d_pass = nullptr;
     int64_t* d_nfb = nullptr;              // gated-out count of the last evaluation
     unsigned long long* d_counter = nullptr;  // work counter of the fallback launch
+    TrainState* d_tstate = nullptr;        // device step counter of training
     int G = 0;
     void* eval_stream = nullptr;           // stream of the last evaluation
     int64_t step = 0;
@@ -152,17 +154,11 @@ env_status upload_baseline(env_surrogate* s) {
     return ENV_OK;
 }
 
-// Forward pass of rows [0, Np) whose first n are real points; y in ws.y.
-void forward(env_surrogate* s, const double* pts, int64_t n, int64_t Np, bool train, void* st) {
+// Forward pass of rows [0, Np) whose first n are real points, storing what
+// the backward pass reads (H and H^T of every layer, Z, y in ws.y); one launch.
+void forward(env_surrogate* s, const double* pts, int64_t n, int64_t Np, void* st) {
     Workspace& w = s->ws;
-    sg_features(pts, n, Np, s->d_B, kFreq, w.H[0], train ? w.HT[0] : nullptr, Np, st);
-    for (int l = 0; l < kLayers; ++l) {
-        sg_gemm_nt(w.H[l], kHidden, s->d_W + size_t(l) * kHidden * kHidden, kHidden, w.Z[l], kHidden, int(Np),
-                   kHidden, kHidden, 1, st);
-        sg_bias_silu(w.Z[l], s->d_params + size_t(l) * kLayerStride + kHidden * kHidden, w.H[l + 1],
-                     train ? w.HT[l + 1] : nullptr, Np, Np, st);
-    }
-    sg_out_fwd(w.H[kLayers], s->d_params + kOutOffset, s->d_params + kOutOffset + kHidden, Np, w.y, st);
+    sg_forward_train(pts, n, Np, s->d_B, s->d_W, s->d_params, w.H, w.HT, w.Z, w.y, st);
 }
 
 // Host copies of the intermediate tensors of one training step (see
@@ -211,15 +207,8 @@ void backward(env_surrogate* s, const float* t, int64_t n, int64_t Np, void* st,
 // n points, in chunks.
 env_status predict(env_surrogate* s, const double* pts, int64_t n, double* out, void* st,
                    const double* add = nullptr) {
-    const int64_t chunk = 65536;
-    if (!ws_ensure(s->ws, std::min(round32(n), chunk), s->ws.train)) return ENV_E_NOMEM;
-    for (int64_t o = 0; o < n; o += chunk) {
-        const int64_t m = std::min(chunk, n - o);
-        const int64_t Np = round32(m);
-        forward(s, pts + 3 * o, m, Np, false, st);
-        sg_finish(pts + 3 * o, s->ws.y, m, s->d_coef, s->d_mono, int(s->mono.size() / 3), 1.0 / s->radius,
-                  s->sigma, add ? add + o : nullptr, out + o, st);
-    }
+    sg_infer(pts, n, s->d_B, s->d_W, s->d_params, s->d_coef, s->d_mono, int(s->mono.size() / 3), 1.0 / s->radius,
+             s->sigma, add, out, st);
     return sg_last_error() == 0 ? ENV_OK : ENV_E_DEVICE;
 }
 
@@ -289,6 +278,7 @@ void destroy(env_surrogate* s) {
     (void)hipFree(s->d_pass);
     (void)hipFree(s->d_nfb);
     (void)hipFree(s->d_counter);
+    (void)hipFree(s->d_tstate);
     delete s;
 }
 
@@ -335,7 +325,7 @@ env_status env_surrogate_create(env_potential* fallback, const env_surrogate_spe
               dalloc(&s->d_m, kNParams) && dalloc(&s->d_v, kNParams) &&
               dalloc(&s->d_W, size_t(kLayers) * kHidden * kHidden) &&
               dalloc(&s->d_WT, size_t(kLayers) * kHidden * kHidden) && dalloc(&s->d_nfb, 1) &&
-              dalloc(&s->d_counter, 1);
+              dalloc(&s->d_counter, 1) && dalloc(&s->d_tstate, 1);
     if (!ok) {
         destroy(s);
         return ENV_E_NOMEM;
@@ -385,7 +375,7 @@ env_status env_surrogate_loss_grad(env_surrogate* s, const double* points, const
     const int64_t Np = round32(n);
     if (!ws_ensure(s->ws, Np, true)) return ENV_E_NOMEM;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    forward(s, points, n, Np, true, stream);
+    forward(s, points, n, Np, stream);
     backward(s, targets, n, Np, stream);
     if (sg_last_error() != 0) return ENV_E_DEVICE;
     std::vector<double> lp((Np + 255) / 256);
@@ -414,7 +404,7 @@ env_status env_surrogate_trace_step(env_surrogate* s, const double* points, cons
     tc.n = n;
     std::vector<uint16_t> hb(tr->H ? size_t(kLayers + 1) * n * kHidden : 0);
     if (tr->dZ) tc.dzb.assign(size_t(kLayers) * n * kHidden, 0);
-    forward(s, points, n, Np, true, stream);
+    forward(s, points, n, Np, stream);
     for (int l = 0; l <= kLayers && tr->H; ++l)
         tc.copy(hb.data() + size_t(l) * n * kHidden, w.H[l], size_t(n) * kHidden * sizeof(uint16_t), st);
     for (int l = 0; l < kLayers && tr->Z; ++l)
@@ -520,39 +510,65 @@ env_status env_surrogate_train(env_surrogate* s, env_potential* teacher, const e
     }
     sg_residual(d_pts, d_V, n, s->d_coef, s->d_mono, int(s->mono.size() / 3), 1.0 / s->radius, 1.0 / s->sigma,
                 d_t, stream);
-    // 3. Adam on minibatches, cosine learning-rate decay
+    // 3. Adam on minibatches, cosine learning-rate decay.  One step (gather,
+    // forward, backward, Adam, BF16 pack, step counter) is captured once as
+    // a graph on a stream of the library's own and replayed for every step;
+    // the step number, minibatch offset and learning rate live on the device.
     const int64_t steps_per_epoch = n / o.batch;
     const int64_t total = steps_per_epoch * o.epochs;
     std::mt19937_64 gen(o.seed ^ 0x5DEECE66Dull);
     std::vector<int32_t> perm(n);
     double last_loss = 0.0;
+    hipStream_t ts = nullptr;
+    hipGraphExec_t step_exec = nullptr;
+    const TrainState tstate0 = {s->step, s->step};
+    if (hipStreamSynchronize(st) != hipSuccess || hipStreamCreateWithFlags(&ts, hipStreamNonBlocking) != hipSuccess ||
+        hipMemcpy(s->d_tstate, &tstate0, sizeof(TrainState), hipMemcpyHostToDevice) != hipSuccess)
+        rc = ENV_E_DEVICE;
+    auto one_step = [&](void* sp) {
+        sg_gather(d_pts, d_t, d_perm, s->d_tstate, steps_per_epoch, o.batch, d_pb, d_tb, sp);
+        forward(s, d_pb, o.batch, o.batch, sp);
+        backward(s, d_tb, o.batch, o.batch, sp);
+        sg_adam(s->d_params, s->d_grad, s->d_m, s->d_v, kNParams, s->d_tstate, o.lr, o.lr_final, total, 0.9f, 0.999f,
+                1e-8f, sp);
+        sg_pack(s->d_params, s->d_W, s->d_WT, sp);
+        sg_advance(s->d_tstate, sp);
+    };
+    const char* ng = std::getenv("ENVPOT_NO_GRAPH");   // plain launches (profilers, debugging)
+    const bool use_graph = !(ng && *ng && *ng != '0');
+    if (rc == ENV_OK && use_graph) {
+        hipGraph_t graph = nullptr;
+        if (hipStreamBeginCapture(ts, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            rc = ENV_E_DEVICE;
+        } else {
+            one_step(ts);
+            const hipError_t e = hipStreamEndCapture(ts, &graph);
+            if (e != hipSuccess || !graph || sg_last_error() != 0 ||
+                hipGraphInstantiate(&step_exec, graph, nullptr, nullptr, 0) != hipSuccess)
+                rc = ENV_E_DEVICE;
+            if (graph) (void)hipGraphDestroy(graph);
+        }
+    }
     for (int ep = 0; ep < o.epochs && rc == ENV_OK; ++ep) {
         for (int64_t i = 0; i < n; ++i) perm[i] = int32_t(i);
         std::shuffle(perm.begin(), perm.end(), gen);
-        if (hipMemcpyAsync(d_perm, perm.data(), size_t(n) * sizeof(int32_t), hipMemcpyHostToDevice, st) !=
+        if (hipMemcpyAsync(d_perm, perm.data(), size_t(n) * sizeof(int32_t), hipMemcpyHostToDevice, ts) !=
             hipSuccess) {
             rc = ENV_E_DEVICE;
             break;
         }
-        for (int64_t k = 0; k < steps_per_epoch; ++k) {
-            sg_gather(d_pts, d_t, d_perm, k * o.batch, o.batch, d_pb, d_tb, stream);
-            forward(s, d_pb, o.batch, o.batch, true, stream);
-            backward(s, d_tb, o.batch, o.batch, stream);
-            ++s->step;
-            const double frac = double(s->step) / double(std::max<int64_t>(total, 1));
-            const double lr = o.lr_final + 0.5 * (o.lr - o.lr_final) * (1.0 + std::cos(M_PI * std::min(1.0, frac)));
-            const float bc1 = float(1.0 - std::pow(0.9, double(s->step)));
-            const float bc2 = float(1.0 - std::pow(0.999, double(s->step)));
-            sg_adam(s->d_params, s->d_grad, s->d_m, s->d_v, kNParams, float(lr), 0.9f, 0.999f, 1e-8f, bc1, bc2,
-                    stream);
-            sg_pack(s->d_params, s->d_W, s->d_WT, stream);
+        for (int64_t k = 0; k < steps_per_epoch && rc == ENV_OK; ++k) {
+            if (!use_graph) one_step(ts);
+            else if (hipGraphLaunch(step_exec, ts) != hipSuccess) rc = ENV_E_DEVICE;
         }
-        // loss of the last minibatch of the epoch
+        s->step += steps_per_epoch;
+        // loss of the last minibatch of the epoch (also keeps the host
+        // permutation from being refilled while its copy may be pending)
         std::vector<double> lp((o.batch + 255) / 256);
-        if (sg_last_error() != 0 ||
-            hipMemcpyAsync(lp.data(), s->ws.losspart, lp.size() * sizeof(double), hipMemcpyDeviceToHost, st) !=
+        if (rc != ENV_OK ||
+            hipMemcpyAsync(lp.data(), s->ws.losspart, lp.size() * sizeof(double), hipMemcpyDeviceToHost, ts) !=
                 hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess) {
+            hipStreamSynchronize(ts) != hipSuccess) {
             rc = ENV_E_DEVICE;
             break;
         }
@@ -561,6 +577,9 @@ env_status env_surrogate_train(env_surrogate* s, env_potential* teacher, const e
         last_loss /= double(o.batch);
         if (ep < int(sizeof(s->info.epoch_loss) / sizeof(double))) s->info.epoch_loss[ep] = last_loss;
     }
+    if (ts) (void)hipStreamSynchronize(ts);
+    if (step_exec) (void)hipGraphExecDestroy(step_exec);
+    if (ts) (void)hipStreamDestroy(ts);
     const auto t2 = std::chrono::steady_clock::now();
     // 4. gate: m validation points per voxel of a G^3 grid over the ball
     if (rc == ENV_OK) {

@@ -5,10 +5,12 @@
 // Linear 128 -> 1 in FP32; V_hat = poly(r/R) + sigma * y.  Training: MSE,
 // straight-through BF16 rounding, Adam on FP32 master weights.
 //
-// All matrix products are one NT kernel: C[M x N] = A[M x K] * Bt[N x K]^T with
-// BF16 row-major operands (K contiguous) and v_mfma_f32_32x32x16_bf16; each
-// wave owns a 32 x 32 tile of C and gridDim.z splits K (partials summed in
-// fixed order by k_reduce_rows).  Operand layout of the instruction (verified
+// The forward pass (features, the four layers, the output) is one kernel,
+// k_mlp, that keeps a workgroup's 128 rows in LDS; the backward products use
+// one NT kernel: C[M x N] = A[M x K] * Bt[N x K]^T with BF16 row-major
+// operands (K contiguous), each wave owning a 32 x 32 tile of C, gridDim.z
+// splitting K (partials summed in fixed order by k_reduce_rows).  Both use
+// v_mfma_f32_32x32x16_bf16.  Operand layout of the instruction (verified
 // on the device): lane l, g = l / 32, r = l % 32 holds A[r][g*8 .. g*8+7] and
 // Bt[r][g*8 .. g*8+7]; result register i holds C[(i/4)*8 + g*4 + i%4][r].
 #include <hip/hip_runtime.h>
@@ -70,57 +72,26 @@ __global__ __launch_bounds__(256) void k_reduce_rows(const float* __restrict__ p
     out[j] = (float)s;
 }
 
-// Fourier features of rows < n (zeros in the padding rows), BF16, row-major
-// [Np x 2F] and optionally transposed [2F x ldT].
-__global__ __launch_bounds__(256) void k_features(const double* __restrict__ pts, int64_t n,
-                                                  int64_t Np, const double* __restrict__ B, int F,
-                                                  uint16_t* __restrict__ H, uint16_t* __restrict__ HT,
-                                                  int64_t ldT) {
-    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= Np * F) return;
-    const int64_t row = idx / F;
-    const int k = (int)(idx % F);
-    uint16_t c = 0, s = 0;
-    if (row < n) {
-        const double ph = kTwoPi * (B[3 * k] * pts[3 * row] + B[3 * k + 1] * pts[3 * row + 1] +
-                                    B[3 * k + 2] * pts[3 * row + 2]);
-        double sv, cv;
-        sincos(ph, &sv, &cv);
-        c = to_bf16((float)cv);
-        s = to_bf16((float)sv);
-    }
-    H[row * (2 * F) + k] = c;
-    H[row * (2 * F) + F + k] = s;
-    if (HT) {
-        HT[(int64_t)k * ldT + row] = c;
-        HT[(int64_t)(F + k) * ldT + row] = s;
-    }
+// Phase 2 pi b_k . r of one Fourier feature (FP64).
+__device__ __forceinline__ double feature_phase(const double* __restrict__ B, int k, double x, double y, double z) {
+    return kTwoPi * (B[3 * k] * x + B[3 * k + 1] * y + B[3 * k + 2] * z);
 }
 
-// Z += bias (kept for the backward pass); H = bf16(silu(Z)), optional H^T.
-__global__ __launch_bounds__(256) void k_bias_silu(float* __restrict__ Z, const float* __restrict__ bias,
-                                                   uint16_t* __restrict__ H, uint16_t* __restrict__ HT,
-                                                   int64_t Np, int64_t ldT) {
-    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= Np * kHidden) return;
-    const int64_t row = idx / kHidden;
-    const int col = (int)(idx % kHidden);
-    const float z = Z[idx] + bias[col];
-    Z[idx] = z;
-    const uint16_t h = to_bf16(silu(z));
-    H[idx] = h;
-    if (HT) HT[(int64_t)col * ldT + row] = h;
-}
-
-// y = H . w_out + b_out (FP32, fixed order).
-__global__ __launch_bounds__(256) void k_out_fwd(const uint16_t* __restrict__ H, const float* __restrict__ w,
-                                                 const float* __restrict__ b, int64_t Np, float* __restrict__ y) {
-    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (row >= Np) return;
-    float s = 0.0f;
-    const uint16_t* h = H + row * kHidden;
-    for (int j = 0; j < kHidden; ++j) s = __builtin_fmaf(__uint_as_float((uint32_t)h[j] << 16), w[j], s);
-    y[row] = s + b[0];
+// poly(r/R) + sigma * y (FP64) at one point.
+__device__ __forceinline__ double finish_value(double x, double y, double z, float net,
+                                               const double* __restrict__ coef, const int8_t* __restrict__ mono,
+                                               int nmono, double inv_r, double sigma) {
+    double px[kMaxPolyDegree + 1], py[kMaxPolyDegree + 1], pz[kMaxPolyDegree + 1];
+    const double ux = x * inv_r, uy = y * inv_r, uz = z * inv_r;
+    px[0] = py[0] = pz[0] = 1.0;
+    for (int d = 1; d <= kMaxPolyDegree; ++d) {
+        px[d] = px[d - 1] * ux;
+        py[d] = py[d - 1] * uy;
+        pz[d] = pz[d - 1] * uz;
+    }
+    double v = 0.0;
+    for (int k = 0; k < nmono; ++k) v += coef[k] * px[mono[3 * k]] * py[mono[3 * k + 1]] * pz[mono[3 * k + 2]];
+    return v + sigma * (double)net;
 }
 
 // dy = 2 (y - t)/n on rows < n, 0 on padding; per-block partials of
@@ -191,17 +162,32 @@ __global__ __launch_bounds__(128) void k_dsilu(const float* __restrict__ dH, con
     if (!dH) colsum_out[(int64_t)blockIdx.x * kHidden + col] = co;
 }
 
+// Adam on the FP32 master weights.  The step number comes from the device
+// training state (so one captured step graph serves every step): step =
+// st->step + 1, learning rate by cosine decay from lr0 to lr1 over `total`
+// steps, bias corrections 1 - b^step.
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
                                               float* __restrict__ m, float* __restrict__ v, int64_t n,
-                                              float lr, float b1, float b2, float eps, float bc1, float bc2) {
+                                              const TrainState* __restrict__ st, double lr0, double lr1,
+                                              int64_t total, float b1, float b2, float eps) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
+    const int64_t step = st->step + 1;
+    const double frac = fmin(1.0, (double)(step - st->step0) / (double)(total > 0 ? total : 1));
+    const float lr = (float)(lr1 + 0.5 * (lr0 - lr1) * (1.0 + cos(3.14159265358979323846 * frac)));
+    const float bc1 = (float)(1.0 - pow((double)b1, (double)step));
+    const float bc2 = (float)(1.0 - pow((double)b2, (double)step));
     const float gi = g[i];
     const float mi = b1 * m[i] + (1.0f - b1) * gi;
     const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
     m[i] = mi;
     v[i] = vi;
     p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// End of a training step: advance the device step counter.
+__global__ void k_advance(TrainState* st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) st->step += 1;
 }
 
 // BF16 copies of the four hidden weight matrices, as stored (out x in) and transposed.
@@ -217,27 +203,130 @@ __global__ __launch_bounds__(256) void k_pack(const float* __restrict__ params, 
     WT[(int64_t)l * kHidden * kHidden + i * kHidden + o] = b;
 }
 
-// V = poly(r/R) + sigma * y (FP64), plus add[i] when add is not null (the
-// exactly evaluated part of a split surrogate).
-__global__ __launch_bounds__(256) void k_finish(const double* __restrict__ pts, const float* __restrict__ y,
-                                                int64_t n, const double* __restrict__ coef,
-                                                const int8_t* __restrict__ mono, int nmono, double inv_r,
-                                                double sigma, const double* __restrict__ add,
-                                                double* __restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    double px[kMaxPolyDegree + 1], py[kMaxPolyDegree + 1], pz[kMaxPolyDegree + 1];
-    const double ux = pts[3 * i] * inv_r, uy = pts[3 * i + 1] * inv_r, uz = pts[3 * i + 2] * inv_r;
-    px[0] = py[0] = pz[0] = 1.0;
-    for (int d = 1; d <= kMaxPolyDegree; ++d) {
-        px[d] = px[d - 1] * ux;
-        py[d] = py[d - 1] * uy;
-        pz[d] = pz[d - 1] * uz;
+// The whole network in one kernel.  A workgroup takes 128 rows (four waves
+// of 32), computes their Fourier features into LDS, then per layer stages
+// the layer's BF16 weights in LDS and lets each wave multiply its own 32
+// rows by them on the matrix cores (the instruction sequence of k_gemm_nt:
+// four 32 x 32 output tiles, K = 128 in steps of 16), adds the bias, applies
+// SiLU and writes the BF16 activations back over its rows; then the FP32
+// output layer.  Inference (TRAIN false) finishes with the baseline and the
+// optional exact part; training (TRAIN true) also stores what the backward
+// pass reads: H_0..H_4 row-major and transposed, the pre-activations Z_l and
+// y, for the first Np rows.  Every step has the arithmetic of the unfused
+// kernels, so the values equal theirs.  LDS rows are padded to 136 elements
+// (bank spread of the 16-byte row reads).
+constexpr int kInferRows = 128;
+constexpr int kLdsLd = kHidden + 8;
+
+struct TrainStores {
+    uint16_t* H[kLayers + 1];
+    uint16_t* HT[kLayers + 1];
+    float* Z[kLayers];
+    float* y;
+    int64_t Np;     // rows stored (multiple of 32; rows >= n are padding with zero features)
+};
+
+template <bool TRAIN>
+__global__ __launch_bounds__(256) void k_mlp(const double* __restrict__ pts, int64_t n,
+                                             const double* __restrict__ B, const uint16_t* __restrict__ W,
+                                             const float* __restrict__ params, const double* __restrict__ coef,
+                                             const int8_t* __restrict__ mono, int nmono, double inv_r,
+                                             double sigma, const double* __restrict__ add,
+                                             double* __restrict__ out, TrainStores ts) {
+    __shared__ __attribute__((aligned(16))) uint16_t sW[kHidden * kLdsLd];
+    __shared__ __attribute__((aligned(16))) uint16_t sH[kInferRows * kLdsLd];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 5, r = lane & 31;
+    const int64_t row0 = (int64_t)blockIdx.x * kInferRows;
+    const int64_t nstore = TRAIN ? ts.Np : n;
+    {   // features: thread t -> row t % 128, frequencies 32 (t / 128) .. + 31
+        const int lr = tid & (kInferRows - 1);
+        const int k0 = (tid >> 7) * (kFreq / 2);
+        const int64_t row = row0 + lr;
+        double x = 0.0, y = 0.0, z = 0.0;
+        if (row < n) {
+            x = pts[3 * row];
+            y = pts[3 * row + 1];
+            z = pts[3 * row + 2];
+        }
+        for (int k = k0; k < k0 + kFreq / 2; ++k) {
+            uint16_t c = 0, sn = 0;
+            if (row < n) {
+                double sv, cv;
+                sincos(feature_phase(B, k, x, y, z), &sv, &cv);
+                c = to_bf16((float)cv);
+                sn = to_bf16((float)sv);
+            }
+            sH[lr * kLdsLd + k] = c;
+            sH[lr * kLdsLd + kFreq + k] = sn;
+            if (TRAIN && row < nstore) {
+                ts.H[0][row * kHidden + k] = c;
+                ts.H[0][row * kHidden + kFreq + k] = sn;
+                ts.HT[0][(int64_t)k * nstore + row] = c;
+                ts.HT[0][(int64_t)(kFreq + k) * nstore + row] = sn;
+            }
+        }
     }
-    double v = 0.0;
-    for (int k = 0; k < nmono; ++k) v += coef[k] * px[mono[3 * k]] * py[mono[3 * k + 1]] * pz[mono[3 * k + 2]];
-    v += sigma * (double)y[i];
-    out[i] = add ? v + add[i] : v;
+    for (int l = 0; l < kLayers; ++l) {
+        {   // stage W_l (out x in) with padded rows: 128 rows x 16 chunks of 8 values
+            const uint4* gW = reinterpret_cast<const uint4*>(W + (int64_t)l * kHidden * kHidden);
+            for (int q = tid; q < kHidden * kHidden / 8; q += 256) {
+                const int o = q >> 4, c = q & 15;
+                *reinterpret_cast<uint4*>(sW + o * kLdsLd + c * 8) = gW[q];
+            }
+        }
+        __syncthreads();  // W_l staged; the previous layer's activations written
+        f32x16 acc[4] = {};
+        const uint16_t* a = sH + (wave * 32 + r) * kLdsLd + g * 8;
+        for (int k = 0; k < kHidden; k += 16) {
+            const bf16x8 av = *reinterpret_cast<const bf16x8*>(a + k);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const bf16x8 bv = *reinterpret_cast<const bf16x8*>(sW + (t * 32 + r) * kLdsLd + g * 8 + k);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[t], 0, 0, 0);
+            }
+        }
+        // this wave's rows are read; its new activations go over them (the
+        // other waves read only their own rows)
+        const float* bias = params + (int64_t)l * kLayerStride + kHidden * kHidden;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int col = t * 32 + r;
+            const float bc = bias[col];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int lr = wave * 32 + (i >> 2) * 8 + g * 4 + (i & 3);
+                const float zv = acc[t][i] + bc;
+                const uint16_t h = to_bf16(silu(zv));
+                sH[lr * kLdsLd + col] = h;
+                if (TRAIN) {
+                    const int64_t row = row0 + lr;
+                    if (row < nstore) {
+                        ts.Z[l][row * kHidden + col] = zv;
+                        ts.H[l + 1][row * kHidden + col] = h;
+                        ts.HT[l + 1][(int64_t)col * nstore + row] = h;
+                    }
+                }
+            }
+        }
+        __syncthreads();  // every wave is done with W_l before it is replaced
+    }
+    if (tid < kInferRows) {
+        const int64_t row = row0 + tid;
+        if (row < nstore) {
+            const float* w = params + kOutOffset;
+            float s = 0.0f;
+            const uint16_t* h = sH + tid * kLdsLd;
+            for (int j = 0; j < kHidden; ++j) s = __builtin_fmaf(__uint_as_float((uint32_t)h[j] << 16), w[j], s);
+            const float yv = s + w[kHidden];
+            if (TRAIN) {
+                ts.y[row] = yv;
+            } else {
+                const double v = finish_value(pts[3 * row], pts[3 * row + 1], pts[3 * row + 2], yv, coef, mono,
+                                              nmono, inv_r, sigma);
+                out[row] = add ? v + add[row] : v;
+            }
+        }
+    }
 }
 
 // Residual targets t = (V - poly(r/R)) / sigma.
@@ -311,11 +400,15 @@ __global__ __launch_bounds__(256) void k_sample_voxels(uint64_t seed, int G, int
     pts[3 * i + 2] = z;
 }
 
+// Minibatch of a training step: rows ((step - step0) mod steps_per_epoch)
+// * bs .. + bs of the epoch's permutation.
 __global__ __launch_bounds__(256) void k_gather(const double* __restrict__ pts, const float* __restrict__ t,
-                                                const int32_t* __restrict__ perm, int64_t start, int64_t bs,
-                                                double* __restrict__ pb, float* __restrict__ tb) {
+                                                const int32_t* __restrict__ perm, const TrainState* __restrict__ st,
+                                                int64_t steps_per_epoch, int64_t bs, double* __restrict__ pb,
+                                                float* __restrict__ tb) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= bs) return;
+    const int64_t start = ((st->step - st->step0) % steps_per_epoch) * bs;
     const int64_t j = perm[start + i];
     pb[3 * i] = pts[3 * j];
     pb[3 * i + 1] = pts[3 * j + 1];
@@ -441,19 +534,6 @@ void sg_reduce_rows(const float* part, int P, int64_t L, float* out, void* st) {
     SG_LAUNCH(k_reduce_rows, dim3(blocks(L)), dim3(256), st, part, P, L, out);
 }
 
-void sg_features(const double* pts, int64_t n, int64_t Np, const double* B, int F, uint16_t* H,
-                 uint16_t* HT, int64_t ldT, void* st) {
-    SG_LAUNCH(k_features, dim3(blocks(Np * F)), dim3(256), st, pts, n, Np, B, F, H, HT, ldT);
-}
-
-void sg_bias_silu(float* Z, const float* bias, uint16_t* H, uint16_t* HT, int64_t Np, int64_t ldT, void* st) {
-    SG_LAUNCH(k_bias_silu, dim3(blocks(Np * kHidden)), dim3(256), st, Z, bias, H, HT, Np, ldT);
-}
-
-void sg_out_fwd(const uint16_t* H, const float* w, const float* b, int64_t Np, float* y, void* st) {
-    SG_LAUNCH(k_out_fwd, dim3(blocks(Np)), dim3(256), st, H, w, b, Np, y);
-}
-
 void sg_loss(const float* y, const float* t, int64_t n, int64_t Np, float* dy, double* part, float* part_dy,
              void* st) {
     SG_LAUNCH(k_loss, dim3(blocks(Np)), dim3(256), st, y, t, n, Np, dy, part, part_dy);
@@ -466,18 +546,40 @@ void sg_dsilu(const float* dH, const float* dy, const float* w_out, const float*
               dZT, ldT, colsum, colsum_out);
 }
 
-void sg_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
-             float bc1, float bc2, void* st) {
-    SG_LAUNCH(k_adam, dim3(blocks(n)), dim3(256), st, p, g, m, v, n, lr, b1, b2, eps, bc1, bc2);
+void sg_adam(float* p, const float* g, float* m, float* v, int64_t n, const TrainState* ts, double lr0,
+             double lr1, int64_t total, float b1, float b2, float eps, void* st) {
+    SG_LAUNCH(k_adam, dim3(blocks(n)), dim3(256), st, p, g, m, v, n, ts, lr0, lr1, total, b1, b2, eps);
 }
+
+void sg_advance(TrainState* ts, void* st) { SG_LAUNCH(k_advance, dim3(1), dim3(64), st, ts); }
 
 void sg_pack(const float* params, uint16_t* W, uint16_t* WT, void* st) {
     SG_LAUNCH(k_pack, dim3(blocks((int64_t)kLayers * kHidden * kHidden)), dim3(256), st, params, W, WT);
 }
 
-void sg_finish(const double* pts, const float* y, int64_t n, const double* coef, const int8_t* mono, int nmono,
-               double inv_r, double sigma, const double* add, double* out, void* st) {
-    SG_LAUNCH(k_finish, dim3(blocks(n)), dim3(256), st, pts, y, n, coef, mono, nmono, inv_r, sigma, add, out);
+void sg_infer(const double* pts, int64_t n, const double* B, const uint16_t* W, const float* params,
+              const double* coef, const int8_t* mono, int nmono, double inv_r, double sigma, const double* add,
+              double* out, void* st) {
+    if (n <= 0) return;
+    TrainStores none = {};
+    SG_LAUNCH(k_mlp<false>, dim3(blocks(n, kInferRows)), dim3(256), st, pts, n, B, W, params, coef, mono, nmono,
+              inv_r, sigma, add, out, none);
+}
+
+void sg_forward_train(const double* pts, int64_t n, int64_t Np, const double* B, const uint16_t* W,
+                      const float* params, uint16_t* const* H, uint16_t* const* HT, float* const* Z, float* y,
+                      void* st) {
+    if (Np <= 0) return;
+    TrainStores ts;
+    for (int l = 0; l <= kLayers; ++l) {
+        ts.H[l] = H[l];
+        ts.HT[l] = HT[l];
+    }
+    for (int l = 0; l < kLayers; ++l) ts.Z[l] = Z[l];
+    ts.y = y;
+    ts.Np = Np;
+    SG_LAUNCH(k_mlp<true>, dim3(blocks(Np, kInferRows)), dim3(256), st, pts, n, B, W, params, nullptr, nullptr, 0,
+              0.0, 0.0, nullptr, nullptr, ts);
 }
 
 void sg_residual(const double* pts, const double* V, int64_t n, const double* coef, const int8_t* mono,
@@ -493,9 +595,9 @@ void sg_sample_voxels(uint64_t seed, int G, int m, double R, double* pts, void* 
     SG_LAUNCH(k_sample_voxels, dim3(blocks((int64_t)G * G * G * m)), dim3(256), st, seed, G, m, R, pts);
 }
 
-void sg_gather(const double* pts, const float* t, const int32_t* perm, int64_t start, int64_t bs, double* pb,
-               float* tb, void* st) {
-    SG_LAUNCH(k_gather, dim3(blocks(bs)), dim3(256), st, pts, t, perm, start, bs, pb, tb);
+void sg_gather(const double* pts, const float* t, const int32_t* perm, const TrainState* ts,
+               int64_t steps_per_epoch, int64_t bs, double* pb, float* tb, void* st) {
+    SG_LAUNCH(k_gather, dim3(blocks(bs)), dim3(256), st, pts, t, perm, ts, steps_per_epoch, bs, pb, tb);
 }
 
 int sg_gate_flags(const double* pts, int64_t n, const uint8_t* pass, int G, double R, uint8_t* flag,

@@ -18,26 +18,41 @@ constexpr int kMaxPolyDegree = 8;
 int sg_gemm_nt(const uint16_t* A, int lda, const uint16_t* Bt, int ldb, float* C, int ldc, int M, int N,
                int K, int ksplit, void* st);
 void sg_reduce_rows(const float* part, int P, int64_t L, float* out, void* st);
-void sg_features(const double* pts, int64_t n, int64_t Np, const double* B, int F, uint16_t* H,
-                 uint16_t* HT, int64_t ldT, void* st);
-void sg_bias_silu(float* Z, const float* bias, uint16_t* H, uint16_t* HT, int64_t Np, int64_t ldT, void* st);
-void sg_out_fwd(const uint16_t* H, const float* w, const float* b, int64_t Np, float* y, void* st);
 void sg_loss(const float* y, const float* t, int64_t n, int64_t Np, float* dy, double* part, float* part_dy,
              void* st);
 void sg_dsilu(const float* dH, const float* dy, const float* w_out, const float* Z, const uint16_t* Htop,
               int64_t Np, uint16_t* dZb, uint16_t* dZT, int64_t ldT, float* colsum, float* colsum_out,
               void* st);
-void sg_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
-             float bc1, float bc2, void* st);
+// Device state of a training run: Adam step count so far and its value at
+// the start of the run (the minibatch index and the learning-rate schedule
+// are derived from them on the device, so one captured step graph is
+// replayed for every step).
+struct TrainState {
+    int64_t step;
+    int64_t step0;
+};
+
+void sg_adam(float* p, const float* g, float* m, float* v, int64_t n, const TrainState* ts, double lr0,
+             double lr1, int64_t total, float b1, float b2, float eps, void* st);
+void sg_advance(TrainState* ts, void* st);
 void sg_pack(const float* params, uint16_t* W, uint16_t* WT, void* st);
-void sg_finish(const double* pts, const float* y, int64_t n, const double* coef, const int8_t* mono, int nmono,
-               double inv_r, double sigma, const double* add, double* out, void* st);
+// The whole network at inference (features, four layers, output, baseline,
+// optional exact part) in one launch: out[i] = poly + sigma y (+ add[i]).
+void sg_infer(const double* pts, int64_t n, const double* B, const uint16_t* W, const float* params,
+              const double* coef, const int8_t* mono, int nmono, double inv_r, double sigma, const double* add,
+              double* out, void* st);
+// The forward pass of a training step in one launch: H_0..H_4 (row-major
+// [Np x 128] and transposed [128 x Np], BF16), Z_0..Z_3 (FP32) and y for the
+// first Np rows (rows >= n have zero features).
+void sg_forward_train(const double* pts, int64_t n, int64_t Np, const double* B, const uint16_t* W,
+                      const float* params, uint16_t* const* H, uint16_t* const* HT, float* const* Z, float* y,
+                      void* st);
 void sg_residual(const double* pts, const double* V, int64_t n, const double* coef, const int8_t* mono,
                  int nmono, double inv_r, double inv_sigma, float* t, void* st);
 void sg_sample_ball(uint64_t seed, int64_t n, double R, double* pts, void* st);
 void sg_sample_voxels(uint64_t seed, int G, int m, double R, double* pts, void* st);
-void sg_gather(const double* pts, const float* t, const int32_t* perm, int64_t start, int64_t bs, double* pb,
-               float* tb, void* st);
+void sg_gather(const double* pts, const float* t, const int32_t* perm, const TrainState* ts,
+               int64_t steps_per_epoch, int64_t bs, double* pb, float* tb, void* st);
 int sg_gate_flags(const double* pts, int64_t n, const uint8_t* pass, int G, double R, uint8_t* flag,
                   int32_t* counts, void* st);
 void sg_scan_counts(const int32_t* counts, int nb, int64_t* offsets, int64_t* total, void* st);
