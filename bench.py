@@ -189,8 +189,8 @@ def large_surrogate(args, torch, envpot, synth, env, pts, x, fb, info, gold, V64
     S = envpot.Surrogate(fb, envpot.fourier_matrix(1005, args.sigma), envpot.init_params(1005), radius=8.0)
     S.set_near(E_near)
     t0 = time.perf_counter()
-    S.train(T_far, n_train=2_000_000, epochs=args.sur_epochs, batch=8192, lr=2e-3, lr_final=1e-5, poly_degree=8,
-            gate_grid=24, gate_samples=32, gate_tol=4e-6)
+    S.train(T_far, n_train=2_000_000, epochs=args.sur_epochs, batch=8192, lr=args.sur_lr, lr_final=1e-5,
+            poly_degree=8, gate_grid=24, gate_samples=32, gate_tol=4e-6)
     t_train = time.perf_counter() - t0
     si = S.info()
     out = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -473,7 +473,8 @@ def surrogate1000_leg(args, torch, envpot, synth):
     npairs = fb.info()["n_pairs"]
     S = envpot.Surrogate(fb, envpot.fourier_matrix(1004, 0.25), envpot.init_params(1004), radius=6.0)
     t0 = time.perf_counter()
-    S.train(te, n_train=2_000_000, epochs=30, batch=8192, lr=2e-3, lr_final=1e-5, poly_degree=8)
+    S.train(te, n_train=args.sur1000_train, epochs=args.sur1000_epochs, batch=8192, lr=2e-3, lr_final=1e-5,
+            poly_degree=8)
     t_train = time.perf_counter() - t0
     si = S.info()
     out = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -543,8 +544,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--sigma", type=float, default=0.25,
                     help="Fourier-feature frequency scale of the large surrogate (1/bohr)")
-    ap.add_argument("--sur-epochs", type=int, default=60, help="large surrogate: training epochs over 2M samples")
-    ap.add_argument("--r-near", type=float, default=16.0,
+    ap.add_argument("--sur-epochs", type=int, default=120, help="large surrogate: training epochs over 2M samples")
+    ap.add_argument("--sur-lr", type=float, default=3e-3, help="large surrogate: initial Adam learning rate")
+    ap.add_argument("--sur1000-train", type=int, default=2_000_000,
+                    help="1000-atom surrogate leg: training samples (profiling runs may shrink it)")
+    ap.add_argument("--sur1000-epochs", type=int, default=30, help="1000-atom surrogate leg: training epochs")
+    ap.add_argument("--r-near", type=float, default=15.0,
                     help="large surrogate: fragments with an atom within this radius (bohr) are evaluated "
                          "exactly and added; the network covers the rest")
     ap.add_argument("--cpu-sample", type=int, default=64,

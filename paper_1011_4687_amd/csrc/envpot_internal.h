@@ -12,7 +12,7 @@ namespace envpot {
 
 constexpr int kLMax = 4;                  // largest L = l_I + l_J (d-d pairs)
 constexpr int kNComp[kLMax + 1] = {1, 4, 10, 20, 35};
-constexpr int kMaxSplitLog2 = 6;          // split-pair factors 1, 2, 4, ..., 64
+constexpr int kMaxSplitLog2 = 8;          // split-pair factors 1, 2, 4, ..., 256
 constexpr int kBlock = 256;               // threads per workgroup of the point kernels
 
 // Boys tables: grid T_k = k / 8, k = 0..rows-1.

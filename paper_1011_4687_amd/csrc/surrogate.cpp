@@ -517,10 +517,34 @@ env_status env_surrogate_train(env_surrogate* s, env_potential* teacher, const e
     const int64_t steps_per_epoch = n / o.batch;
     const int64_t total = steps_per_epoch * o.epochs;
     std::mt19937_64 gen(o.seed ^ 0x5DEECE66Dull);
-    std::vector<int32_t> perm(n);
     double last_loss = 0.0;
     hipStream_t ts = nullptr;
     hipGraphExec_t step_exec = nullptr;
+    // two pinned host permutations: the next epoch's is shuffled on the host
+    // while the device runs the current one; the last minibatch's loss
+    // partials of every epoch are kept on the device and read at the end
+    const int64_t nlp = (o.batch + 255) / 256;
+    int32_t* hperm[2] = {nullptr, nullptr};
+    hipEvent_t copied[2] = {nullptr, nullptr};
+    double* d_losshist = nullptr;
+    auto release = [&]() {
+        for (int b = 0; b < 2; ++b) {
+            if (hperm[b]) (void)hipHostFree(hperm[b]);
+            if (copied[b]) (void)hipEventDestroy(copied[b]);
+        }
+        (void)hipFree(d_losshist);
+    };
+    for (int b = 0; b < 2 && rc == ENV_OK; ++b)
+        if (hipHostMalloc(reinterpret_cast<void**>(&hperm[b]), size_t(n) * sizeof(int32_t), hipHostMallocDefault) !=
+                hipSuccess ||
+            hipEventCreateWithFlags(&copied[b], hipEventDisableTiming) != hipSuccess)
+            rc = ENV_E_NOMEM;
+    if (rc == ENV_OK && !dalloc(&d_losshist, size_t(nlp) * o.epochs)) rc = ENV_E_NOMEM;
+    auto shuffle_into = [&](int32_t* pv) {
+        for (int64_t i = 0; i < n; ++i) pv[i] = int32_t(i);
+        std::shuffle(pv, pv + n, gen);
+    };
+    if (rc == ENV_OK) shuffle_into(hperm[0]);
     const TrainState tstate0 = {s->step, s->step};
     if (hipStreamSynchronize(st) != hipSuccess || hipStreamCreateWithFlags(&ts, hipStreamNonBlocking) != hipSuccess ||
         hipMemcpy(s->d_tstate, &tstate0, sizeof(TrainState), hipMemcpyHostToDevice) != hipSuccess)
@@ -550,10 +574,12 @@ env_status env_surrogate_train(env_surrogate* s, env_potential* teacher, const e
         }
     }
     for (int ep = 0; ep < o.epochs && rc == ENV_OK; ++ep) {
-        for (int64_t i = 0; i < n; ++i) perm[i] = int32_t(i);
-        std::shuffle(perm.begin(), perm.end(), gen);
-        if (hipMemcpyAsync(d_perm, perm.data(), size_t(n) * sizeof(int32_t), hipMemcpyHostToDevice, ts) !=
-            hipSuccess) {
+        const int b = ep & 1;
+        // the epoch's permutation goes to the device after the previous
+        // epoch's steps (stream order), from pinned memory
+        if (hipMemcpyAsync(d_perm, hperm[b], size_t(n) * sizeof(int32_t), hipMemcpyHostToDevice, ts) !=
+                hipSuccess ||
+            hipEventRecord(copied[b], ts) != hipSuccess) {
             rc = ENV_E_DEVICE;
             break;
         }
@@ -562,24 +588,35 @@ env_status env_surrogate_train(env_surrogate* s, env_potential* teacher, const e
             else if (hipGraphLaunch(step_exec, ts) != hipSuccess) rc = ENV_E_DEVICE;
         }
         s->step += steps_per_epoch;
-        // loss of the last minibatch of the epoch (also keeps the host
-        // permutation from being refilled while its copy may be pending)
-        std::vector<double> lp((o.batch + 255) / 256);
-        if (rc != ENV_OK ||
-            hipMemcpyAsync(lp.data(), s->ws.losspart, lp.size() * sizeof(double), hipMemcpyDeviceToHost, ts) !=
+        if (rc == ENV_OK && hipMemcpyAsync(d_losshist + size_t(ep) * nlp, s->ws.losspart, size_t(nlp) * sizeof(double),
+                                           hipMemcpyDeviceToDevice, ts) != hipSuccess)
+            rc = ENV_E_DEVICE;
+        // next epoch's permutation, on the host while the device works; its
+        // buffer's last copy (two epochs ago) must have finished
+        if (rc == ENV_OK && ep + 1 < o.epochs) {
+            if (hipEventSynchronize(copied[b ^ 1]) != hipSuccess) rc = ENV_E_DEVICE;
+            else shuffle_into(hperm[b ^ 1]);
+        }
+    }
+    if (rc == ENV_OK) {
+        std::vector<double> lh(size_t(nlp) * o.epochs);
+        if (hipMemcpyAsync(lh.data(), d_losshist, lh.size() * sizeof(double), hipMemcpyDeviceToHost, ts) !=
                 hipSuccess ||
             hipStreamSynchronize(ts) != hipSuccess) {
             rc = ENV_E_DEVICE;
-            break;
+        } else {
+            for (int ep = 0; ep < o.epochs; ++ep) {
+                double l = 0.0;
+                for (int64_t q = 0; q < nlp; ++q) l += lh[size_t(ep) * nlp + q];
+                last_loss = l / double(o.batch);
+                if (ep < int(sizeof(s->info.epoch_loss) / sizeof(double))) s->info.epoch_loss[ep] = last_loss;
+            }
         }
-        last_loss = 0.0;
-        for (double v : lp) last_loss += v;
-        last_loss /= double(o.batch);
-        if (ep < int(sizeof(s->info.epoch_loss) / sizeof(double))) s->info.epoch_loss[ep] = last_loss;
     }
     if (ts) (void)hipStreamSynchronize(ts);
     if (step_exec) (void)hipGraphExecDestroy(step_exec);
     if (ts) (void)hipStreamDestroy(ts);
+    release();
     const auto t2 = std::chrono::steady_clock::now();
     // 4. gate: m validation points per voxel of a G^3 grid over the ball
     if (rc == ENV_OK) {

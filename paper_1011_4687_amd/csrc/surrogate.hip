@@ -62,40 +62,23 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A,
     for (int i = 0; i < 16; ++i) c[(int64_t)(tm + (i >> 2) * 8 + g * 4 + (i & 3)) * ldc + tn + r] = acc[i];
 }
 
-// out[j] = sum_{p < P} part[p * L + j], fixed order, FP64 accumulation.
+// out[j] = sum_{p < P} part[p * L + j] in FP64: four groups of consecutive
+// partials summed in order by four waves, then the group sums added in group
+// order (a fixed order, so the result is reproducible).  Block: 64 outputs.
 __global__ __launch_bounds__(256) void k_reduce_rows(const float* __restrict__ part, int P, int64_t L,
                                                      float* __restrict__ out) {
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= L) return;
+    __shared__ double sh[4][64];
+    const int jl = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int64_t j = (int64_t)blockIdx.x * 64 + jl;
+    const int chunk = (P + 3) / 4;
     double s = 0.0;
-    for (int p = 0; p < P; ++p) s += part[(int64_t)p * L + j];
-    out[j] = (float)s;
+    if (j < L)
+        for (int p = g * chunk; p < min(P, (g + 1) * chunk); ++p) s += part[(int64_t)p * L + j];
+    sh[g][jl] = s;
+    __syncthreads();
+    if (g == 0 && j < L) out[j] = (float)(((sh[0][jl] + sh[1][jl]) + sh[2][jl]) + sh[3][jl]);
 }
 
-// Phase 2 pi b_k . r of one Fourier feature (FP64).
-__device__ __forceinline__ double feature_phase(const double* __restrict__ B, int k, double x, double y, double z) {
-    return kTwoPi * (B[3 * k] * x + B[3 * k + 1] * y + B[3 * k + 2] * z);
-}
-
-// poly(r/R) + sigma * y (FP64) at one point.
-__device__ __forceinline__ double finish_value(double x, double y, double z, float net,
-                                               const double* __restrict__ coef, const int8_t* __restrict__ mono,
-                                               int nmono, double inv_r, double sigma) {
-    double px[kMaxPolyDegree + 1], py[kMaxPolyDegree + 1], pz[kMaxPolyDegree + 1];
-    const double ux = x * inv_r, uy = y * inv_r, uz = z * inv_r;
-    px[0] = py[0] = pz[0] = 1.0;
-    for (int d = 1; d <= kMaxPolyDegree; ++d) {
-        px[d] = px[d - 1] * ux;
-        py[d] = py[d - 1] * uy;
-        pz[d] = pz[d - 1] * uz;
-    }
-    double v = 0.0;
-    for (int k = 0; k < nmono; ++k) v += coef[k] * px[mono[3 * k]] * py[mono[3 * k + 1]] * pz[mono[3 * k + 2]];
-    return v + sigma * (double)net;
-}
-
-// dy = 2 (y - t)/n on rows < n, 0 on padding; per-block partials of
-// sum (y-t)^2 (FP64) and of sum dy (the output-bias gradient).
 __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ y, const float* __restrict__ t,
                                               int64_t n, int64_t Np, float* __restrict__ dy,
                                               double* __restrict__ part, float* __restrict__ part_dy) {
@@ -130,20 +113,25 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ y, const
 
 // Backward through SiLU for one layer.  dH = dy (x) w_out for the top layer
 // (dH == nullptr), else the given FP32 dH.  Writes bf16(dZ) [Np x 128] and
-// its transpose [128 x ldT], the per-block column sums of dZ (bias
-// gradient) and, for the top layer, the per-block column sums of dy * H
-// (output-weight gradient).  Block: 128 threads (one column), kRowsPerBlock rows.
-__global__ __launch_bounds__(128) void k_dsilu(const float* __restrict__ dH, const float* __restrict__ dy,
+// its transpose [128 x ldT] (staged through LDS, so both are written in
+// 16-byte rows), the per-block column sums of dZ (bias gradient) and, for the
+// top layer, the per-block column sums of dy * H (output-weight gradient).
+// Block: 256 threads over kRowsPerBlock = 64 rows (two halves of 32 rows per
+// column; Np is a multiple of 32).
+__global__ __launch_bounds__(256) void k_dsilu(const float* __restrict__ dH, const float* __restrict__ dy,
                                                const float* __restrict__ w_out, const float* __restrict__ Z,
                                                const uint16_t* __restrict__ Htop, int64_t Np,
                                                uint16_t* __restrict__ dZb, uint16_t* __restrict__ dZT,
                                                int64_t ldT, float* __restrict__ colsum,
                                                float* __restrict__ colsum_out) {
-    const int col = threadIdx.x;
+    __shared__ uint16_t tile[kRowsPerBlock][kHidden + 2];
+    __shared__ float csh[2][kHidden], cosh_[2][kHidden];
+    const int col = threadIdx.x & (kHidden - 1), half = threadIdx.x >> 7;
     const int64_t r0 = (int64_t)blockIdx.x * kRowsPerBlock;
-    const int64_t r1 = min(Np, r0 + kRowsPerBlock);
     float cs = 0.0f, co = 0.0f;
-    for (int64_t row = r0; row < r1; ++row) {
+    for (int rl = half * 32; rl < half * 32 + 32; ++rl) {
+        const int64_t row = r0 + rl;
+        if (row >= Np) break;
         const int64_t idx = row * kHidden + col;
         float g;
         if (dH) {
@@ -156,10 +144,28 @@ __global__ __launch_bounds__(128) void k_dsilu(const float* __restrict__ dH, con
         cs += dz;
         const uint16_t b = to_bf16(dz);
         dZb[idx] = b;
-        dZT[(int64_t)col * ldT + row] = b;
+        tile[rl][col] = b;
     }
-    colsum[(int64_t)blockIdx.x * kHidden + col] = cs;
-    if (!dH) colsum_out[(int64_t)blockIdx.x * kHidden + col] = co;
+    csh[half][col] = cs;
+    cosh_[half][col] = co;
+    __syncthreads();
+    if (half == 0) {
+        colsum[(int64_t)blockIdx.x * kHidden + col] = csh[0][col] + csh[1][col];
+        if (!dH) colsum_out[(int64_t)blockIdx.x * kHidden + col] = cosh_[0][col] + cosh_[1][col];
+    }
+    // transposed rows: thread -> column t / 2, rows 32 (t % 2) .. + 31 as four 16-byte stores
+    const int tc = threadIdx.x >> 1, rb = (threadIdx.x & 1) * 32;
+    if (r0 + rb < Np) {
+        uint16_t* dst = dZT + (int64_t)tc * ldT + r0 + rb;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            uint32_t w[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                w[q] = (uint32_t)tile[rb + 8 * c + 2 * q][tc] | ((uint32_t)tile[rb + 8 * c + 2 * q + 1][tc] << 16);
+            *reinterpret_cast<uint4*>(dst + 8 * c) = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
 }
 
 // Adam on the FP32 master weights.  The step number comes from the device
@@ -201,6 +207,28 @@ __global__ __launch_bounds__(256) void k_pack(const float* __restrict__ params, 
     const uint16_t b = to_bf16(params[(int64_t)l * kLayerStride + e]);
     W[idx] = b;
     WT[(int64_t)l * kHidden * kHidden + i * kHidden + o] = b;
+}
+
+// Phase 2 pi b_k . r of one Fourier feature (FP64).
+__device__ __forceinline__ double feature_phase(const double* __restrict__ B, int k, double x, double y, double z) {
+    return kTwoPi * (B[3 * k] * x + B[3 * k + 1] * y + B[3 * k + 2] * z);
+}
+
+// poly(r/R) + sigma * y (FP64) at one point.
+__device__ __forceinline__ double finish_value(double x, double y, double z, float net,
+                                               const double* __restrict__ coef, const int8_t* __restrict__ mono,
+                                               int nmono, double inv_r, double sigma) {
+    double px[kMaxPolyDegree + 1], py[kMaxPolyDegree + 1], pz[kMaxPolyDegree + 1];
+    const double ux = x * inv_r, uy = y * inv_r, uz = z * inv_r;
+    px[0] = py[0] = pz[0] = 1.0;
+    for (int d = 1; d <= kMaxPolyDegree; ++d) {
+        px[d] = px[d - 1] * ux;
+        py[d] = py[d - 1] * uy;
+        pz[d] = pz[d - 1] * uz;
+    }
+    double v = 0.0;
+    for (int k = 0; k < nmono; ++k) v += coef[k] * px[mono[3 * k]] * py[mono[3 * k + 1]] * pz[mono[3 * k + 2]];
+    return v + sigma * (double)net;
 }
 
 // The whole network in one kernel.  A workgroup takes 128 rows (four waves
@@ -326,6 +354,119 @@ __global__ __launch_bounds__(256) void k_mlp(const double* __restrict__ pts, int
                 out[row] = add ? v + add[row] : v;
             }
         }
+    }
+}
+
+// One layer of the backward pass in one kernel.  A workgroup takes 128 rows
+// (four waves of 32):
+//  1. dZ = dH * silu'(Z) (dH = dy w_out for the top layer) in FP32; BF16 dZ
+//     into LDS (row-major and transposed) and to dZb; the workgroup's column
+//     sums of the FP32 dZ (bias gradient) and, for the top layer, of
+//     dy * H_top (output weights);
+//  2. for a layer with one below it, dH of that layer = dZ W_l on the matrix
+//     cores with W_l^T staged in LDS (the instruction sequence of k_gemm_nt,
+//     so the values equal the unfused product's), written over dH: every
+//     row of dH is read and rewritten by the one workgroup that owns it;
+//  3. the workgroup's share of dW_l = dZ^T H_l (its rows only), with H_l^T
+//     staged in LDS: a 128 x 128 FP32 partial per workgroup, summed over the
+//     workgroups in fixed order by k_reduce_rows.
+// Rows >= Np contribute zeros.  LDS: three padded 128 x 128 BF16 tiles.
+template <bool TOP>
+__global__ __launch_bounds__(256) void k_mlp_bwd(float* __restrict__ dH, const float* __restrict__ dy,
+                                                 const float* __restrict__ w_out, const float* __restrict__ Z,
+                                                 const uint16_t* __restrict__ Htop,
+                                                 const uint16_t* __restrict__ WT, const uint16_t* __restrict__ HT,
+                                                 int64_t Np, bool below, uint16_t* __restrict__ dZb,
+                                                 float* __restrict__ gpart, float* __restrict__ colsum,
+                                                 float* __restrict__ colsum_out) {
+    __shared__ __attribute__((aligned(16))) uint16_t sA[kInferRows * kLdsLd];  // dZ [row][o]
+    __shared__ __attribute__((aligned(16))) uint16_t sB[kHidden * kLdsLd];     // dZ^T [o][row]
+    __shared__ __attribute__((aligned(16))) uint16_t sC[kHidden * kLdsLd];     // W^T [i][o], then H^T [i][row]
+    __shared__ float csh[2][kHidden], cosh_[2][kHidden];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 5, r = lane & 31;
+    const int64_t row0 = (int64_t)blockIdx.x * kInferRows;
+    {   // 1. thread -> column t % 128, rows 64 (t / 128) .. + 63
+        const int col = tid & (kHidden - 1), half = tid >> 7;
+        float cs = 0.0f, co = 0.0f;
+        for (int rl = half * 64; rl < half * 64 + 64; ++rl) {
+            const int64_t row = row0 + rl;
+            uint16_t b = 0;
+            if (row < Np) {
+                const int64_t idx = row * kHidden + col;
+                float gv;
+                if (TOP) {
+                    gv = dy[row] * w_out[col];
+                    co = __builtin_fmaf(dy[row], __uint_as_float((uint32_t)Htop[idx] << 16), co);
+                } else {
+                    gv = dH[idx];
+                }
+                const float dz = gv * dsilu(Z[idx]);
+                cs += dz;
+                b = to_bf16(dz);
+                dZb[idx] = b;
+            }
+            sA[rl * kLdsLd + col] = b;
+            sB[col * kLdsLd + rl] = b;
+        }
+        csh[half][col] = cs;
+        if (TOP) cosh_[half][col] = co;
+    }
+    __syncthreads();
+    if (tid < kHidden) {
+        colsum[(int64_t)blockIdx.x * kHidden + tid] = csh[0][tid] + csh[1][tid];
+        if (TOP) colsum_out[(int64_t)blockIdx.x * kHidden + tid] = cosh_[0][tid] + cosh_[1][tid];
+    }
+    if (below) {   // 2. dH of the layer below = dZ W (Bt = W^T rows)
+        const uint4* gW = reinterpret_cast<const uint4*>(WT);
+        for (int q = tid; q < kHidden * kHidden / 8; q += 256) {
+            const int i = q >> 4, c = q & 15;
+            *reinterpret_cast<uint4*>(sC + i * kLdsLd + c * 8) = gW[q];
+        }
+        __syncthreads();
+        f32x16 acc[4] = {};
+        const uint16_t* a = sA + (wave * 32 + r) * kLdsLd + g * 8;
+        for (int k = 0; k < kHidden; k += 16) {
+            const bf16x8 av = *reinterpret_cast<const bf16x8*>(a + k);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const bf16x8 bv = *reinterpret_cast<const bf16x8*>(sC + (t * 32 + r) * kLdsLd + g * 8 + k);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[t], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int64_t row = row0 + wave * 32 + (i >> 2) * 8 + g * 4 + (i & 3);
+                if (row < Np) dH[row * kHidden + t * 32 + r] = acc[t][i];
+            }
+        __syncthreads();   // sC is overwritten next
+    }
+    {   // 3. stage H^T [i][row0 .. row0 + 127] (zero past Np; Np is a multiple of 32)
+        for (int q = tid; q < kHidden * kInferRows / 8; q += 256) {
+            const int i = q >> 4, c = q & 15;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (row0 + c * 8 < Np) v = *reinterpret_cast<const uint4*>(HT + (int64_t)i * Np + row0 + c * 8);
+            *reinterpret_cast<uint4*>(sC + i * kLdsLd + c * 8) = v;
+        }
+        __syncthreads();
+        // wave w: output rows o = 32 w .. + 31, all 128 columns i
+        f32x16 acc[4] = {};
+        const uint16_t* a = sB + (wave * 32 + r) * kLdsLd + g * 8;
+        for (int k = 0; k < kInferRows; k += 16) {
+            const bf16x8 av = *reinterpret_cast<const bf16x8*>(a + k);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const bf16x8 bv = *reinterpret_cast<const bf16x8*>(sC + (t * 32 + r) * kLdsLd + g * 8 + k);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[t], 0, 0, 0);
+            }
+        }
+        float* gp = gpart + (int64_t)blockIdx.x * kHidden * kHidden;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                gp[(wave * 32 + (i >> 2) * 8 + g * 4 + (i & 3)) * kHidden + t * 32 + r] = acc[t][i];
     }
 }
 
@@ -531,7 +672,7 @@ int sg_gemm_nt(const uint16_t* A, int lda, const uint16_t* Bt, int ldb, float* C
 }
 
 void sg_reduce_rows(const float* part, int P, int64_t L, float* out, void* st) {
-    SG_LAUNCH(k_reduce_rows, dim3(blocks(L)), dim3(256), st, part, P, L, out);
+    SG_LAUNCH(k_reduce_rows, dim3(blocks(L, 64)), dim3(256), st, part, P, L, out);
 }
 
 void sg_loss(const float* y, const float* t, int64_t n, int64_t Np, float* dy, double* part, float* part_dy,
@@ -542,7 +683,7 @@ void sg_loss(const float* y, const float* t, int64_t n, int64_t Np, float* dy, d
 void sg_dsilu(const float* dH, const float* dy, const float* w_out, const float* Z, const uint16_t* Htop,
               int64_t Np, uint16_t* dZb, uint16_t* dZT, int64_t ldT, float* colsum, float* colsum_out,
               void* st) {
-    SG_LAUNCH(k_dsilu, dim3(blocks(Np, kRowsPerBlock)), dim3(kHidden), st, dH, dy, w_out, Z, Htop, Np, dZb,
+    SG_LAUNCH(k_dsilu, dim3(blocks(Np, kRowsPerBlock)), dim3(256), st, dH, dy, w_out, Z, Htop, Np, dZb,
               dZT, ldT, colsum, colsum_out);
 }
 
@@ -580,6 +721,19 @@ void sg_forward_train(const double* pts, int64_t n, int64_t Np, const double* B,
     ts.Np = Np;
     SG_LAUNCH(k_mlp<true>, dim3(blocks(Np, kInferRows)), dim3(256), st, pts, n, B, W, params, nullptr, nullptr, 0,
               0.0, 0.0, nullptr, nullptr, ts);
+}
+
+int sg_backward_layer(bool top, float* dH, const float* dy, const float* w_out, const float* Z, const uint16_t* Htop,
+                      const uint16_t* WT, const uint16_t* HT, int64_t Np, bool below, uint16_t* dZb, float* gpart,
+                      float* colsum, float* colsum_out, void* st) {
+    const unsigned nb = blocks(Np, kInferRows);
+    if (top)
+        SG_LAUNCH(k_mlp_bwd<true>, dim3(nb), dim3(256), st, dH, dy, w_out, Z, Htop, WT, HT, Np, below, dZb, gpart,
+                  colsum, colsum_out);
+    else
+        SG_LAUNCH(k_mlp_bwd<false>, dim3(nb), dim3(256), st, dH, dy, w_out, Z, Htop, WT, HT, Np, below, dZb, gpart,
+                  colsum, colsum_out);
+    return int(nb);
 }
 
 void sg_residual(const double* pts, const double* V, int64_t n, const double* coef, const int8_t* mono,

@@ -47,6 +47,14 @@ void sg_infer(const double* pts, int64_t n, const double* B, const uint16_t* W, 
 void sg_forward_train(const double* pts, int64_t n, int64_t Np, const double* B, const uint16_t* W,
                       const float* params, uint16_t* const* H, uint16_t* const* HT, float* const* Z, float* y,
                       void* st);
+// One layer of the backward pass in one launch: BF16 dZ (to dZb), the
+// per-workgroup column sums of dZ (and, top layer, of dy H_top), dH of the
+// layer below written over dH (when `below`), and per-workgroup 128 x 128
+// partials of dW; returns the number of workgroups (partials).  Np is a
+// multiple of 32.
+int sg_backward_layer(bool top, float* dH, const float* dy, const float* w_out, const float* Z, const uint16_t* Htop,
+                      const uint16_t* WT, const uint16_t* HT, int64_t Np, bool below, uint16_t* dZb, float* gpart,
+                      float* colsum, float* colsum_out, void* st);
 void sg_residual(const double* pts, const double* V, int64_t n, const double* coef, const int8_t* mono,
                  int nmono, double inv_r, double inv_sigma, float* t, void* st);
 void sg_sample_ball(uint64_t seed, int64_t n, double R, double* pts, void* st);

@@ -161,8 +161,8 @@ def test_clusters_match_pairwise(precision):
 
 
 @pytest.mark.parametrize("precision,shapes", [
-    ("fp32c", [(4, 0), (4, 3), (4, 6), (2, 5), (1, 2)]),
-    ("fp64", [(2, 0), (2, 6), (1, 3)]),
+    ("fp32c", [(4, 0), (4, 3), (4, 6), (4, 8), (2, 5), (1, 2)]),
+    ("fp64", [(2, 0), (2, 6), (2, 8), (1, 3)]),
 ])
 def test_launch_shapes_agree(precision, shapes, monkeypatch):
     """Every points-per-lane / pair-split shape gives the same potential up to

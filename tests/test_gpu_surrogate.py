@@ -156,6 +156,15 @@ def test_train_gate_and_fallback():
     ref = fb.eval(torch.from_numpy(np.ascontiguousarray(pts[idx])).cuda()).cpu().numpy()
     assert np.array_equal(V[idx], ref)
     assert S.info()["last_eval_fallback"] == len(idx)
+    # a new density of the fallback environment: the network was trained on
+    # the old one, so the surrogate refuses to evaluate
+    from paper_1011_4687_amd import envpot
+    rowp, col, val = P
+    fb.update_density((rowp, col, val * 1.05))
+    for call in (lambda: S.eval(x), lambda: S.predict(x)):
+        with pytest.raises(envpot.EnvError) as ei:
+            call()
+        assert ei.value.status == envpot.ENV_E_STATE
     S.close()
 
 
@@ -202,6 +211,77 @@ def test_gain_on_surrogate_workload():
     print(f"[surrogate] max err vs oracle {err.max():.3e}", flush=True)
     assert err.max() <= 1e-5
     assert used.cpu().numpy()[len(infer):].all()
+    # every point against the FP64 kernel
+    V64 = te.eval(x).cpu().numpy()
+    d = np.abs(V.cpu().numpy() - V64)
+    print(f"[surrogate] all {len(d)} points vs FP64 kernel: max {d.max():.3e}", flush=True)
+    assert d.max() <= 1e-5
+    # the stored oracle sample of the workload (16,384 of its 1,065,536
+    # points, tests/golden/make_goldens.py), evaluated at those points
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "surrogate_oracle_16384.npz")
+    if os.path.exists(path):
+        g = np.load(path)
+        _, inf_all, out_all = synth.surrogate_sets(n_train=1, n_infer=1_000_000, n_out=65536)
+        allp = np.ascontiguousarray(np.concatenate([inf_all, out_all]))
+        assert str(g["env_digest"]) == env.digest() and str(g["points_digest"]) == synth.digest(allp)
+        xs = torch.from_numpy(np.ascontiguousarray(allp[g["idx"]])).cuda()
+        Vg, ug = S.eval(xs)
+        eg = np.abs(Vg.cpu().numpy() - g["V"])
+        print(f"[surrogate] stored oracle sample ({len(eg)} points, fallback "
+              f"{ug.float().mean().item():.3f}): max {eg.max():.3e}", flush=True)
+        assert eg.max() <= 1e-5
     S.close()
     fb.close()
     te.close()
+
+
+def test_split_surrogate_with_exact_part():
+    """Split surrogate (env_surrogate_set_near): the network learns the
+    potential of the fragments other than the nearest one (teacher: their
+    FP64 handle), the nearest fragment is evaluated exactly at every point
+    and added.  Points the network serves are within 1e-5 Ha of the FP64
+    kernel of the whole environment; gated-out points equal the whole
+    environment's FP32C kernel bit for bit; predict gives the network alone;
+    removing the exact part changes served points by exactly its values."""
+    import torch
+    from oracle import oracle as O
+    from paper_1011_4687_amd.envpot import Environment, Surrogate, fourier_matrix, init_params
+    print("[surrogate] split", flush=True)
+    rng = np.random.Generator(np.random.PCG64(777))
+    env = synth.make_fragmented(60, rng)
+    sc = O.neutral_scales(env)
+    nearest = int(env.fragment[np.argmin(np.linalg.norm(env.xyz, axis=1))])
+    far = [f for f in range(env.n_fragments) if f != nearest]
+    fb = Environment.from_synth(env, scale=sc, precision="fp32c")
+    full64 = Environment.from_synth(env, scale=sc, precision="fp64")
+    near = Environment.from_synth(synth.subset(env, [nearest]), scale=sc[[nearest]], precision="fp32c")
+    teach = Environment.from_synth(synth.subset(env, far), scale=sc[far], precision="fp64")
+    S = Surrogate(fb, fourier_matrix(12, 0.25), init_params(12), radius=3.0)
+    S.set_near(near)
+    S.train(teach, n_train=262144, epochs=24, batch=4096, gate_grid=12, gate_samples=16, n_fit=65536,
+            poly_degree=8)
+    pts = np.concatenate([synth.points_in_ball(np.random.default_rng(21), 20000, 3.0),
+                          synth.points_in_ball(np.random.default_rng(22), 1000, 5.0, r_min=3.5)])
+    x = torch.from_numpy(pts).cuda()
+    V, used = S.eval(x)
+    V, used = V.cpu().numpy(), used.cpu().numpy().astype(bool)
+    served = float((~used[:20000]).mean())
+    print(f"[surrogate] split: network serves {served:.3f} of the in-region points", flush=True)
+    assert used[20000:].all() and served > 0.0
+    ref64 = full64.eval(x).cpu().numpy()
+    assert np.abs(V[~used] - ref64[~used]).max() <= 1e-5
+    idx = np.nonzero(used)[0]
+    ref32 = fb.eval(torch.from_numpy(np.ascontiguousarray(pts[idx])).cuda()).cpu().numpy()
+    assert np.array_equal(V[idx], ref32)
+    # the network alone, and the network plus the exact part
+    net = S.predict(x).cpu().numpy()
+    vn = near.eval(x).cpu().numpy()
+    assert np.array_equal(V[~used], net[~used] + vn[~used])
+    S.set_near(None)
+    V2, used2 = S.eval(x)
+    assert np.array_equal(used2.cpu().numpy().astype(bool), used)
+    assert np.array_equal(V2.cpu().numpy()[~used], net[~used])
+    S.close()
+    for E in (fb, full64, near, teach):
+        E.close()
