@@ -649,7 +649,12 @@ def main():
             "flops_basis": "McMurchie-Davidson-equivalent flops per point-pair (recursion, Boys, contraction); "
                            "the kernel evaluates far pairs by an exact multipole polynomial and merged "
                            "same-centre clusters, which execute fewer, so this is a work rate, not issue use",
-            "valu_issue_utilization": counters.get("valu_issue_utilization") if counters else None,
+            "issue": {k: counters.get(k) for k in ("valu_issue_vs_probe", "valubusy_rocprof",
+                                                     "probe_valubusy_rocprof", "probe_issue_vs_nominal",
+                                                     "lds_bank_conflict_rocprof")} if counters else None,
+            "issue_basis": "committed counter record of this kernel (profiles/k_potential_large_counters.json): "
+                           "VALU wave-instructions per second against the v_fma_f32 probe of the same counter "
+                           "pass, rocprof VALUBusy of both" if counters else None,
         },
         "paths": paths,
         "secondary": secondary,
