@@ -24,21 +24,18 @@ struct Workspace {
     int64_t cap = 0;    // rows (multiple of 32)
     bool train = false;
     uint16_t* H[kLayers + 1] = {};
-    uint16_t* HT[kLayers + 1] = {};
     float* Z[kLayers] = {};
     float* y = nullptr;
     float* dy = nullptr;
     uint16_t* dZb = nullptr;
-    uint16_t* dZT = nullptr;
     float* dH = nullptr;
-    float* gpart = nullptr;     // split-K partials of dW: kSplitK x 128 x 128
+    float* gpart = nullptr;     // per-workgroup partials of dW: (rows / 128) x 128 x 128
     float* colb = nullptr;      // per-block column sums (bias gradient)
     float* colo = nullptr;      // per-block column sums (output weights)
     double* losspart = nullptr;
     float* dypart = nullptr;    // per-block sums of dy
 };
 
-constexpr int kSplitK = 16;
 
 template <typename T>
 bool dalloc(T** p, size_t n) {
@@ -48,8 +45,7 @@ bool dalloc(T** p, size_t n) {
 void ws_free(Workspace& w) {
     for (int l = 0; l <= kLayers; ++l) {
         (void)hipFree(w.H[l]);
-        (void)hipFree(w.HT[l]);
-        w.H[l] = w.HT[l] = nullptr;
+        w.H[l] = nullptr;
     }
     for (int l = 0; l < kLayers; ++l) {
         (void)hipFree(w.Z[l]);
@@ -58,7 +54,6 @@ void ws_free(Workspace& w) {
     (void)hipFree(w.y);
     (void)hipFree(w.dy);
     (void)hipFree(w.dZb);
-    (void)hipFree(w.dZT);
     (void)hipFree(w.dH);
     (void)hipFree(w.gpart);
     (void)hipFree(w.colb);
@@ -77,15 +72,14 @@ bool ws_ensure(Workspace& w, int64_t rows, bool train) {
     bool ok = true;
     for (int l = 0; l <= kLayers; ++l) {
         ok = ok && dalloc(&w.H[l], size_t(cap) * kHidden);
-        if (train) ok = ok && dalloc(&w.HT[l], size_t(cap) * kHidden);
     }
     for (int l = 0; l < kLayers; ++l) ok = ok && dalloc(&w.Z[l], size_t(cap) * kHidden);
     ok = ok && dalloc(&w.y, cap);
     if (train) {
-        const int64_t nb = (cap + kRowsPerBlock - 1) / kRowsPerBlock;
+        const int64_t nb = (cap + 127) / 128;   // workgroups of the backward layer kernel
         ok = ok && dalloc(&w.dy, cap) && dalloc(&w.dZb, size_t(cap) * kHidden) &&
-             dalloc(&w.dZT, size_t(cap) * kHidden) && dalloc(&w.dH, size_t(cap) * kHidden) &&
-             dalloc(&w.gpart, size_t(kSplitK) * kHidden * kHidden) && dalloc(&w.colb, size_t(nb) * kHidden) &&
+             dalloc(&w.dH, size_t(cap) * kHidden) &&
+             dalloc(&w.gpart, size_t((cap + 127) / 128) * kHidden * kHidden) && dalloc(&w.colb, size_t(nb) * kHidden) &&
              dalloc(&w.colo, size_t(nb) * kHidden) && dalloc(&w.losspart, size_t((cap + 255) / 256)) &&
              dalloc(&w.dypart, size_t((cap + 255) / 256));
     }
@@ -158,7 +152,7 @@ env_status upload_baseline(env_surrogate* s) {
 // the backward pass reads (H and H^T of every layer, Z, y in ws.y); one launch.
 void forward(env_surrogate* s, const double* pts, int64_t n, int64_t Np, void* st) {
     Workspace& w = s->ws;
-    sg_forward_train(pts, n, Np, s->d_B, s->d_W, s->d_params, w.H, w.HT, w.Z, w.y, st);
+    sg_forward_train(pts, n, Np, s->d_B, s->d_W, s->d_params, w.H, w.Z, w.y, st);
 }
 
 // Host copies of the intermediate tensors of one training step (see
@@ -179,13 +173,15 @@ void backward(env_surrogate* s, const float* t, int64_t n, int64_t Np, void* st,
     hipStream_t hst = static_cast<hipStream_t>(st);
     sg_loss(w.y, t, n, Np, w.dy, w.losspart, w.dypart, st);
     if (tc) tc->copy(tc->tr->dy, w.dy, size_t(n) * sizeof(float), hst);
-    const int nb = int((Np + kRowsPerBlock - 1) / kRowsPerBlock);
     for (int l = kLayers - 1; l >= 0; --l) {
         const bool top = l == kLayers - 1;
         if (tc && !top) tc->copy(tc->tr->dH ? tc->tr->dH + size_t(l) * n * kHidden : nullptr, w.dH,
                                  size_t(n) * kHidden * sizeof(float), hst);
-        sg_dsilu(top ? nullptr : w.dH, w.dy, s->d_params + kOutOffset, w.Z[l], w.H[kLayers], Np, w.dZb, w.dZT,
-                 Np, w.colb, w.colo, st);
+        // dZ, the bias and output-weight column sums, dH of the layer below
+        // (over w.dH) and the dW partials in one launch
+        const int nb = sg_backward_layer(top, w.dH, w.dy, s->d_params + kOutOffset, w.Z[l], w.H[kLayers],
+                                         s->d_WT + size_t(l) * kHidden * kHidden, w.H[l], Np, l > 0, w.dZb,
+                                         w.gpart, w.colb, w.colo, st);
         if (tc && tc->tr->dZ)
             tc->copy(tc->dzb.data() + size_t(l) * n * kHidden, w.dZb, size_t(n) * kHidden * sizeof(uint16_t), hst);
         float* gl = s->d_grad + size_t(l) * kLayerStride;
@@ -194,12 +190,7 @@ void backward(env_surrogate* s, const float* t, int64_t n, int64_t Np, void* st,
             sg_reduce_rows(w.colo, nb, kHidden, s->d_grad + kOutOffset, st);
             sg_reduce_rows(w.dypart, int((Np + 255) / 256), 1, s->d_grad + kOutOffset + kHidden, st);
         }
-        const int nz = sg_gemm_nt(w.dZT, int(Np), w.HT[l], int(Np), w.gpart, kHidden, kHidden, kHidden, int(Np),
-                                  kSplitK, st);
-        sg_reduce_rows(w.gpart, nz, int64_t(kHidden) * kHidden, gl, st);
-        if (l > 0)
-            sg_gemm_nt(w.dZb, kHidden, s->d_WT + size_t(l) * kHidden * kHidden, kHidden, w.dH, kHidden, int(Np),
-                       kHidden, kHidden, 1, st);
+        sg_reduce_rows(w.gpart, nb, int64_t(kHidden) * kHidden, gl, st);
     }
 }
 

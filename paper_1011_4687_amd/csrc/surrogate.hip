@@ -6,11 +6,11 @@
 // straight-through BF16 rounding, Adam on FP32 master weights.
 //
 // The forward pass (features, the four layers, the output) is one kernel,
-// k_mlp, that keeps a workgroup's 128 rows in LDS; the backward products use
-// one NT kernel: C[M x N] = A[M x K] * Bt[N x K]^T with BF16 row-major
-// operands (K contiguous), each wave owning a 32 x 32 tile of C, gridDim.z
-// splitting K (partials summed in fixed order by k_reduce_rows).  Both use
-// v_mfma_f32_32x32x16_bf16.  Operand layout of the instruction (verified
+// k_mlp, that keeps a workgroup's 128 rows in LDS; each layer of the backward
+// pass is one kernel, k_mlp_bwd, likewise (dZ, dH of the layer below, the
+// workgroup's dW partial, summed over workgroups in fixed order by
+// k_reduce_rows).  Every product is C[M x N] = A[M x K] * Bt[N x K]^T with
+// BF16 operands (K contiguous) staged in LDS, on v_mfma_f32_32x32x16_bf16.  Operand layout of the instruction (verified
 // on the device): lane l, g = l / 32, r = l % 32 holds A[r][g*8 .. g*8+7] and
 // Bt[r][g*8 .. g*8+7]; result register i holds C[(i/4)*8 + g*4 + i%4][r].
 #include <hip/hip_runtime.h>
@@ -36,30 +36,6 @@ __device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z));
 __device__ __forceinline__ float dsilu(float z) {
     const float s = 1.0f / (1.0f + __expf(-z));
     return s * (1.0f + z * (1.0f - s));
-}
-
-__global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t* __restrict__ A, int lda,
-                                                 const uint16_t* __restrict__ Bt, int ldb,
-                                                 float* __restrict__ C, int ldc, int M, int N, int K,
-                                                 int kchunk, int64_t cstride) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 5, r = lane & 31;
-    const int tm = (blockIdx.y * 2 + (wave >> 1)) * 32;
-    const int tn = (blockIdx.x * 2 + (wave & 1)) * 32;
-    if (tm >= M || tn >= N) return;  // wave-uniform
-    const int k0 = blockIdx.z * kchunk;
-    const int k1 = min(K, k0 + kchunk);
-    f32x16 acc = {};
-    const uint16_t* a = A + (int64_t)(tm + r) * lda + g * 8;
-    const uint16_t* b = Bt + (int64_t)(tn + r) * ldb + g * 8;
-    for (int k = k0; k < k1; k += 16) {
-        const uint4 av = *reinterpret_cast<const uint4*>(a + k);
-        const uint4 bv = *reinterpret_cast<const uint4*>(b + k);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av),
-                                                      __builtin_bit_cast(bf16x8, bv), acc, 0, 0, 0);
-    }
-    float* c = C + blockIdx.z * cstride;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) c[(int64_t)(tm + (i >> 2) * 8 + g * 4 + (i & 3)) * ldc + tn + r] = acc[i];
 }
 
 // out[j] = sum_{p < P} part[p * L + j] in FP64: four groups of consecutive
@@ -108,63 +84,6 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ y, const
     if (threadIdx.x == 0) {
         part[blockIdx.x] = sh[0];
         part_dy[blockIdx.x] = shd[0];
-    }
-}
-
-// Backward through SiLU for one layer.  dH = dy (x) w_out for the top layer
-// (dH == nullptr), else the given FP32 dH.  Writes bf16(dZ) [Np x 128] and
-// its transpose [128 x ldT] (staged through LDS, so both are written in
-// 16-byte rows), the per-block column sums of dZ (bias gradient) and, for the
-// top layer, the per-block column sums of dy * H (output-weight gradient).
-// Block: 256 threads over kRowsPerBlock = 64 rows (two halves of 32 rows per
-// column; Np is a multiple of 32).
-__global__ __launch_bounds__(256) void k_dsilu(const float* __restrict__ dH, const float* __restrict__ dy,
-                                               const float* __restrict__ w_out, const float* __restrict__ Z,
-                                               const uint16_t* __restrict__ Htop, int64_t Np,
-                                               uint16_t* __restrict__ dZb, uint16_t* __restrict__ dZT,
-                                               int64_t ldT, float* __restrict__ colsum,
-                                               float* __restrict__ colsum_out) {
-    __shared__ uint16_t tile[kRowsPerBlock][kHidden + 2];
-    __shared__ float csh[2][kHidden], cosh_[2][kHidden];
-    const int col = threadIdx.x & (kHidden - 1), half = threadIdx.x >> 7;
-    const int64_t r0 = (int64_t)blockIdx.x * kRowsPerBlock;
-    float cs = 0.0f, co = 0.0f;
-    for (int rl = half * 32; rl < half * 32 + 32; ++rl) {
-        const int64_t row = r0 + rl;
-        if (row >= Np) break;
-        const int64_t idx = row * kHidden + col;
-        float g;
-        if (dH) {
-            g = dH[idx];
-        } else {
-            g = dy[row] * w_out[col];
-            co = __builtin_fmaf(dy[row], __uint_as_float((uint32_t)Htop[idx] << 16), co);
-        }
-        const float dz = g * dsilu(Z[idx]);
-        cs += dz;
-        const uint16_t b = to_bf16(dz);
-        dZb[idx] = b;
-        tile[rl][col] = b;
-    }
-    csh[half][col] = cs;
-    cosh_[half][col] = co;
-    __syncthreads();
-    if (half == 0) {
-        colsum[(int64_t)blockIdx.x * kHidden + col] = csh[0][col] + csh[1][col];
-        if (!dH) colsum_out[(int64_t)blockIdx.x * kHidden + col] = cosh_[0][col] + cosh_[1][col];
-    }
-    // transposed rows: thread -> column t / 2, rows 32 (t % 2) .. + 31 as four 16-byte stores
-    const int tc = threadIdx.x >> 1, rb = (threadIdx.x & 1) * 32;
-    if (r0 + rb < Np) {
-        uint16_t* dst = dZT + (int64_t)tc * ldT + r0 + rb;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            uint32_t w[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                w[q] = (uint32_t)tile[rb + 8 * c + 2 * q][tc] | ((uint32_t)tile[rb + 8 * c + 2 * q + 1][tc] << 16);
-            *reinterpret_cast<uint4*>(dst + 8 * c) = make_uint4(w[0], w[1], w[2], w[3]);
-        }
     }
 }
 
@@ -234,21 +153,18 @@ __device__ __forceinline__ double finish_value(double x, double y, double z, flo
 // The whole network in one kernel.  A workgroup takes 128 rows (four waves
 // of 32), computes their Fourier features into LDS, then per layer stages
 // the layer's BF16 weights in LDS and lets each wave multiply its own 32
-// rows by them on the matrix cores (the instruction sequence of k_gemm_nt:
-// four 32 x 32 output tiles, K = 128 in steps of 16), adds the bias, applies
-// SiLU and writes the BF16 activations back over its rows; then the FP32
-// output layer.  Inference (TRAIN false) finishes with the baseline and the
-// optional exact part; training (TRAIN true) also stores what the backward
-// pass reads: H_0..H_4 row-major and transposed, the pre-activations Z_l and
-// y, for the first Np rows.  Every step has the arithmetic of the unfused
-// kernels, so the values equal theirs.  LDS rows are padded to 136 elements
-// (bank spread of the 16-byte row reads).
+// rows by them on the matrix cores (four 32 x 32 output tiles, K = 128 in
+// steps of 16), adds the bias, applies SiLU and writes the BF16 activations
+// back over its rows; then the FP32 output layer.  Inference (TRAIN false)
+// finishes with the baseline and the optional exact part; training (TRAIN
+// true) also stores what the backward pass reads: H_0..H_4 (row-major), the
+// pre-activations Z_l and y, for the first Np rows.  LDS rows
+// are padded to 136 elements (bank spread of the 16-byte row reads).
 constexpr int kInferRows = 128;
 constexpr int kLdsLd = kHidden + 8;
 
 struct TrainStores {
     uint16_t* H[kLayers + 1];
-    uint16_t* HT[kLayers + 1];
     float* Z[kLayers];
     float* y;
     int64_t Np;     // rows stored (multiple of 32; rows >= n are padding with zero features)
@@ -289,8 +205,6 @@ __global__ __launch_bounds__(256) void k_mlp(const double* __restrict__ pts, int
             if (TRAIN && row < nstore) {
                 ts.H[0][row * kHidden + k] = c;
                 ts.H[0][row * kHidden + kFreq + k] = sn;
-                ts.HT[0][(int64_t)k * nstore + row] = c;
-                ts.HT[0][(int64_t)(kFreq + k) * nstore + row] = sn;
             }
         }
     }
@@ -331,7 +245,6 @@ __global__ __launch_bounds__(256) void k_mlp(const double* __restrict__ pts, int
                     if (row < nstore) {
                         ts.Z[l][row * kHidden + col] = zv;
                         ts.H[l + 1][row * kHidden + col] = h;
-                        ts.HT[l + 1][(int64_t)col * nstore + row] = h;
                     }
                 }
             }
@@ -364,18 +277,19 @@ __global__ __launch_bounds__(256) void k_mlp(const double* __restrict__ pts, int
 //     sums of the FP32 dZ (bias gradient) and, for the top layer, of
 //     dy * H_top (output weights);
 //  2. for a layer with one below it, dH of that layer = dZ W_l on the matrix
-//     cores with W_l^T staged in LDS (the instruction sequence of k_gemm_nt,
-//     so the values equal the unfused product's), written over dH: every
-//     row of dH is read and rewritten by the one workgroup that owns it;
+//     cores with W_l^T staged in LDS (the tiling of the forward layers),
+//     written over dH: every row of dH is read and rewritten by the one
+//     workgroup that owns it;
 //  3. the workgroup's share of dW_l = dZ^T H_l (its rows only), with H_l^T
-//     staged in LDS: a 128 x 128 FP32 partial per workgroup, summed over the
-//     workgroups in fixed order by k_reduce_rows.
+//     transposed into LDS from the row-major H_l: a 128 x 128 FP32 partial
+//     per workgroup, summed over the workgroups in fixed order by
+//     k_reduce_rows.
 // Rows >= Np contribute zeros.  LDS: three padded 128 x 128 BF16 tiles.
 template <bool TOP>
 __global__ __launch_bounds__(256) void k_mlp_bwd(float* __restrict__ dH, const float* __restrict__ dy,
                                                  const float* __restrict__ w_out, const float* __restrict__ Z,
                                                  const uint16_t* __restrict__ Htop,
-                                                 const uint16_t* __restrict__ WT, const uint16_t* __restrict__ HT,
+                                                 const uint16_t* __restrict__ WT, const uint16_t* __restrict__ H,
                                                  int64_t Np, bool below, uint16_t* __restrict__ dZb,
                                                  float* __restrict__ gpart, float* __restrict__ colsum,
                                                  float* __restrict__ colsum_out) {
@@ -442,12 +356,18 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(float* __restrict__ dH, const f
             }
         __syncthreads();   // sC is overwritten next
     }
-    {   // 3. stage H^T [i][row0 .. row0 + 127] (zero past Np; Np is a multiple of 32)
+    {   // 3. stage H^T [i][row] from the row-major H rows row0 .. row0 + 127
+        //    (16-byte global reads, transposed into LDS; zero past Np)
         for (int q = tid; q < kHidden * kInferRows / 8; q += 256) {
-            const int i = q >> 4, c = q & 15;
+            const int rl = q >> 4, c = q & 15;
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (row0 + c * 8 < Np) v = *reinterpret_cast<const uint4*>(HT + (int64_t)i * Np + row0 + c * 8);
-            *reinterpret_cast<uint4*>(sC + i * kLdsLd + c * 8) = v;
+            if (row0 + rl < Np) v = *reinterpret_cast<const uint4*>(H + (row0 + rl) * kHidden + c * 8);
+            const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                sC[(c * 8 + 2 * j) * kLdsLd + rl] = (uint16_t)(w4[j] & 0xFFFFu);
+                sC[(c * 8 + 2 * j + 1) * kLdsLd + rl] = (uint16_t)(w4[j] >> 16);
+            }
         }
         __syncthreads();
         // wave w: output rows o = 32 w .. + 31, all 128 columns i
@@ -659,18 +579,6 @@ inline unsigned blocks(int64_t n, int per = 256) { return (unsigned)((n + per - 
 
 #define SG_LAUNCH(k, g, b, st, ...) hipLaunchKernelGGL(k, g, b, 0, static_cast<hipStream_t>(st), __VA_ARGS__)
 
-int sg_gemm_nt(const uint16_t* A, int lda, const uint16_t* Bt, int ldb, float* C, int ldc, int M, int N,
-               int K, int ksplit, void* st) {
-    if (M % 32 || N % 32 || K % 16 || lda % 8 || ldb % 8 || ksplit < 1) return -1;
-    int kchunk = (K + ksplit - 1) / ksplit;
-    kchunk = (kchunk + 15) / 16 * 16;
-    const int nz = (K + kchunk - 1) / kchunk;
-    const dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64), (unsigned)nz);
-    SG_LAUNCH(k_gemm_nt, grid, dim3(256), st, A, lda, Bt, ldb, C, ldc, M, N, K, kchunk,
-              (int64_t)M * ldc);
-    return nz;
-}
-
 void sg_reduce_rows(const float* part, int P, int64_t L, float* out, void* st) {
     SG_LAUNCH(k_reduce_rows, dim3(blocks(L, 64)), dim3(256), st, part, P, L, out);
 }
@@ -678,13 +586,6 @@ void sg_reduce_rows(const float* part, int P, int64_t L, float* out, void* st) {
 void sg_loss(const float* y, const float* t, int64_t n, int64_t Np, float* dy, double* part, float* part_dy,
              void* st) {
     SG_LAUNCH(k_loss, dim3(blocks(Np)), dim3(256), st, y, t, n, Np, dy, part, part_dy);
-}
-
-void sg_dsilu(const float* dH, const float* dy, const float* w_out, const float* Z, const uint16_t* Htop,
-              int64_t Np, uint16_t* dZb, uint16_t* dZT, int64_t ldT, float* colsum, float* colsum_out,
-              void* st) {
-    SG_LAUNCH(k_dsilu, dim3(blocks(Np, kRowsPerBlock)), dim3(256), st, dH, dy, w_out, Z, Htop, Np, dZb,
-              dZT, ldT, colsum, colsum_out);
 }
 
 void sg_adam(float* p, const float* g, float* m, float* v, int64_t n, const TrainState* ts, double lr0,
@@ -708,14 +609,10 @@ void sg_infer(const double* pts, int64_t n, const double* B, const uint16_t* W, 
 }
 
 void sg_forward_train(const double* pts, int64_t n, int64_t Np, const double* B, const uint16_t* W,
-                      const float* params, uint16_t* const* H, uint16_t* const* HT, float* const* Z, float* y,
-                      void* st) {
+                      const float* params, uint16_t* const* H, float* const* Z, float* y, void* st) {
     if (Np <= 0) return;
     TrainStores ts;
-    for (int l = 0; l <= kLayers; ++l) {
-        ts.H[l] = H[l];
-        ts.HT[l] = HT[l];
-    }
+    for (int l = 0; l <= kLayers; ++l) ts.H[l] = H[l];
     for (int l = 0; l < kLayers; ++l) ts.Z[l] = Z[l];
     ts.y = y;
     ts.Np = Np;
@@ -724,14 +621,14 @@ void sg_forward_train(const double* pts, int64_t n, int64_t Np, const double* B,
 }
 
 int sg_backward_layer(bool top, float* dH, const float* dy, const float* w_out, const float* Z, const uint16_t* Htop,
-                      const uint16_t* WT, const uint16_t* HT, int64_t Np, bool below, uint16_t* dZb, float* gpart,
+                      const uint16_t* WT, const uint16_t* H, int64_t Np, bool below, uint16_t* dZb, float* gpart,
                       float* colsum, float* colsum_out, void* st) {
     const unsigned nb = blocks(Np, kInferRows);
     if (top)
-        SG_LAUNCH(k_mlp_bwd<true>, dim3(nb), dim3(256), st, dH, dy, w_out, Z, Htop, WT, HT, Np, below, dZb, gpart,
+        SG_LAUNCH(k_mlp_bwd<true>, dim3(nb), dim3(256), st, dH, dy, w_out, Z, Htop, WT, H, Np, below, dZb, gpart,
                   colsum, colsum_out);
     else
-        SG_LAUNCH(k_mlp_bwd<false>, dim3(nb), dim3(256), st, dH, dy, w_out, Z, Htop, WT, HT, Np, below, dZb, gpart,
+        SG_LAUNCH(k_mlp_bwd<false>, dim3(nb), dim3(256), st, dH, dy, w_out, Z, Htop, WT, H, Np, below, dZb, gpart,
                   colsum, colsum_out);
     return int(nb);
 }

@@ -12,17 +12,11 @@ constexpr int kFreq = 64;                    // Fourier frequencies: 2 x 64 = 12
 constexpr int kLayerStride = kHidden * kHidden + kHidden;   // W (out x in) then b
 constexpr int kOutOffset = kLayers * kLayerStride;          // w_out (128) then b_out
 constexpr int kNParams = kOutOffset + kHidden + 1;          // 66,177
-constexpr int kRowsPerBlock = 64;            // rows per workgroup of k_dsilu
 constexpr int kMaxPolyDegree = 8;
 
-int sg_gemm_nt(const uint16_t* A, int lda, const uint16_t* Bt, int ldb, float* C, int ldc, int M, int N,
-               int K, int ksplit, void* st);
 void sg_reduce_rows(const float* part, int P, int64_t L, float* out, void* st);
 void sg_loss(const float* y, const float* t, int64_t n, int64_t Np, float* dy, double* part, float* part_dy,
              void* st);
-void sg_dsilu(const float* dH, const float* dy, const float* w_out, const float* Z, const uint16_t* Htop,
-              int64_t Np, uint16_t* dZb, uint16_t* dZT, int64_t ldT, float* colsum, float* colsum_out,
-              void* st);
 // Device state of a training run: Adam step count so far and its value at
 // the start of the run (the minibatch index and the learning-rate schedule
 // are derived from them on the device, so one captured step graph is
@@ -42,18 +36,17 @@ void sg_infer(const double* pts, int64_t n, const double* B, const uint16_t* W, 
               const double* coef, const int8_t* mono, int nmono, double inv_r, double sigma, const double* add,
               double* out, void* st);
 // The forward pass of a training step in one launch: H_0..H_4 (row-major
-// [Np x 128] and transposed [128 x Np], BF16), Z_0..Z_3 (FP32) and y for the
-// first Np rows (rows >= n have zero features).
+// [Np x 128], BF16), Z_0..Z_3 (FP32) and y for the first Np rows (rows >= n
+// have zero features).
 void sg_forward_train(const double* pts, int64_t n, int64_t Np, const double* B, const uint16_t* W,
-                      const float* params, uint16_t* const* H, uint16_t* const* HT, float* const* Z, float* y,
-                      void* st);
+                      const float* params, uint16_t* const* H, float* const* Z, float* y, void* st);
 // One layer of the backward pass in one launch: BF16 dZ (to dZb), the
 // per-workgroup column sums of dZ (and, top layer, of dy H_top), dH of the
 // layer below written over dH (when `below`), and per-workgroup 128 x 128
 // partials of dW; returns the number of workgroups (partials).  Np is a
 // multiple of 32.
 int sg_backward_layer(bool top, float* dH, const float* dy, const float* w_out, const float* Z, const uint16_t* Htop,
-                      const uint16_t* WT, const uint16_t* HT, int64_t Np, bool below, uint16_t* dZb, float* gpart,
+                      const uint16_t* WT, const uint16_t* H, int64_t Np, bool below, uint16_t* dZb, float* gpart,
                       float* colsum, float* colsum_out, void* st);
 void sg_residual(const double* pts, const double* V, int64_t n, const double* coef, const int8_t* mono,
                  int nmono, double inv_r, double inv_sigma, float* t, void* st);
