@@ -93,6 +93,10 @@ typedef enum {
                                      sets the thread count (default: all cores). */
 #define ENV_NO_MERGE 0x8u         /* evaluate every pair on its own: no same-centre
                                      clusters (results agree to rounding) */
+#define ENV_HOST_PACK 0x20u       /* device handles: enumerate, screen, order and lay
+                                     out the pairs on the host (the packer of
+                                     ENV_BUILD_ONLY handles) instead of on the device;
+                                     the records are the same bit for bit */
 
 typedef struct {
     double xyz[3];     /* position, bohr */
@@ -147,7 +151,8 @@ typedef struct {
     int64_t n_clusters;           /* same-centre clusters (far fields merged per atom) */
     int64_t n_cluster_members;    /* pairs inside those clusters (counted in n_pairs too) */
     int32_t on_host;              /* 1 with ENV_FORCE_CPU: evaluation runs on host threads */
-    int32_t reserved;
+    int32_t pairs_built_on_device;/* 1 when the pairs were enumerated, screened, ordered
+                                     and laid out on the device (see env_potential_create) */
 } env_info;
 
 /* Default options: FP32C, current device, threshold 1e-12, no flags. */
@@ -155,8 +160,13 @@ void env_options_default(env_options* opts);
 
 /* Build the environment (paper Sec. II.B: nuclei {Z_beta, R_beta} plus the
  * electron density; Sec. III: uploaded once, read-only afterwards).
- * Builds the screened primitive-pair list with its Hermite densities on the
- * host, uploads it, and returns a handle in *out.
+ * The host validates the inputs and parses the density into shell blocks;
+ * for a device handle the device then enumerates every primitive pair of the
+ * nonzero blocks, screens it, orders the kept pairs, forms the same-centre
+ * clusters, writes the records and folds the density into them (ENV_HOST_PACK:
+ * the host does the pairs and the layout, the device the fold; same records
+ * bit for bit).  ENV_BUILD_ONLY and ENV_FORCE_CPU handles are built on the
+ * host entirely.  Returns the handle in *out.
  * Errors: ENV_E_ARG (NULL pointers, n < 0, non-finite input, exponent <= 0,
  * atom index out of range, nbf mismatch, P not symmetric, ENV_FORCE_CPU with
  * ENV_BUILD_ONLY), ENV_E_UNSUPPORTED (l > 2; ENV_NEUTRALIZE with density
@@ -404,6 +414,18 @@ env_status env_peak_probe(int32_t device, env_peak* out);
 env_status env_potential_export_pairs(const env_potential* h, int64_t cap, int32_t* L,
                                       int32_t* group, double* center, double* p,
                                       double* D);
+
+/* Copy of a device handle's record image for inspection (host buffers):
+ * the records (rec_words 4-byte words: pair records, cluster records and the
+ * clusters' member records of every fragment group) and the segment tables
+ * of the split factors 1, 2, 4, ..., 256, concatenated (seg_words 4-byte
+ * words, 8 per segment: L, count, first record word (int64), first and end
+ * nucleus, flags, 0).  Call with NULL buffers to get the sizes; a buffer
+ * smaller than the size (cap in words) gives ENV_E_ARG.  Waits for the
+ * device.  ENV_E_STATE for a host handle. */
+env_status env_potential_export_image(const env_potential* h, uint32_t* rec, int64_t rec_cap,
+                                      int64_t* rec_words, uint32_t* segs, int64_t seg_cap,
+                                      int64_t* seg_words);
 
 /* ------------------------------------------------------------------------
  * Learned surrogate of V inside the QM region (not in the paper: an addition

@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libenvpot.so")
 
 SOURCES = ["kernels.hip", "pairlist.cpp", "layout.cpp", "api.cpp", "batch.cpp", "surrogate.hip", "surrogate.cpp",
            "probe.hip", "cells.hip", "cells.cpp", "field.hip", "field.cpp",
-           "server.cpp", "update.hip", "update.cpp", "sortpts.hip", "hosteval.cpp", "noalloc.hip"]
+           "server.cpp", "update.hip", "update.cpp", "sortpts.hip", "hosteval.cpp", "noalloc.hip", "devbuild.hip"]
 
 HIP_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "devbuild_internal.h"
 #include "handle.h"
 #include "probe.h"
 #include "sort_internal.h"
@@ -174,7 +175,8 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
     else env_options_default(&opt);
     if (opt.precision != ENV_PREC_FP64 && opt.precision != ENV_PREC_FP32C) return ENV_E_ARG;
     if (opt.reserved[0] || opt.reserved[1] || opt.reserved[2]) return ENV_E_ARG;
-    if (opt.flags & ~(ENV_BUILD_ONLY | ENV_NEUTRALIZE | ENV_NO_SCREENING | ENV_NO_MERGE | ENV_FORCE_CPU))
+    if (opt.flags &
+        ~(ENV_BUILD_ONLY | ENV_NEUTRALIZE | ENV_NO_SCREENING | ENV_NO_MERGE | ENV_FORCE_CPU | ENV_HOST_PACK))
         return ENV_E_ARG;
     const bool force_cpu = (opt.flags & ENV_FORCE_CPU) != 0;
     if (force_cpu && (opt.flags & ENV_BUILD_ONLY)) return ENV_E_ARG;
@@ -214,29 +216,38 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
     bool fits = true;
     for (int32_t s = 0; s < n_shells && shells; ++s) fits = fits && shells[s].nprim <= 32767;
     src.device_fold = !build_only && fits;
-    try {
-        st = build_pair_list(nuclei, n_nuclei, shells, n_shells, P, opt, h->host, build_only ? nullptr : &src);
-    } catch (const std::bad_alloc&) {
-        st = ENV_E_NOMEM;
-    } catch (...) {
-        st = ENV_E_ARG;
-    }
+    const bool merge = (opt.flags & ENV_NO_MERGE) == 0;
+    // device handles also enumerate, screen, order and lay out their pairs on
+    // the device (the host parses the inputs into density blocks), unless
+    // ENV_HOST_PACK asks for the host packer
+    bool dev_build = src.device_fold && (opt.flags & ENV_HOST_PACK) == 0;
+    BlockPlan plan;
+    auto host_list = [&]() -> env_status {
+        try {
+            return build_pair_list(nuclei, n_nuclei, shells, n_shells, P, opt, h->host, build_only ? nullptr : &src,
+                                   dev_build ? &plan : nullptr);
+        } catch (const std::bad_alloc&) {
+            return ENV_E_NOMEM;
+        } catch (...) {
+            return ENV_E_ARG;
+        }
+    };
+    auto host_again = [&]() {  // the host packer after all
+        dev_build = false;
+        h->host = PairList();
+        const bool df = src.device_fold;
+        src = PairSources();
+        src.device_fold = df;
+        return host_list();
+    };
+    st = host_list();
+    if (st == ENV_OK && dev_build && !device_build_fits(plan, h->host, n_nuclei)) st = host_again();
     if (st != ENV_OK) {
         delete h;
         return st;
     }
-    lap("pair list");
-    const PairList& pl = h->host;
+    lap(dev_build ? "block plan" : "pair list");
     env_info& in = h->info;
-    in.nbf = pl.nbf;
-    in.n_nuclei = int32_t(pl.nuc.size() / 4);
-    in.n_groups = pl.n_groups;
-    in.n_pairs = int64_t(pl.L.size());
-    for (int L : pl.L) in.n_pairs_by_L[L]++;
-    in.n_pairs_unscreened = pl.n_unscreened;
-    in.electrons = pl.electrons;
-    in.nuclear_charge = pl.nuclear_charge;
-    in.screened_bound = pl.screened_bound;
     in.precision = h->precision;
 
     std::vector<float> t32;
@@ -252,15 +263,59 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
     const bool fp64 = h->precision == ENV_PREC_FP64;
     Layout lay;
     LayoutMap lmap;
-    try {
-        pack_layout(pl, fp64, h->bp, (opt.flags & ENV_NO_MERGE) == 0, lay, build_only ? nullptr : &lmap);
-    } catch (const std::bad_alloc&) {
-        delete h;
-        return ENV_E_NOMEM;
+    DevBuild db;
+    if (dev_build) {
+        {
+            DeviceGuard g(device);
+            try {
+                st = device_build(plan, src, h->host, fp64, h->bp, merge, db);
+            } catch (const std::bad_alloc&) {
+                st = ENV_E_NOMEM;
+            }
+        }
+        if (st == ENV_E_UNSUPPORTED) {  // cluster tables beyond 32-bit words: the host packer drops the clusters
+            free_device_build(db);
+            st = host_again();
+        }
+        if (st != ENV_OK) {
+            free_device_build(db);
+            delete h;
+            return st;
+        }
     }
-    lap("layout");
+    const PairList& pl = h->host;
+    in.nbf = pl.nbf;
+    in.n_nuclei = int32_t(pl.nuc.size() / 4);
+    in.n_groups = pl.n_groups;
+    in.nuclear_charge = pl.nuclear_charge;
+    in.electrons = pl.electrons;
+    if (dev_build) {
+        lay.base = db.base;
+        lay.unit_cost = db.unit_cost;
+        lay.n_clusters = db.n_clusters;
+        lay.n_members = db.n_members;
+        in.n_pairs = db.n_pairs;
+        for (int L = 0; L <= kLMax; ++L) in.n_pairs_by_L[L] = db.n_pairs_by_L[L];
+        in.n_pairs_unscreened = db.n_unscreened;
+        in.screened_bound = db.screened_bound;
+        h->host.group_pair_begin = db.group_pair_begin;
+        lap("device build");
+    } else {
+        in.n_pairs = int64_t(pl.L.size());
+        for (int L : pl.L) in.n_pairs_by_L[L]++;
+        in.n_pairs_unscreened = pl.n_unscreened;
+        in.screened_bound = pl.screened_bound;
+        try {
+            pack_layout(pl, fp64, h->bp, merge, lay, build_only ? nullptr : &lmap);
+        } catch (const std::bad_alloc&) {
+            delete h;
+            return ENV_E_NOMEM;
+        }
+        lap("layout");
+    }
     in.n_clusters = lay.n_clusters;
     in.n_cluster_members = lay.n_members;
+    in.pairs_built_on_device = dev_build ? 1 : 0;
     std::vector<Segment> allsegs;
     std::vector<int32_t> allsplit;
     for (int k = 0; k <= kMaxSplitLog2; ++k) {
@@ -294,7 +349,16 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, device) == hipSuccess) h->cu_count = prop.multiProcessorCount;
         h->on_device = true;
-        st = upload(rec, &h->d_rec, h->device_bytes);
+        h->rec_words = dev_build ? db.words : int64_t(rec.size());
+        h->n_segs_all = int64_t(allsegs.size());
+        if (dev_build) {
+            h->d_rec = db.d_rec;
+            db.d_rec = nullptr;
+            h->device_bytes += std::max<int64_t>(db.words, 1) * 4;
+            st = ENV_OK;
+        } else {
+            st = upload(rec, &h->d_rec, h->device_bytes);
+        }
         if (st == ENV_OK) st = upload(allsegs, &h->d_segs, h->device_bytes);
         if (st == ENV_OK) st = upload(allsplit, &h->d_split, h->device_bytes);
         if (st == ENV_OK) st = upload(pl.nuc, &h->d_nuc, h->device_bytes);
@@ -309,7 +373,8 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
         lap("upload");
         if (st == ENV_OK) {
             try {
-                h->upd = make_update_state(pl, src, lmap, &st);
+                h->upd = dev_build ? make_update_state_device(pl, src, db, &st)
+                                   : make_update_state(pl, src, lmap, &st);
             } catch (const std::bad_alloc&) {
                 st = ENV_E_NOMEM;
             }
@@ -321,6 +386,7 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
         if (st == ENV_OK && src.device_fold) st = env_potential_update_density(h, P, nullptr);
         lap("device fold");
     }
+    free_device_build(db);
     if (st != ENV_OK) {
         free_device(h);
         delete h;
@@ -529,6 +595,25 @@ env_status env_potential_export_pairs(const env_potential* h, int64_t cap, int32
         for (int64_t k = 0; k < n; ++k)
             std::copy(pl.D.begin() + pl.d_off[k], pl.D.begin() + pl.d_off[k + 1], D + 35 * k);
     }
+    return ENV_OK;
+}
+
+env_status env_potential_export_image(const env_potential* h, uint32_t* rec, int64_t rec_cap,
+                                      int64_t* rec_words, uint32_t* segs, int64_t seg_cap,
+                                      int64_t* seg_words) {
+    if (!h) return ENV_E_ARG;
+    if (!h->on_device) return ENV_E_STATE;
+    static_assert(sizeof(Segment) == 32, "8 words per segment");
+    const int64_t rw = h->rec_words, sw = 8 * h->n_segs_all;
+    if (rec_words) *rec_words = rw;
+    if (seg_words) *seg_words = sw;
+    if ((rec && rec_cap < rw) || (segs && seg_cap < sw)) return ENV_E_ARG;
+    DeviceGuard g(h->device);
+    if (hipDeviceSynchronize() != hipSuccess) return ENV_E_DEVICE;
+    if (rec && rw > 0 && hipMemcpy(rec, h->d_rec, size_t(rw) * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return ENV_E_DEVICE;
+    if (segs && sw > 0 && hipMemcpy(segs, h->d_segs, size_t(sw) * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return ENV_E_DEVICE;
     return ENV_OK;
 }
 

@@ -40,6 +40,8 @@ struct env_potential {
     void* d_boys_field = nullptr;       // Boys table of the field (one order more)
     envpot::FieldParams fp{};
     envpot::UpdateState* upd = nullptr;  // density update tables (device)
+    int64_t rec_words = 0;              // words of d_rec
+    int64_t n_segs_all = 0;             // segments of d_segs (every split factor)
     int64_t seg_off[envpot::kMaxSplitLog2 + 1] = {};    // per split factor 2^k: first segment
     int64_t split_off[envpot::kMaxSplitLog2 + 1] = {};  // per split factor 2^k: first offset
     int64_t device_bytes = 0;

@@ -16,13 +16,10 @@
 #include <utility>
 
 #include "envpot_internal.h"
+#include "screen_math.h"
 #include "update_internal.h"
 
 namespace envpot {
-
-namespace {
-
-constexpr double kPi = 3.14159265358979323846;
 
 // Estimated relative cost of one point-pair by L and of one point-nucleus.
 const double kCost32[kLMax + 1] = {1.0, 1.5, 2.6, 4.4, 7.5};
@@ -31,25 +28,19 @@ const double kCostNuc = 0.6;
 // Extra cost of a cluster per unit of member cost: the share of waves that
 // have some point inside the cluster's far-field radius.
 const double kClusterNearShare = 0.1;
-// Far-field radius bands per atom (log-uniform over the one-centre pairs);
-// ENVPOT_BANDS (1..8) overrides it for tuning.
-int radius_bands() {
-    const char* e = std::getenv("ENVPOT_BANDS");
-    const int v = e ? std::atoi(e) : 0;
-    return (v >= 1 && v <= 8) ? v : 4;
-}
+
+namespace {
 
 double pair_r2far(const PairList& pl, int64_t k, bool fp64, const BoysParams& bp) {
     const int L = pl.L[k];
-    if (fp64) return bp.tfar64[L] / pl.p[k];
-    return double(float(double(bp.tfar32[L]) / pl.p[k]));  // as stored in the record
+    return sm::rec_r2far(fp64 ? bp.tfar64[L] : double(bp.tfar32[L]), pl.p[k], fp64);  // as stored in the record
 }
 
 void append_pair(const PairList& pl, int64_t k, bool fp64, const BoysParams& bp, std::vector<uint32_t>& rec) {
     double h[35];
     const int L = pl.L[k], nc = kNComp[L];
     const double p = pl.p[k];
-    const double c1 = 2.0 * std::sqrt(p / kPi);
+    const double c1 = sm::rec_c1(p);
     const double* D = &pl.D[pl.d_off[k]];
     far_coefs(L, D, h);
     const size_t o = rec.size();
@@ -59,7 +50,7 @@ void append_pair(const PairList& pl, int64_t k, bool fp64, const BoysParams& bp,
         r[0] = pl.center[3 * k];
         r[1] = pl.center[3 * k + 1];
         r[2] = pl.center[3 * k + 2];
-        r[3] = bp.tfar64[L] / p;
+        r[3] = sm::rec_r2far(bp.tfar64[L], p, true);
         r[4] = p;
         r[5] = c1;
         for (int c = 0; c < nc; ++c) r[kRec64Head + c] = h[c];
@@ -71,7 +62,7 @@ void append_pair(const PairList& pl, int64_t k, bool fp64, const BoysParams& bp,
         r[1] = pl.center[3 * k + 1];
         r[2] = pl.center[3 * k + 2];
         float* f = reinterpret_cast<float*>(&rec[o + 6]);
-        f[0] = float(double(bp.tfar32[L]) / p);
+        f[0] = float(sm::rec_r2far(double(bp.tfar32[L]), p, false));
         f[1] = float(p);
         f[2] = float(c1);
         for (int c = 0; c < nc; ++c) f[3 + c] = float(h[c]);
@@ -98,7 +89,7 @@ struct GroupPack {
     int64_t n_clusters = 0, n_members = 0;
 };
 
-void pack_group(const PairList& pl, int g, bool fp64, const BoysParams& bp, bool merge, double lo, double band_w,
+void pack_group(const PairList& pl, int g, bool fp64, const BoysParams& bp, bool merge, const double* edges,
                 int bands, bool want_map, GroupPack& gp) {
     const double* w = fp64 ? kCost64 : kCost32;
     const int64_t b = pl.group_pair_begin[g], e = pl.group_pair_begin[g + 1];
@@ -108,8 +99,7 @@ void pack_group(const PairList& pl, int g, bool fp64, const BoysParams& bp, bool
         std::map<std::pair<int, int>, std::vector<int64_t>> by_key;  // (atom, band)
         for (int64_t k = b; k < e; ++k) {
             if (merge && pl.atom1[k] >= 0) {
-                const double v = std::log(pair_r2far(pl, k, fp64, bp));
-                const int band = std::min(bands - 1, std::max(0, int((v - lo) / band_w)));
+                const int band = sm::band_of(pair_r2far(pl, k, fp64, bp), edges, bands);
                 by_key[{pl.atom1[k], band}].push_back(k);
             } else {
                 ord.push_back(k);
@@ -204,7 +194,7 @@ void pack_group(const PairList& pl, int g, bool fp64, const BoysParams& bp, bool
                             for (int cc = 0; cc <= Lm - a - bb; ++cc, ++im)
                                 hsum[hermite_index(Lc, a, bb, cc)] += hm[im];
                 }
-                cost += w[Lc] + kClusterNearShare * mcost;
+                cost += sm::cluster_term(w[Lc], kClusterNearShare, mcost);
                 uint32_t mask = 0;
                 for (int L = 0; L <= kLMax; ++L) mask |= cnt[L] ? (1u << L) : 0u;
                 const int64_t k0 = c.members[0];
@@ -273,6 +263,21 @@ void pack_group(const PairList& pl, int g, bool fp64, const BoysParams& bp, bool
 
 }  // namespace
 
+int radius_bands() {
+    const char* e = std::getenv("ENVPOT_BANDS");
+    const int v = e ? std::atoi(e) : 0;
+    return (v >= 1 && v <= kMaxBands) ? v : 4;
+}
+
+void radius_band_edges(double vmin, double vmax, int bands, double* edges) {
+    // log-uniform bands between the smallest and the largest r2far
+    for (int j = 0; j < kMaxBands; ++j) edges[j] = 0.0;
+    if (!(vmin > 0.0) || !(vmax >= vmin) || !std::isfinite(vmax)) return;
+    const double lo = std::log(vmin), hi = std::log(vmax);
+    const double w = (hi > lo) ? (hi - lo) / bands : 1.0;
+    for (int j = 1; j < bands; ++j) edges[j] = std::exp(lo + j * w);
+}
+
 void pack_layout(const PairList& pl, bool fp64, const BoysParams& bp, bool merge, Layout& out) {
     pack_layout(pl, fp64, bp, merge, out, nullptr);
 }
@@ -285,18 +290,19 @@ void pack_layout(const PairList& pl, bool fp64, const BoysParams& bp, bool merge
     out.n_clusters = out.n_members = 0;
     const int64_t npairs = int64_t(pl.L.size());
 
-    // band edges of log(r2far) over all one-centre pairs
-    double lo = std::numeric_limits<double>::infinity(), hi = -lo;
+    // radius band edges over all one-centre pairs
+    double vmin = std::numeric_limits<double>::infinity(), vmax = -vmin;
     if (merge) {
         for (int64_t k = 0; k < npairs; ++k) {
             if (pl.atom1[k] < 0) continue;
-            const double v = std::log(pair_r2far(pl, k, fp64, bp));
-            lo = std::min(lo, v);
-            hi = std::max(hi, v);
+            const double v = pair_r2far(pl, k, fp64, bp);
+            vmin = std::min(vmin, v);
+            vmax = std::max(vmax, v);
         }
     }
     const int bands = radius_bands();
-    const double band_w = (hi > lo) ? (hi - lo) / bands : 1.0;
+    double edges[kMaxBands];
+    radius_band_edges(vmin, vmax, bands, edges);
 
     // groups in parallel, each with local offsets
     const int ng = pl.n_groups;
@@ -310,7 +316,7 @@ void pack_layout(const PairList& pl, bool fp64, const BoysParams& bp, bool merge
                 for (;;) {
                     const int g = next.fetch_add(1);
                     if (g >= ng) break;
-                    pack_group(pl, g, fp64, bp, merge, lo, band_w, bands, map != nullptr, packs[g]);
+                    pack_group(pl, g, fp64, bp, merge, edges, bands, map != nullptr, packs[g]);
                 }
             });
         for (auto& t : th) t.join();

@@ -18,10 +18,10 @@
 #include <cmath>
 #include <cstring>
 #include <thread>
-#include <unordered_map>
 #include <xmmintrin.h>
 
 #include "envpot_internal.h"
+#include "screen_math.h"
 #include "update_internal.h"
 
 namespace envpot {
@@ -93,7 +93,7 @@ void hermite_coefs(int li, int lj, double a, double b, double A, double B, Ecoef
 
 struct Block {   // one unordered shell pair I <= J with its density block
     int I, J;
-    double w[6][6];   // P_IJ x contraction scales x (2 if I != J)
+    int64_t woff;     // its weights P_IJ x contraction scales x (2 if I != J): nI x nJ from here
     double maxabs;
 };
 
@@ -140,7 +140,7 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
 env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
                            const env_shell* shells, int32_t n_shells,
                            const env_density* P, const env_options& opt, PairList& out,
-                           PairSources* src) {
+                           PairSources* src, BlockPlan* plan) {
     const char* tenv = std::getenv("ENVPOT_TIMING");
     const bool timing = tenv && *tenv && *tenv != '0';
     auto tlast = std::chrono::steady_clock::now();
@@ -228,35 +228,34 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
     }
 
     lap("validate, norms");
-    // density blocks of ordered shell pairs
-    std::unordered_map<uint64_t, int> bidx;
-    std::vector<std::array<double, 36>> raw;
+    // density blocks of ordered shell pairs, numbered in order of first
+    // touch; rows arrive in order, so the rows of one shell I are
+    // consecutive and slot[J] holds the block (I, J) while they last
+    std::vector<double> rawv;                // per block nI x nJ elements, row-major
+    std::vector<int64_t> roff;               // per block: first element in rawv
     std::vector<std::pair<int, int>> rawkey;
-    uint64_t last_key = ~uint64_t(0);
-    int last_k = -1;  // consecutive elements of a row mostly share a block
+    std::vector<int> slot(size_t(std::max(n_shells, 1)), -1), touched;
+    int cur_I = -1;
     auto put = [&](int mu, int nu, double v) -> bool {
         if (!finite(v)) return false;
         if (v == 0.0) return true;
         const int I = shell_of_bf[mu], J = shell_of_bf[nu];
-        const uint64_t key = (uint64_t(uint32_t(I)) << 32) | uint32_t(J);
-        int k;
-        if (key == last_key) {
-            k = last_k;
-        } else {
-            auto it = bidx.find(key);
-            if (it == bidx.end()) {
-                k = int(raw.size());
-                bidx.emplace(key, k);
-                raw.emplace_back();
-                raw.back().fill(0.0);
-                rawkey.emplace_back(I, J);
-            } else {
-                k = it->second;
-            }
-            last_key = key;
-            last_k = k;
+        if (I != cur_I) {
+            for (int j : touched) slot[j] = -1;
+            touched.clear();
+            cur_I = I;
         }
-        raw[k][(mu - bf0[I]) * 6 + (nu - bf0[J])] += v;
+        const int nJ = bf0[J + 1] - bf0[J];
+        int k = slot[J];
+        if (k < 0) {
+            k = int(rawkey.size());
+            roff.push_back(int64_t(rawv.size()));
+            rawv.resize(rawv.size() + size_t(bf0[I + 1] - bf0[I]) * size_t(nJ), 0.0);
+            rawkey.emplace_back(I, J);
+            slot[J] = k;
+            touched.push_back(J);
+        }
+        rawv[size_t(roff[k] + int64_t(mu - bf0[I]) * nJ + (nu - bf0[J]))] += v;
         return true;
     };
     if (P->format == ENV_DENSITY_DENSE) {
@@ -275,23 +274,35 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
         }
     }
     lap("density blocks");
-    // symmetry: block (I,J) must equal the transpose of block (J,I)
+    // symmetry: block (I,J) must equal the transpose of block (J,I); each
+    // shell's blocks sorted by partner shell for the lookup
+    std::vector<int64_t> rbeg(size_t(n_shells) + 1, 0);
+    for (const auto& key : rawkey) ++rbeg[size_t(key.first) + 1];
+    for (int sI = 0; sI < n_shells; ++sI) rbeg[sI + 1] += rbeg[sI];
+    std::vector<std::pair<int, int>> rlist(rawkey.size());  // (J, block), grouped by I
+    {
+        std::vector<int64_t> fill(rbeg.begin(), rbeg.end() - 1);
+        for (size_t k = 0; k < rawkey.size(); ++k) rlist[size_t(fill[rawkey[k].first]++)] = {rawkey[k].second, int(k)};
+        for (int sI = 0; sI < n_shells; ++sI) std::sort(rlist.begin() + rbeg[sI], rlist.begin() + rbeg[sI + 1]);
+    }
     auto blk = [&](int I, int J) -> const double* {
-        auto it = bidx.find((uint64_t(uint32_t(I)) << 32) | uint32_t(J));
-        return it == bidx.end() ? nullptr : raw[it->second].data();
+        const auto b = rlist.begin() + rbeg[I], e = rlist.begin() + rbeg[I + 1];
+        const auto it = std::lower_bound(b, e, std::make_pair(J, -1));
+        return (it != e && it->first == J) ? rawv.data() + roff[size_t(it->second)] : nullptr;
     };
     static const double zero36[36] = {0};
     std::vector<Block> blocks;
+    std::vector<double> bw;   // block weights, nI x nJ per block
     std::vector<int> block_group;
     for (size_t k = 0; k < rawkey.size(); ++k) {
         const int I = rawkey[k].first, J = rawkey[k].second;
-        const double* a = raw[k].data();
+        const double* a = rawv.data() + roff[k];
         const double* b = blk(J, I);
         if (!b) b = zero36;
         const int nI = ncart(shells[I].l), nJ = ncart(shells[J].l);
         for (int x = 0; x < nI; ++x)
             for (int y = 0; y < nJ; ++y) {
-                const double u = a[x * 6 + y], v = b[y * 6 + x];
+                const double u = a[x * nJ + y], v = b[y * nI + x];
                 if (std::fabs(u - v) > 1e-10 * (std::fabs(u) + std::fabs(v))) return ENV_E_ARG;
             }
         if (I > J) continue;
@@ -299,12 +310,14 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
         B.I = I;
         B.J = J;
         B.maxabs = 0.0;
-        std::memset(B.w, 0, sizeof(B.w));
+        B.woff = int64_t(bw.size());
+        bw.resize(bw.size() + size_t(nI) * size_t(nJ));
         const double f = (I == J) ? 1.0 : 2.0;
         for (int x = 0; x < nI; ++x)
             for (int y = 0; y < nJ; ++y) {
-                B.w[x][y] = f * a[x * 6 + y] * cscale[bf0[I] + x] * cscale[bf0[J] + y];
-                B.maxabs = std::max(B.maxabs, std::fabs(B.w[x][y]));
+                const double wv = f * a[x * nJ + y] * cscale[bf0[I] + x] * cscale[bf0[J] + y];
+                bw[size_t(B.woff + x * nJ + y)] = wv;
+                B.maxabs = std::max(B.maxabs, std::fabs(wv));
             }
         const int gI = group_of_atom(shells[I].atom), gJ = group_of_atom(shells[J].atom);
         blocks.push_back(B);
@@ -328,8 +341,87 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
     }
 
     lap("symmetry, grouping");
-    std::vector<GroupOut> gout(n_groups);
+    // nuclei by group (Z == 0 centres carry basis functions only)
+    std::vector<double> zg(n_groups, 0.0);
+    out.group_nuc_begin.assign(n_groups, 0);
+    out.group_nuc_end.assign(n_groups, 0);
+    for (int g = 0; g < n_frag_groups; ++g) {
+        out.group_nuc_begin[g] = int(out.nuc.size() / 4);
+        for (int a = 0; a < n_nuclei; ++a) {
+            if (group_of_atom(a) != g || nuclei[a].Z == 0.0) continue;
+            out.nuc.push_back(nuclei[a].xyz[0]);
+            out.nuc.push_back(nuclei[a].xyz[1]);
+            out.nuc.push_back(nuclei[a].xyz[2]);
+            out.nuc.push_back(nuclei[a].Z);
+            zg[g] += nuclei[a].Z;
+            out.nuclear_charge += nuclei[a].Z;
+        }
+        out.group_nuc_end[g] = int(out.nuc.size() / 4);
+    }
+    if (out.has_cross) {
+        out.group_nuc_begin[n_frag_groups] = out.group_nuc_end[n_frag_groups] = int(out.nuc.size() / 4);
+    }
+
+    lap("nuclei");
     const bool neutralize = (opt.flags & ENV_NEUTRALIZE) != 0;
+    // basis and blocks for the density update tables (and the device build)
+    auto fill_sources = [&]() {
+        src->neutralize = neutralize;
+        src->blk_I.resize(blocks.size());
+        src->blk_J.resize(blocks.size());
+        for (size_t k = 0; k < blocks.size(); ++k) {
+            src->blk_I[k] = blocks[k].I;
+            src->blk_J[k] = blocks[k].J;
+        }
+        src->shell_l.resize(n_shells);
+        src->shell_atom.resize(n_shells);
+        src->bf0.assign(bf0.begin(), bf0.end());
+        for (int s2 = 0; s2 < n_shells; ++s2) {
+            src->shell_l[s2] = shells[s2].l;
+            src->shell_atom[s2] = shells[s2].atom;
+        }
+        src->poff.assign(poff.begin(), poff.end());
+        src->noff.assign(noff.begin(), noff.end());
+        src->cscale = cscale;
+        src->cnorm = cnorm;
+        src->exps.resize(poff[n_shells]);
+        for (int s2 = 0; s2 < n_shells; ++s2)
+            for (int k = 0; k < shells[s2].nprim; ++k) src->exps[poff[s2] + k] = shells[s2].exponents[k];
+        src->atom_xyz.resize(3 * size_t(n_nuclei));
+        for (int a = 0; a < n_nuclei; ++a)
+            for (int c = 0; c < 3; ++c) src->atom_xyz[3 * size_t(a) + c] = nuclei[a].xyz[c];
+        src->group_charge = zg;
+    };
+    if (plan) {  // the device build takes over from here
+        if (!src) return ENV_E_ARG;
+        fill_sources();
+        *plan = BlockPlan();
+        plan->thr = thr;
+        plan->screen = screen;
+        plan->blk_maxabs.resize(blocks.size());
+        for (size_t k = 0; k < blocks.size(); ++k) plan->blk_maxabs[k] = blocks[k].maxabs;
+        plan->shell_nprim.resize(n_shells);
+        for (int s2 = 0; s2 < n_shells; ++s2) plan->shell_nprim[s2] = shells[s2].nprim;
+        plan->coefs.resize(poff[n_shells]);
+        plan->n0 = n0;
+        for (int s2 = 0; s2 < n_shells; ++s2)
+            for (int k = 0; k < shells[s2].nprim; ++k) plan->coefs[poff[s2] + k] = shells[s2].coefs[k];
+        int64_t u = 0;
+        for (int g = 0; g < n_groups; ++g)
+            for (int bk : gblocks[g]) {
+                const int64_t nI = shells[blocks[bk].I].nprim, nJ = shells[blocks[bk].J].nprim;
+                plan->enum_blk.push_back(bk);
+                plan->enum_group.push_back(g);
+                plan->enum_first.push_back(u);
+                u += blocks[bk].I == blocks[bk].J ? nI * (nI + 1) / 2 : nI * nJ;
+            }
+        plan->enum_first.push_back(u);
+        out.n_unscreened = u;
+        out.group_pair_begin.assign(n_groups + 1, 0);
+        lap("block plan");
+        return ENV_OK;
+    }
+    std::vector<GroupOut> gout(n_groups);
     // the fold into D (and the charges of screened-out pairs) is left to the
     // device: D stays zero here
     const bool device_fold = src && src->device_fold;
@@ -346,8 +438,7 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
             const double* Bc = nuclei[SJ.atom].xyz;
             const int lI = SI.l, lJ = SJ.l, L = lI + lJ, nc = kNComp[L];
             const int nI = ncart(lI), nJ = ncart(lJ);
-            const double rab2 = (A[0] - Bc[0]) * (A[0] - Bc[0]) + (A[1] - Bc[1]) * (A[1] - Bc[1]) +
-                                (A[2] - Bc[2]) * (A[2] - Bc[2]);
+            const double rab2 = sm::dist2(A, Bc);
             const bool one_centre = SI.atom == SJ.atom;
             int eI[6][3], eJ[6][3];
             for (int c = 0; c < nI; ++c) cart(lI, c, eI[c]);
@@ -356,14 +447,13 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
                 for (int ib = (B.I == B.J ? ia : 0); ib < SJ.nprim; ++ib) {
                     const double a = SI.exponents[ia], b = SJ.exponents[ib];
                     const double ca = SI.coefs[ia], cb = SJ.coefs[ib];
-                    const double p = a + b, mu = a * b / p;
+                    const double p = a + b;
                     const double w = (B.I == B.J && ia != ib) ? 2.0 : 1.0;
                     const double pp = kPi / p, pp32 = pp * std::sqrt(pp);
                     const double* na_c = &cnorm[noff[B.I] + int64_t(ia) * nI];  // c_a N_a per component
                     const double* nb_c = &cnorm[noff[B.J] + int64_t(ib) * nJ];
                     ++go.n_unscreened;
-                    const double bound = std::fabs(ca * cb) * n0[poff[B.I] + ia] * n0[poff[B.J] + ib] * pp32 *
-                                         std::exp(-mu * rab2);
+                    const double bound = sm::screen_bound(ca, cb, n0[poff[B.I] + ia], n0[poff[B.J] + ib], a, b, rab2);
                     const bool drop = screen && bound < thr;
                     if (drop) go.screened_bound += w * B.maxabs * bound;
                     if (drop && !neutralize) continue;
@@ -378,7 +468,7 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
                         double q = 0.0;
                         for (int x = 0; x < nI; ++x)
                             for (int y = 0; y < nJ; ++y)
-                                q += B.w[x][y] * na_c[x] * nb_c[y] * Ex.v[eI[x][0]][eJ[y][0]][0] *
+                                q += bw[size_t(B.woff + x * nJ + y)] * na_c[x] * nb_c[y] * Ex.v[eI[x][0]][eJ[y][0]][0] *
                                      Ey.v[eI[x][1]][eJ[y][1]][0] * Ez.v[eI[x][2]][eJ[y][2]][0];
                         go.dropped_charge += w * q * pp32;
                         continue;
@@ -386,7 +476,7 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
                     for (int k = 0; k < nc; ++k) D[k] = 0.0;
                     for (int x = 0; x < (device_fold ? 0 : nI); ++x) {
                         for (int y = 0; y < nJ; ++y) {
-                            const double pw = B.w[x][y];
+                            const double pw = bw[size_t(B.woff + x * nJ + y)];
                             if (pw == 0.0) continue;
                             const double f = w * pw * na_c[x] * nb_c[y];
                             const int ix = eI[x][0], jx = eJ[y][0], iy = eI[x][1], jy = eJ[y][1],
@@ -408,9 +498,9 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
                         bu.rec.push_back(A[1]);
                         bu.rec.push_back(A[2]);
                     } else {
-                        bu.rec.push_back((a * A[0] + b * Bc[0]) / p);
-                        bu.rec.push_back((a * A[1] + b * Bc[1]) / p);
-                        bu.rec.push_back((a * A[2] + b * Bc[2]) / p);
+                        bu.rec.push_back(sm::prod_centre(a, A[0], b, Bc[0], p));
+                        bu.rec.push_back(sm::prod_centre(a, A[1], b, Bc[1], p));
+                        bu.rec.push_back(sm::prod_centre(a, A[2], b, Bc[2], p));
                     }
                     bu.atom.push_back(one_centre ? SI.atom : -1);
                     if (src) bu.src.insert(bu.src.end(), {int32_t(bk), int32_t(ia), int32_t(ib)});
@@ -441,28 +531,6 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
     }
 
     lap("primitive pairs");
-    // nuclei by group (Z == 0 centres carry basis functions only)
-    std::vector<double> zg(n_groups, 0.0);
-    out.group_nuc_begin.assign(n_groups, 0);
-    out.group_nuc_end.assign(n_groups, 0);
-    for (int g = 0; g < n_frag_groups; ++g) {
-        out.group_nuc_begin[g] = int(out.nuc.size() / 4);
-        for (int a = 0; a < n_nuclei; ++a) {
-            if (group_of_atom(a) != g || nuclei[a].Z == 0.0) continue;
-            out.nuc.push_back(nuclei[a].xyz[0]);
-            out.nuc.push_back(nuclei[a].xyz[1]);
-            out.nuc.push_back(nuclei[a].xyz[2]);
-            out.nuc.push_back(nuclei[a].Z);
-            zg[g] += nuclei[a].Z;
-            out.nuclear_charge += nuclei[a].Z;
-        }
-        out.group_nuc_end[g] = int(out.nuc.size() / 4);
-    }
-    if (out.has_cross) {
-        out.group_nuc_begin[n_frag_groups] = out.group_nuc_end[n_frag_groups] = int(out.nuc.size() / 4);
-    }
-
-    lap("nuclei");
     // neutralise: scale the Hermite densities of each group so that its
     // electron count tr(P_f S_f) (screened-out pairs included) equals its
     // nuclear charge
@@ -561,13 +629,7 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
     }
     for (int g = 0; g < n_groups; ++g) out.electrons += qg[g];
     if (src) {
-        src->neutralize = neutralize;
-        src->blk_I.resize(blocks.size());
-        src->blk_J.resize(blocks.size());
-        for (size_t k = 0; k < blocks.size(); ++k) {
-            src->blk_I[k] = blocks[k].I;
-            src->blk_J[k] = blocks[k].J;
-        }
+        fill_sources();
         for (int g = 0; g < n_groups; ++g) {
             const std::vector<int32_t>& dr = gout[g].drop;
             for (size_t j = 0; j + 2 < dr.size(); j += 3) {
@@ -577,24 +639,6 @@ env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei,
                 src->drop_group.push_back(g);
             }
         }
-        src->shell_l.resize(n_shells);
-        src->shell_atom.resize(n_shells);
-        src->bf0.assign(bf0.begin(), bf0.end());
-        for (int s2 = 0; s2 < n_shells; ++s2) {
-            src->shell_l[s2] = shells[s2].l;
-            src->shell_atom[s2] = shells[s2].atom;
-        }
-        src->poff.assign(poff.begin(), poff.end());
-        src->noff.assign(noff.begin(), noff.end());
-        src->cscale = cscale;
-        src->cnorm = cnorm;
-        src->exps.resize(poff[n_shells]);
-        for (int s2 = 0; s2 < n_shells; ++s2)
-            for (int k = 0; k < shells[s2].nprim; ++k) src->exps[poff[s2] + k] = shells[s2].exponents[k];
-        src->atom_xyz.resize(3 * size_t(n_nuclei));
-        for (int a = 0; a < n_nuclei; ++a)
-            for (int c = 0; c < 3; ++c) src->atom_xyz[3 * size_t(a) + c] = nuclei[a].xyz[c];
-        src->group_charge = zg;
     }
     lap("order");
     return ENV_OK;

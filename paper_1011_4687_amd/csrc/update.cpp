@@ -13,6 +13,7 @@
 #include <new>
 #include <vector>
 
+#include "devbuild_internal.h"
 #include "handle.h"
 #include "update_internal.h"
 
@@ -61,35 +62,12 @@ void free_update_state(UpdateState* u) {
     delete u;
 }
 
-// Device tables of the update (on the current device).  Returns nullptr
-// when the input does not fit them (then updates are unsupported).
-UpdateState* make_update_state(const PairList& pl, const PairSources& src, const LayoutMap& map,
-                               env_status* st) {
-    *st = ENV_OK;
-    const int64_t n_pairs = int64_t(pl.L.size());
-    const int64_t n_drop = src.neutralize ? int64_t(src.drop_blk.size()) : 0;
-    if (int64_t(src.pair_blk.size()) != n_pairs || int64_t(map.pair_word.size()) != n_pairs) return nullptr;
-    std::vector<UpdPair> pairs(size_t(n_pairs + n_drop));
-    for (int64_t k = 0; k < n_pairs; ++k) {
-        if (src.pair_ia[k] > 32767 || src.pair_ib[k] > 32767 || map.pair_word[k] < 0) return nullptr;
-        UpdPair& q = pairs[k];
-        q.blk = src.pair_blk[k];
-        q.ia = int16_t(src.pair_ia[k]);
-        q.ib = int16_t(src.pair_ib[k]);
-        q.group = pl.group[k];
-        q.L = pl.L[k];
-        q.word = map.pair_word[k];
-    }
-    for (int64_t j = 0; j < n_drop; ++j) {
-        if (src.drop_ia[j] > 32767 || src.drop_ib[j] > 32767) return nullptr;
-        UpdPair& q = pairs[n_pairs + j];
-        q.blk = src.drop_blk[j];
-        q.ia = int16_t(src.drop_ia[j]);
-        q.ib = int16_t(src.drop_ib[j]);
-        q.group = src.drop_group[j];
-        q.L = 0;
-        q.word = -1;
-    }
+namespace {
+
+// The update tables that depend on the blocks and the basis only (both
+// builds): shells, blocks, far-field matrices, block weights and the
+// per-shell block lists; the caller attaches the pairs and clusters.
+UpdateState* block_state(const PairList& pl, const PairSources& src, env_status* st) {
     const int n_shells = int(src.shell_l.size());
     std::vector<UpdShell> shells(n_shells);
     for (int s = 0; s < n_shells; ++s) {
@@ -117,24 +95,11 @@ UpdateState* make_update_state(const PairList& pl, const PairSources& src, const
             for (int i = 0; i < nc; ++i) M[kFarMatOff[L] + i * nc + j] = h[i];
         }
     }
-    const int64_t n_clusters = int64_t(map.cl_word.size());
-    std::vector<UpdCluster> cl(static_cast<size_t>(n_clusters));
-    for (int64_t c = 0; c < n_clusters; ++c) {
-        cl[c].word = map.cl_word[c];
-        cl[c].begin = map.cl_begin[c];
-        cl[c].end = map.cl_begin[c + 1];
-        cl[c].L = map.cl_L[c];
-        cl[c].pad = 0;
-    }
     UpdateState* u = new (std::nothrow) UpdateState;
     if (!u) {
         *st = ENV_E_NOMEM;
         return nullptr;
     }
-    u->n_pairs = n_pairs;
-    u->n_drop = n_drop;
-    u->n_clusters = n_clusters;
-    u->n_members = int64_t(map.cl_members.size());
     u->n_groups = pl.n_groups;
     u->nbf = pl.nbf;
     u->n_shells = n_shells;
@@ -147,7 +112,6 @@ UpdateState* make_update_state(const PairList& pl, const PairSources& src, const
     u->cscale = src.cscale;
     u->group_charge = src.group_charge;
     u->group_pair_begin = pl.group_pair_begin;
-    u->drop_group.assign(src.drop_group.begin(), src.drop_group.begin() + n_drop);
     u->n_blocks = n_blocks;
     u->blk_I = src.blk_I;
     u->blk_J = src.blk_J;
@@ -173,22 +137,110 @@ UpdateState* make_update_state(const PairList& pl, const PairSources& src, const
             }
         }
     }
-    std::vector<int64_t> moff(map.cl_members.size() + 1, 0);
-    for (size_t m = 0; m < map.cl_members.size(); ++m) moff[m + 1] = moff[m] + kNComp[pl.L[map.cl_members[m]]];
-    env_status s = upload_vec(pairs, &u->d_pairs, u->device_bytes);
-    if (s == ENV_OK) s = upload_vec(shells, &u->d_shells, u->device_bytes);
+    env_status s = upload_vec(shells, &u->d_shells, u->device_bytes);
     if (s == ENV_OK) s = upload_vec(blk, &u->d_blk, u->device_bytes);
     if (s == ENV_OK) s = upload_vec(src.exps, &u->d_exps, u->device_bytes);
     if (s == ENV_OK) s = upload_vec(src.cnorm, &u->d_cnorm, u->device_bytes);
     if (s == ENV_OK) s = upload_vec(M, &u->d_M, u->device_bytes);
-    if (s == ENV_OK) s = upload_vec(cl, &u->d_clusters, u->device_bytes);
-    if (s == ENV_OK) s = upload_vec(map.cl_members, &u->d_members, u->device_bytes);
     if (s == ENV_OK) s = upload_vec(u->woff, &u->d_woff, u->device_bytes);
-    if (s == ENV_OK) s = upload_vec(moff, &u->d_moff, u->device_bytes);
-    if (s == ENV_OK) s = alloc_dev(size_t(moff.back()), &u->d_hm, u->device_bytes);
     if (s == ENV_OK) s = alloc_dev(size_t(u->woff.back()), &u->d_W, u->device_bytes);
     if (s == ENV_OK) s = alloc_dev(size_t(std::max(pl.n_groups, 1)), &u->d_scale, u->device_bytes);
+    if (s != ENV_OK) {
+        free_update_state(u);
+        *st = s;
+        return nullptr;
+    }
+    return u;
+}
+
+}  // namespace
+
+// Device tables of the update (on the current device) for a host-packed
+// pair list.  Returns nullptr when the input does not fit them (then
+// updates are unsupported).
+UpdateState* make_update_state(const PairList& pl, const PairSources& src, const LayoutMap& map,
+                               env_status* st) {
+    *st = ENV_OK;
+    const int64_t n_pairs = int64_t(pl.L.size());
+    const int64_t n_drop = src.neutralize ? int64_t(src.drop_blk.size()) : 0;
+    if (int64_t(src.pair_blk.size()) != n_pairs || int64_t(map.pair_word.size()) != n_pairs) return nullptr;
+    std::vector<UpdPair> pairs(size_t(n_pairs + n_drop));
+    for (int64_t k = 0; k < n_pairs; ++k) {
+        if (src.pair_ia[k] > 32767 || src.pair_ib[k] > 32767 || map.pair_word[k] < 0) return nullptr;
+        UpdPair& q = pairs[k];
+        q.blk = src.pair_blk[k];
+        q.ia = int16_t(src.pair_ia[k]);
+        q.ib = int16_t(src.pair_ib[k]);
+        q.group = pl.group[k];
+        q.L = pl.L[k];
+        q.word = map.pair_word[k];
+    }
+    for (int64_t j = 0; j < n_drop; ++j) {
+        if (src.drop_ia[j] > 32767 || src.drop_ib[j] > 32767) return nullptr;
+        UpdPair& q = pairs[n_pairs + j];
+        q.blk = src.drop_blk[j];
+        q.ia = int16_t(src.drop_ia[j]);
+        q.ib = int16_t(src.drop_ib[j]);
+        q.group = src.drop_group[j];
+        q.L = 0;
+        q.word = -1;
+    }
+    const int64_t n_clusters = int64_t(map.cl_word.size());
+    std::vector<UpdCluster> cl(static_cast<size_t>(n_clusters));
+    for (int64_t c = 0; c < n_clusters; ++c) {
+        cl[c].word = map.cl_word[c];
+        cl[c].begin = map.cl_begin[c];
+        cl[c].end = map.cl_begin[c + 1];
+        cl[c].L = map.cl_L[c];
+        cl[c].pad = 0;
+    }
+    std::vector<int64_t> moff(map.cl_members.size() + 1, 0);
+    for (size_t m = 0; m < map.cl_members.size(); ++m) moff[m + 1] = moff[m] + kNComp[pl.L[map.cl_members[m]]];
+    UpdateState* u = block_state(pl, src, st);
+    if (!u) return nullptr;
+    u->n_pairs = n_pairs;
+    u->n_drop = n_drop;
+    u->n_clusters = n_clusters;
+    u->n_members = int64_t(map.cl_members.size());
+    u->drop_group.assign(src.drop_group.begin(), src.drop_group.begin() + n_drop);
+    env_status s = upload_vec(pairs, &u->d_pairs, u->device_bytes);
+    if (s == ENV_OK) s = upload_vec(cl, &u->d_clusters, u->device_bytes);
+    if (s == ENV_OK) s = upload_vec(map.cl_members, &u->d_members, u->device_bytes);
+    if (s == ENV_OK) s = upload_vec(moff, &u->d_moff, u->device_bytes);
+    if (s == ENV_OK) s = alloc_dev(size_t(moff.back()), &u->d_hm, u->device_bytes);
     if (s == ENV_OK) s = alloc_dev(size_t(n_pairs + n_drop), &u->d_charge, u->device_bytes);
+    if (s != ENV_OK) {
+        free_update_state(u);
+        *st = s;
+        return nullptr;
+    }
+    return u;
+}
+
+// The same tables for a device-built pair list: the pair, cluster and member
+// tables the device build wrote are taken over (db's pointers are cleared).
+UpdateState* make_update_state_device(const PairList& meta, const PairSources& src, DevBuild& db,
+                                      env_status* st) {
+    *st = ENV_OK;
+    UpdateState* u = block_state(meta, src, st);
+    if (!u) return nullptr;
+    u->n_pairs = db.n_pairs;
+    u->n_drop = db.n_drop;
+    u->n_clusters = db.n_clusters;
+    u->n_members = db.n_members;
+    u->drop_group = db.drop_group;
+    u->d_pairs = db.d_pairs;
+    u->d_clusters = db.d_clusters;
+    u->d_members = db.d_members;
+    u->d_moff = db.d_moff;
+    db.d_pairs = nullptr;
+    db.d_clusters = nullptr;
+    db.d_members = nullptr;
+    db.d_moff = nullptr;
+    u->device_bytes += (db.n_pairs + db.n_drop) * int64_t(sizeof(UpdPair)) +
+                       db.n_clusters * int64_t(sizeof(UpdCluster)) + (2 * db.n_members + 1) * 8;
+    env_status s = alloc_dev(size_t(db.hm_words), &u->d_hm, u->device_bytes);
+    if (s == ENV_OK) s = alloc_dev(size_t(db.n_pairs + db.n_drop), &u->d_charge, u->device_bytes);
     if (s != ENV_OK) {
         free_update_state(u);
         *st = s;

@@ -43,12 +43,46 @@ struct LayoutMap {
     std::vector<int64_t> cl_members;  // pair indices, in merge order
 };
 
+// The enumeration plan of a build, from the host's parse of the inputs
+// (validation, density blocks, symmetry, fragment groups, nuclei): the
+// device build enumerates, screens and orders the primitive pairs from it.
+struct BlockPlan {
+    // enumerated blocks: groups ascending, the blocks of a group by (I, J);
+    // a block's primitive pairs in the order ia, then ib (ib >= ia when I == J)
+    std::vector<int32_t> enum_blk;    // block index (build order, as in PairSources)
+    std::vector<int32_t> enum_group;  // fragment group of the block
+    std::vector<int64_t> enum_first;  // first primitive pair of the block; last entry: the total
+    std::vector<double> blk_maxabs;   // per block: largest |weight|
+    std::vector<int32_t> shell_nprim; // per shell
+    std::vector<double> coefs, n0;    // per primitive: contraction coefficient, (2 alpha / pi)^{3/4}
+    double thr = 0.0;
+    bool screen = false;
+};
+
+// With plan != nullptr the build stops before the pairs: it fills plan, src
+// and the pair list's fields that do not depend on pairs (nbf, groups,
+// nuclei, n_unscreened) and leaves the pairs to the device build.
 env_status build_pair_list(const env_nucleus* nuclei, int32_t n_nuclei, const env_shell* shells,
                            int32_t n_shells, const env_density* P, const env_options& opt, PairList& out,
-                           PairSources* src);
+                           PairSources* src, BlockPlan* plan = nullptr);
 
 void pack_layout(const PairList& pl, bool fp64, const BoysParams& bp, bool merge, Layout& out,
                  LayoutMap* map);
+
+// Far-field radius bands of the same-centre clusters: the number of bands
+// (ENVPOT_BANDS, 1..kMaxBands, default 4) and their edges, log-uniform between
+// the smallest and the largest r2far of the one-centre pairs (edges[1] ..
+// edges[bands-1]; a pair's band is sm::band_of).
+constexpr int kMaxBands = 8;
+int radius_bands();
+void radius_band_edges(double vmin, double vmax, int bands, double* edges);
+
+// Estimated relative cost of one point-pair by L, of one point-nucleus, and
+// the share of a cluster's member cost that its segment is charged.
+extern const double kCost32[kLMax + 1];
+extern const double kCost64[kLMax + 1];
+extern const double kCostNuc;
+extern const double kClusterNearShare;
 
 // Device records of one pair and one cluster for the fold kernels.
 struct UpdPair {
@@ -136,6 +170,10 @@ constexpr int kFarMatOff[kLMax + 2] = {0, 1, 17, 117, 517, 1742};
 // nullptr with *st == ENV_OK when the input does not fit them.
 UpdateState* make_update_state(const PairList& pl, const PairSources& src, const LayoutMap& map,
                                env_status* st);
+struct DevBuild;
+// The same for a device-built pair list (takes over db's fold tables).
+UpdateState* make_update_state_device(const PairList& meta, const PairSources& src, DevBuild& db,
+                                      env_status* st);
 void free_update_state(UpdateState* u);
 
 int launch_update_charges(const UpdateArgs& a, void* stream);

@@ -33,6 +33,7 @@ ENV_NEUTRALIZE = 0x2
 ENV_NO_SCREENING = 0x4
 ENV_NO_MERGE = 0x8
 ENV_FORCE_CPU = 0x10
+ENV_HOST_PACK = 0x20
 
 ENV_DENSITY_DENSE = 0
 ENV_DENSITY_CSR = 1
@@ -73,7 +74,7 @@ class env_info(ctypes.Structure):
                 ("nuclear_charge", c_double), ("screened_bound", c_double),
                 ("device_bytes", c_int64), ("precision", c_int32),
                 ("built_on_device", c_int32), ("n_clusters", c_int64),
-                ("n_cluster_members", c_int64), ("on_host", c_int32), ("reserved", c_int32)]
+                ("n_cluster_members", c_int64), ("on_host", c_int32), ("pairs_built_on_device", c_int32)]
 
 
 class env_batch_stats(ctypes.Structure):
@@ -166,6 +167,9 @@ def lib():
                                                  POINTER(c_int32), POINTER(c_double),
                                                  POINTER(c_double), POINTER(c_double)]
         L.env_potential_export_pairs.restype = c_int32
+        L.env_potential_export_image.argtypes = [c_void_p, POINTER(c_uint32), c_int64, POINTER(c_int64),
+                                                 POINTER(c_uint32), c_int64, POINTER(c_int64)]
+        L.env_potential_export_image.restype = c_int32
         L.env_potential_destroy.argtypes = [c_void_p]
         L.env_potential_destroy.restype = None
         L.env_potential_autotune.argtypes = [c_void_p, c_void_p, c_int64, c_void_p]
@@ -383,7 +387,8 @@ class Environment:
     def __init__(self, xyz, Z, fragment, shells, P, precision: str = "fp32c",
                  device: int = -1, screen_threshold: float = 1e-12,
                  neutralize: bool = False, build_only: bool = False,
-                 screening: bool = True, merge: bool = True, force_cpu: bool = False):
+                 screening: bool = True, merge: bool = True, force_cpu: bool = False,
+                 host_pack: bool = False):
         self.handle = 0
         self.on_host = bool(force_cpu)
         xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
@@ -412,7 +417,7 @@ class Environment:
         opt.screen_threshold = float(screen_threshold)
         opt.flags = ((ENV_NEUTRALIZE if neutralize else 0) | (ENV_BUILD_ONLY if build_only else 0)
                      | (0 if screening else ENV_NO_SCREENING) | (0 if merge else ENV_NO_MERGE)
-                     | (ENV_FORCE_CPU if force_cpu else 0))
+                     | (ENV_FORCE_CPU if force_cpu else 0) | (ENV_HOST_PACK if host_pack else 0))
         self.precision = precision
         self.handle = env_potential_create(nuc, K, sh, len(shells), dens, opt)
         self._keep = None
@@ -460,6 +465,22 @@ class Environment:
         if st != ENV_OK:
             raise EnvError(st, "env_potential_export_pairs")
         return L[:n], g[:n], c[:n], p[:n], D[:n]
+
+    def export_image(self):
+        """(records, segments) of a device handle as uint32 arrays: the record
+        words and the segment tables of every split factor (8 words each)."""
+        rw, sw = c_int64(0), c_int64(0)
+        h = c_void_p(self.handle)
+        st = lib().env_potential_export_image(h, None, 0, ctypes.byref(rw), None, 0, ctypes.byref(sw))
+        if st != ENV_OK:
+            raise EnvError(st, "env_potential_export_image")
+        rec = np.zeros(max(rw.value, 1), dtype=np.uint32)
+        seg = np.zeros(max(sw.value, 1), dtype=np.uint32)
+        st = lib().env_potential_export_image(h, rec.ctypes.data_as(POINTER(c_uint32)), rec.size, ctypes.byref(rw),
+                                              seg.ctypes.data_as(POINTER(c_uint32)), seg.size, ctypes.byref(sw))
+        if st != ENV_OK:
+            raise EnvError(st, "env_potential_export_image")
+        return rec[:rw.value], seg[:sw.value]
 
     def eval_host(self, points) -> np.ndarray:
         """V at (n,3) host points of a handle built with force_cpu=True

@@ -1,0 +1,139 @@
+"""Pair list built on the device against the host packer (ENV_HOST_PACK):
+the same records and segment tables of every split factor bit for bit, the
+same counts, and bitwise-equal potentials, in both precisions, with and
+without same-centre clusters, screening and neutral scaling, with density
+between fragments, after a density update, and on the 5000-atom workload
+(where the create times of both builds are printed)."""
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+_cache = {}
+
+
+def _workload(name, n_points):
+    if name not in _cache:
+        from paper_1011_4687_amd import synth
+        _cache[name] = synth.workload(name, n_points=n_points)
+    return _cache[name]
+
+
+def _shells(env):
+    return [(s.atom, s.l, s.exponents, s.coefs) for s in env.shells]
+
+
+def _both(env, frag=None, P=None, **kw):
+    from paper_1011_4687_amd.envpot import Environment
+    frag = env.fragment if frag is None else frag
+    P = env.density_csr() if P is None else P
+    t0 = time.perf_counter()
+    A = Environment(env.xyz, env.Z, frag, _shells(env), P, **kw)
+    t1 = time.perf_counter()
+    B = Environment(env.xyz, env.Z, frag, _shells(env), P, host_pack=True, **kw)
+    t2 = time.perf_counter()
+    return A, B, t1 - t0, t2 - t1
+
+
+def _eval(E, pts):
+    import torch
+    v = E.eval(torch.from_numpy(np.ascontiguousarray(pts)).cuda())
+    torch.cuda.synchronize()
+    return v.cpu().numpy()
+
+
+def _same(A, B, pts=None):
+    ia, ib = A.info(), B.info()
+    assert ia["pairs_built_on_device"] == 1 and ib["pairs_built_on_device"] == 0
+    for f in ("n_pairs", "n_pairs_by_L", "n_pairs_unscreened", "n_clusters", "n_cluster_members", "n_segments",
+              "n_groups", "n_nuclei", "electrons", "nuclear_charge"):
+        assert ia[f] == ib[f], (f, ia[f], ib[f])
+    # a sum over the dropped pairs, in another order on the device
+    assert ia["screened_bound"] == pytest.approx(ib["screened_bound"], rel=1e-12, abs=1e-300)
+    ra, sa = A.export_image()
+    rb, sb = B.export_image()
+    assert ra.size == rb.size and sa.size == sb.size
+    bad = np.flatnonzero(ra != rb)
+    assert bad.size == 0, f"{bad.size} of {ra.size} record words differ, first at {bad[:8]}"
+    assert np.array_equal(sa, sb)
+    if pts is not None:
+        va, vb = _eval(A, pts), _eval(B, pts)
+        assert np.array_equal(va, vb)
+    return ia
+
+
+@pytest.mark.parametrize("precision", ["fp32c", "fp64"])
+@pytest.mark.parametrize("screening", [True, False])
+def test_tiny_device_build_equals_host_packer(precision, screening):
+    print(f"[devbuild] tiny {precision} screening={screening}", flush=True)
+    env, pts = _workload("tiny", 1024)
+    A, B, _, _ = _both(env, precision=precision, screening=screening, neutralize=True)
+    try:
+        _same(A, B, pts)
+    finally:
+        A.close()
+        B.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32c", "fp64"])
+@pytest.mark.parametrize("merge", [True, False])
+@pytest.mark.parametrize("neutralize", [True, False])
+def test_mid_device_build_equals_host_packer(precision, merge, neutralize):
+    print(f"[devbuild] mid {precision} merge={merge} neutralize={neutralize}", flush=True)
+    env, pts = _workload("mid", 8192)
+    A, B, ta, tb = _both(env, precision=precision, merge=merge, neutralize=neutralize)
+    try:
+        i = _same(A, B, pts)
+        if merge:
+            assert i["n_clusters"] > 0
+        print(f"[devbuild] mid create: device {ta * 1e3:.0f} ms, host packer {tb * 1e3:.0f} ms", flush=True)
+    finally:
+        A.close()
+        B.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32c", "fp64"])
+def test_density_between_fragments(precision):
+    """Two fragments and one unassigned atom under one density block: pairs
+    between fragments form the cross group."""
+    print(f"[devbuild] cross group {precision}", flush=True)
+    env, pts = _workload("tiny", 1024)
+    frag = np.array([0] * 5 + [1] * 6 + [-1], dtype=np.int32)
+    A, B, _, _ = _both(env, frag=frag, precision=precision)
+    try:
+        i = _same(A, B, pts)
+        assert i["n_groups"] == 4
+    finally:
+        A.close()
+        B.close()
+
+
+def test_same_after_density_update():
+    from oracle import oracle as O
+    print("[devbuild] mid fp32c after a density update", flush=True)
+    env, pts = _workload("mid", 8192)
+    rng = np.random.default_rng(5)
+    P2 = env.density_dense(O.neutral_scales(env) * rng.uniform(0.8, 1.2, env.n_fragments))
+    A, B, _, _ = _both(env, P=env.density_dense(), precision="fp32c")
+    try:
+        A.update_density(P2)
+        B.update_density(P2)
+        _same(A, B, pts)
+    finally:
+        A.close()
+        B.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32c", "fp64"])
+def test_large_device_build_equals_host_packer(precision):
+    print(f"[devbuild] large {precision}", flush=True)
+    env, pts = _workload("large", 65536)
+    A, B, ta, tb = _both(env, precision=precision, neutralize=True)
+    try:
+        _same(A, B, pts)
+        print(f"[devbuild] large {precision} create: device build {ta:.3f} s, host packer {tb:.3f} s", flush=True)
+    finally:
+        A.close()
+        B.close()
