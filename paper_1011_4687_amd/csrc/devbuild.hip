@@ -23,7 +23,10 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -449,6 +452,17 @@ void free_device_build(DevBuild& b) {
 env_status device_build(const BlockPlan& plan, const PairSources& src, const PairList& meta, bool fp64,
                         const BoysParams& bp, bool merge, DevBuild& out) {
     out = DevBuild();
+    const char* tenv = std::getenv("ENVPOT_TIMING");
+    const bool timing = tenv && *tenv && *tenv != '0';
+    auto tlast = std::chrono::steady_clock::now();
+    auto lap = [&](const char* what) {  // waits for the device when timing
+        if (!timing) return;
+        (void)hipDeviceSynchronize();
+        const auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[envpot device build] %-16s %8.3f ms\n", what,
+                     std::chrono::duration<double, std::milli>(now - tlast).count());
+        tlast = now;
+    };
     Arena ar;
     const int nG = meta.n_groups;
     const int64_t U = plan.enum_first.back();
@@ -525,6 +539,7 @@ env_status device_build(const BlockPlan& plan, const PairSources& src, const Pai
         DB_CHECK(hipMemcpy(&out.screened_bound, d_sb, sizeof(double), hipMemcpyDeviceToHost) == hipSuccess);
     }
     DB_LAUNCH(U, k_key_starts, key_s, U, pstart);
+    lap("upload, screen, sort");
     std::vector<int64_t> hstart;
     DB_CHECK(download(hstart, pstart, 5 * int64_t(nG) + 1));
     const std::vector<int64_t> pcount = counts_of(hstart, U);
@@ -561,6 +576,7 @@ env_status device_build(const BlockPlan& plan, const PairSources& src, const Pai
         for (int64_t j = 0; j < n_drop; ++j) out.drop_group[j] = dr[j].group;
     }
 
+    lap("pair data");
     // ---- 4. clusters
     DB_CHECK(hipMemset(in_cl, 0, size_t(std::max<int64_t>(n_pairs, 1))) == hipSuccess);
     DB_CHECK(hipMemset(memb_cnt, 0, 5 * size_t(std::max(nG, 1)) * sizeof(unsigned long long)) == hipSuccess);
@@ -648,6 +664,7 @@ env_status device_build(const BlockPlan& plan, const PairSources& src, const Pai
         DB_CHECK(download(ct, d_ct, nC) && download(cmw, d_cmw, nC) && download(cn, d_cn, nC));
     }
 
+    lap("clusters");
     // ---- 5. per-group layout on the host
     std::vector<unsigned long long> hmemb;
     DB_CHECK(download(hmemb, memb_cnt, 5 * int64_t(nG)));
@@ -726,6 +743,7 @@ env_status device_build(const BlockPlan& plan, const PairSources& src, const Pai
     out.n_clusters = nC;
     out.n_members = mpos[nC];
 
+    lap("group tables");
     // ---- 6. records and the density-fold tables
     uint32_t* rec = ar.alloc<uint32_t>(words);
     int64_t* d_ooff = ar.upload(ooff);
@@ -769,6 +787,7 @@ env_status device_build(const BlockPlan& plan, const PairSources& src, const Pai
                  hipSuccess);
     }
     DB_CHECK(hipDeviceSynchronize() == hipSuccess);
+    lap("records");
     out.d_rec = rec;
     out.d_pairs = upd;
     out.d_clusters = ucl;
