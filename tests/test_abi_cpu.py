@@ -121,6 +121,21 @@ def test_eval_requires_device_handle():
     assert ei.value.status == E.ENV_E_ARG
 
 
+def test_host_pack_flag_and_image_export_on_a_host_handle():
+    """ENV_HOST_PACK is accepted (a build-only handle is host-packed anyway,
+    with the same pairs); the record image exists only for device handles."""
+    env, shells = _tiny_args()
+    P = env.density_dense([1.0])
+    a = _build_only(env, shells, P)
+    b = _build_only(env, shells, P, host_pack=True)
+    assert a.info()["pairs_built_on_device"] == 0 == b.info()["pairs_built_on_device"]
+    for x, y in zip(a.export_pairs(), b.export_pairs()):
+        assert np.array_equal(x, y)
+    with pytest.raises(E.EnvError) as ei:
+        a.export_image()
+    assert ei.value.status == E.ENV_E_STATE
+
+
 def test_create_without_gpu_fails_loudly():
     import torch
     if torch.cuda.is_available():
