@@ -267,6 +267,7 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
         delete h;
         return ENV_E_DEVICE;
     }
+    lap("Boys tables");
     const bool fp64 = h->precision == ENV_PREC_FP64;
     Layout lay;
     LayoutMap lmap;
