@@ -33,6 +33,17 @@ __device__ __forceinline__ float rsqrt_refined(float x) {
     return __builtin_fmaf(0.5f * e, y, y);
 }
 
+// 1/sqrt(x) from v_rsq_f32 alone, for the FP32C far field.  Over its input
+// mantissas the instruction's relative error averages -7.36e-9 (-0.086 ulp;
+// measured on gfx950 over 2^24 log-uniform inputs in [1, 4), two binades,
+// which cover every pattern since rsq(4x) = rsq(x)/2); the error of a single
+// value stays below 0.87 ulp.  The far-field kernels remove the mean from
+// their FP64 tile sums (kRsqMeanFix), so what is left per term is the
+// zero-mean part of the error instead of a systematic bias times the sum of
+// the terms' magnitudes.
+constexpr double kRsqMeanFix = 1.0 + 7.36e-9;
+__device__ __forceinline__ float rsqrt_raw(float x) { return __builtin_amdgcn_rsqf(x); }
+
 // 1/sqrt(x) for finite x > 0 (far-field distances): v_rsq_f64 plus the
 // second-order correction y (1 + e/2 + 3e^2/8), e = 1 - x y^2, of the series
 // of (1 - e)^(-1/2).

@@ -209,7 +209,7 @@ __device__ __forceinline__ void pairs_f32(const GLB uint32_t* __restrict__ rec, 
                 if (__builtin_expect(__builtin_amdgcn_ballot_w64(m < cur.r2far) != 0, 0)) break;
 #pragma unroll
                 for (int k = 0; k < NP; ++k) {
-                    const float ri = rsqrt_refined(r2[k]);
+                    const float ri = rsqrt_raw(r2[k]);
                     const float w = ri * ri;
                     tile[k] = __builtin_fmaf(ri, far_value<L, float>(cur.h, X[k], Y[k], Z[k], w), tile[k]);
                 }
@@ -227,7 +227,7 @@ __device__ __forceinline__ void pairs_f32(const GLB uint32_t* __restrict__ rec, 
                 if (r2[k] < cur.r2far) {
                     nm |= 1u << k;
                 } else {
-                    const float ri = rsqrt_refined(r2[k]);
+                    const float ri = rsqrt_raw(r2[k]);
                     const float w = ri * ri;
                     tile[k] = __builtin_fmaf(ri, far_value<L, float>(cur.h, X[k], Y[k], Z[k], w), tile[k]);
                 }
@@ -256,7 +256,7 @@ __device__ __forceinline__ void pairs_f32(const GLB uint32_t* __restrict__ rec, 
             ++i;
         }
 #pragma unroll
-        for (int k = 0; k < NP; ++k) ele[k] += (double)tile[k];
+        for (int k = 0; k < NP; ++k) ele[k] = __builtin_fma((double)tile[k], kRsqMeanFix, ele[k]);
     }
 }
 
@@ -346,20 +346,20 @@ __device__ __forceinline__ int clusters_f32(const GLB uint32_t* __restrict__ rec
         if (__builtin_amdgcn_ballot_w64(nearp) != 0) break;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
-            const float ri = rsqrt_refined(r2[k]);
+            const float ri = rsqrt_raw(r2[k]);
             const float w = ri * ri;
             tile[k] = __builtin_fmaf(ri, far_value<LC, float>(h, X[k], Y[k], Z[k], w), tile[k]);
         }
         if ((++done & (kTile - 1)) == 0) {
 #pragma unroll
             for (int k = 0; k < NP; ++k) {
-                ele[k] += (double)tile[k];
+                ele[k] = __builtin_fma((double)tile[k], kRsqMeanFix, ele[k]);
                 tile[k] = 0.0f;
             }
         }
     }
 #pragma unroll
-    for (int k = 0; k < NP; ++k) ele[k] += (double)tile[k];
+    for (int k = 0; k < NP; ++k) ele[k] = __builtin_fma((double)tile[k], kRsqMeanFix, ele[k]);
     return i;
 }
 
