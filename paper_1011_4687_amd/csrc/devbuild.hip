@@ -410,10 +410,19 @@ struct Arena {
     }
 };
 
+// Copy n elements to the host after the stream's work so far.
 template <class T>
-bool download(std::vector<T>& v, const T* d, int64_t n) {
+bool download(std::vector<T>& v, const T* d, int64_t n, hipStream_t st) {
     v.resize(size_t(n));
-    return n == 0 || hipMemcpy(v.data(), d, size_t(n) * sizeof(T), hipMemcpyDeviceToHost) == hipSuccess;
+    if (n == 0) return true;
+    return hipMemcpyAsync(v.data(), d, size_t(n) * sizeof(T), hipMemcpyDeviceToHost, st) == hipSuccess &&
+           hipStreamSynchronize(st) == hipSuccess;
+}
+
+template <class T>
+bool download1(T* v, const T* d, hipStream_t st) {
+    return hipMemcpyAsync(v, d, sizeof(T), hipMemcpyDeviceToHost, st) == hipSuccess &&
+           hipStreamSynchronize(st) == hipSuccess;
 }
 
 #define DB_CHECK(x)                                  \
@@ -423,7 +432,7 @@ bool download(std::vector<T>& v, const T* d, int64_t n) {
 #define DB_LAUNCH(n, kern, ...)                                                                  \
     do {                                                                                         \
         if ((n) > 0) {                                                                           \
-            hipLaunchKernelGGL(kern, dim3(grid_of(n)), dim3(kBuildBlock), 0, nullptr, __VA_ARGS__); \
+            hipLaunchKernelGGL(kern, dim3(grid_of(n)), dim3(kBuildBlock), 0, st, __VA_ARGS__);      \
             if (hipGetLastError() != hipSuccess) return ENV_E_DEVICE;                            \
         }                                                                                        \
     } while (0)
@@ -452,18 +461,26 @@ void free_device_build(DevBuild& b) {
 env_status device_build(const BlockPlan& plan, const PairSources& src, const PairList& meta, bool fp64,
                         const BoysParams& bp, bool merge, DevBuild& out) {
     out = DevBuild();
+    Arena ar;
+    // the build's own stream (default priority): its work and copies wait
+    // for nothing else on the device, and nothing else waits for them
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return ENV_E_DEVICE;
+    struct StreamGuard {
+        hipStream_t s;
+        ~StreamGuard() { (void)hipStreamDestroy(s); }
+    } stream_guard{st};
     const char* tenv = std::getenv("ENVPOT_TIMING");
     const bool timing = tenv && *tenv && *tenv != '0';
     auto tlast = std::chrono::steady_clock::now();
     auto lap = [&](const char* what) {  // waits for the device when timing
         if (!timing) return;
-        (void)hipDeviceSynchronize();
+        (void)hipStreamSynchronize(st);
         const auto now = std::chrono::steady_clock::now();
         std::fprintf(stderr, "[envpot device build] %-16s %8.3f ms\n", what,
                      std::chrono::duration<double, std::milli>(now - tlast).count());
         tlast = now;
     };
-    Arena ar;
     const int nG = meta.n_groups;
     const int64_t U = plan.enum_first.back();
     const int64_t nE = int64_t(plan.enum_blk.size());
@@ -522,26 +539,27 @@ env_status device_build(const BlockPlan& plan, const PairSources& src, const Pai
     int64_t* pstart = ar.alloc<int64_t>(5 * int64_t(nG) + 1);
     if (!key || !val || !key_s || !val_s || !dropb || !d_sb || !pstart) return ENV_E_NOMEM;
     DB_LAUNCH(U, k_screen, a, key, val, dropb);
-    DB_CHECK(hipMemset(pstart, 0xff, (5 * size_t(nG) + 1) * sizeof(int64_t)) == hipSuccess);
+    DB_CHECK(hipMemsetAsync(pstart, 0xff, (5 * size_t(nG) + 1) * sizeof(int64_t), st) == hipSuccess);
     if (U > 0) {
         const int eb = end_bit_above(uint64_t(5) * nG);
         size_t tb = 0;
-        DB_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, key, key_s, val, val_s, int(U), 0, eb) ==
+        DB_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, key, key_s, val, val_s, int(U), 0, eb, st) ==
                  hipSuccess);
         void* tmp = ar.alloc<char>(int64_t(tb));
         if (!tmp) return ENV_E_NOMEM;
-        DB_CHECK(hipcub::DeviceRadixSort::SortPairs(tmp, tb, key, key_s, val, val_s, int(U), 0, eb) == hipSuccess);
+        DB_CHECK(hipcub::DeviceRadixSort::SortPairs(tmp, tb, key, key_s, val, val_s, int(U), 0, eb, st) ==
+                 hipSuccess);
         size_t tr = 0;
-        DB_CHECK(hipcub::DeviceReduce::Sum(nullptr, tr, dropb, d_sb, int(U)) == hipSuccess);
+        DB_CHECK(hipcub::DeviceReduce::Sum(nullptr, tr, dropb, d_sb, int(U), st) == hipSuccess);
         void* tmp2 = ar.alloc<char>(int64_t(tr));
         if (!tmp2) return ENV_E_NOMEM;
-        DB_CHECK(hipcub::DeviceReduce::Sum(tmp2, tr, dropb, d_sb, int(U)) == hipSuccess);
-        DB_CHECK(hipMemcpy(&out.screened_bound, d_sb, sizeof(double), hipMemcpyDeviceToHost) == hipSuccess);
+        DB_CHECK(hipcub::DeviceReduce::Sum(tmp2, tr, dropb, d_sb, int(U), st) == hipSuccess);
+        DB_CHECK(download1(&out.screened_bound, d_sb, st));
     }
     DB_LAUNCH(U, k_key_starts, key_s, U, pstart);
     lap("upload, screen, sort");
     std::vector<int64_t> hstart;
-    DB_CHECK(download(hstart, pstart, 5 * int64_t(nG) + 1));
+    DB_CHECK(download(hstart, pstart, 5 * int64_t(nG) + 1, st));
     const std::vector<int64_t> pcount = counts_of(hstart, U);
     const int64_t n_dropped = pcount[5 * size_t(nG)];
     const int64_t n_pairs = U - n_dropped;
@@ -571,15 +589,15 @@ env_status device_build(const BlockPlan& plan, const PairSources& src, const Pai
     DB_LAUNCH(n_pairs + n_drop, k_pairs, a, val_s, n_pairs, n_pairs + n_drop, pc, pp, pL, pg, patom, pr2, upd);
     if (n_drop > 0) {
         std::vector<UpdPair> dr;
-        DB_CHECK(download(dr, upd + n_pairs, n_drop));
+        DB_CHECK(download(dr, upd + n_pairs, n_drop, st));
         out.drop_group.resize(size_t(n_drop));
         for (int64_t j = 0; j < n_drop; ++j) out.drop_group[j] = dr[j].group;
     }
 
     lap("pair data");
     // ---- 4. clusters
-    DB_CHECK(hipMemset(in_cl, 0, size_t(std::max<int64_t>(n_pairs, 1))) == hipSuccess);
-    DB_CHECK(hipMemset(memb_cnt, 0, 5 * size_t(std::max(nG, 1)) * sizeof(unsigned long long)) == hipSuccess);
+    DB_CHECK(hipMemsetAsync(in_cl, 0, size_t(std::max<int64_t>(n_pairs, 1)), st) == hipSuccess);
+    DB_CHECK(hipMemsetAsync(memb_cnt, 0, 5 * size_t(std::max(nG, 1)) * sizeof(unsigned long long), st) == hipSuccess);
     int64_t n1 = 0, nr = 0, nC = 0;
     uint32_t* cval_s = nullptr;
     int64_t* rstart = nullptr;
@@ -592,12 +610,13 @@ env_status device_build(const BlockPlan& plan, const PairSources& src, const Pai
         unsigned long long* mm = ar.alloc<unsigned long long>(3);
         if (!mm) return ENV_E_NOMEM;
         const unsigned long long init[3] = {~0ull, 0ull, 0ull};
-        DB_CHECK(hipMemcpy(mm, init, sizeof(init), hipMemcpyHostToDevice) == hipSuccess);
+        DB_CHECK(hipMemcpyAsync(mm, init, sizeof(init), hipMemcpyHostToDevice, st) == hipSuccess);
         hipLaunchKernelGGL(k_r2_range, dim3(std::min<unsigned>(grid_of(n_pairs), 2048u)), dim3(kBuildBlock), 0,
-                           nullptr, patom, pr2, n_pairs, mm);
+                           st, patom, pr2, n_pairs, mm);
         DB_CHECK(hipGetLastError() == hipSuccess);
         unsigned long long hm[3];
-        DB_CHECK(hipMemcpy(hm, mm, sizeof(hm), hipMemcpyDeviceToHost) == hipSuccess);
+        DB_CHECK(hipMemcpyAsync(hm, mm, sizeof(hm), hipMemcpyDeviceToHost, st) == hipSuccess &&
+                 hipStreamSynchronize(st) == hipSuccess);
         n1 = int64_t(hm[2]);
         if (n1 > 0) {
             double vmin, vmax;
@@ -619,20 +638,20 @@ env_status device_build(const BlockPlan& plan, const PairSources& src, const Pai
         DB_LAUNCH(n_pairs, k_cluster_keys, a, patom, pr2, n_pairs, ck, cv);
         const int eb = end_bit_above(uint64_t(n_atoms) * 8ull);
         size_t tb = 0;
-        DB_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, ck, ck_s, cv, cval_s, int(n_pairs), 0, eb) ==
+        DB_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, ck, ck_s, cv, cval_s, int(n_pairs), 0, eb, st) ==
                  hipSuccess);
         void* tmp = ar.alloc<char>(int64_t(tb));
         if (!tmp) return ENV_E_NOMEM;
-        DB_CHECK(hipcub::DeviceRadixSort::SortPairs(tmp, tb, ck, ck_s, cv, cval_s, int(n_pairs), 0, eb) ==
+        DB_CHECK(hipcub::DeviceRadixSort::SortPairs(tmp, tb, ck, ck_s, cv, cval_s, int(n_pairs), 0, eb, st) ==
                  hipSuccess);
         DB_LAUNCH(n1, k_heads, ck_s, n1, head);
         size_t ts = 0;
-        DB_CHECK(hipcub::DeviceScan::ExclusiveSum(nullptr, ts, head, runid, int(n1)) == hipSuccess);
+        DB_CHECK(hipcub::DeviceScan::ExclusiveSum(nullptr, ts, head, runid, int(n1), st) == hipSuccess);
         void* tmp2 = ar.alloc<char>(int64_t(ts));
         if (!tmp2) return ENV_E_NOMEM;
-        DB_CHECK(hipcub::DeviceScan::ExclusiveSum(tmp2, ts, head, runid, int(n1)) == hipSuccess);
+        DB_CHECK(hipcub::DeviceScan::ExclusiveSum(tmp2, ts, head, runid, int(n1), st) == hipSuccess);
         DB_LAUNCH(n1, k_run_begin, head, runid, n1, rstart, d_nr);
-        DB_CHECK(hipMemcpy(&nr, d_nr, sizeof(int64_t), hipMemcpyDeviceToHost) == hipSuccess);
+        DB_CHECK(download1(&nr, d_nr, st));
 
         uint32_t* rkey = ar.alloc<uint32_t>(nr);
         uint32_t* rval = ar.alloc<uint32_t>(nr);
@@ -646,28 +665,28 @@ env_status device_build(const BlockPlan& plan, const PairSources& src, const Pai
         DB_LAUNCH(nr, k_runs, a, rstart, cval_s, nr, pL, pg, rkey, rval, rterm, rmw, rn, in_cl, memb_cnt);
         const int eb2 = end_bit_above(uint64_t(8) * nG);
         size_t tb2 = 0;
-        DB_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb2, rkey, rkey_s, rval, cl_run, int(nr), 0, eb2) ==
-                 hipSuccess);
+        DB_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb2, rkey, rkey_s, rval, cl_run, int(nr), 0, eb2,
+                                                    st) == hipSuccess);
         void* tmp3 = ar.alloc<char>(int64_t(tb2));
         if (!tmp3) return ENV_E_NOMEM;
-        DB_CHECK(hipcub::DeviceRadixSort::SortPairs(tmp3, tb2, rkey, rkey_s, rval, cl_run, int(nr), 0, eb2) ==
-                 hipSuccess);
-        DB_CHECK(hipMemset(cstart, 0xff, (8 * size_t(nG) + 1) * sizeof(int64_t)) == hipSuccess);
+        DB_CHECK(hipcub::DeviceRadixSort::SortPairs(tmp3, tb2, rkey, rkey_s, rval, cl_run, int(nr), 0, eb2,
+                                                    st) == hipSuccess);
+        DB_CHECK(hipMemsetAsync(cstart, 0xff, (8 * size_t(nG) + 1) * sizeof(int64_t), st) == hipSuccess);
         DB_LAUNCH(nr, k_key_starts, rkey_s, nr, cstart);
-        DB_CHECK(download(hcstart, cstart, 8 * int64_t(nG) + 1));
+        DB_CHECK(download(hcstart, cstart, 8 * int64_t(nG) + 1, st));
         nC = hcstart[8 * size_t(nG)] >= 0 ? hcstart[8 * size_t(nG)] : nr;
         double* d_ct = ar.alloc<double>(nC);
         int64_t* d_cmw = ar.alloc<int64_t>(nC);
         int32_t* d_cn = ar.alloc<int32_t>(nC);
         if (!d_ct || !d_cmw || !d_cn) return ENV_E_NOMEM;
         DB_LAUNCH(nC, k_gather_runs, cl_run, nC, rterm, rmw, rn, d_ct, d_cmw, d_cn);
-        DB_CHECK(download(ct, d_ct, nC) && download(cmw, d_cmw, nC) && download(cn, d_cn, nC));
+        DB_CHECK(download(ct, d_ct, nC, st) && download(cmw, d_cmw, nC, st) && download(cn, d_cn, nC, st));
     }
 
     lap("clusters");
     // ---- 5. per-group layout on the host
     std::vector<unsigned long long> hmemb;
-    DB_CHECK(download(hmemb, memb_cnt, 5 * int64_t(nG)));
+    DB_CHECK(download(hmemb, memb_cnt, 5 * int64_t(nG), st));
     const std::vector<int64_t> ccount = nC > 0 ? counts_of(hcstart, nr) : std::vector<int64_t>(8 * size_t(nG) + 1, 0);
     std::vector<int64_t> ooff(5 * size_t(nG), 0), cword(size_t(nC), 0), mbase(size_t(nC), 0),
         mpos(size_t(nC) + 1, 0);
@@ -751,17 +770,17 @@ env_status device_build(const BlockPlan& plan, const PairSources& src, const Pai
     int64_t* members = ar.alloc<int64_t>(out.n_members);
     int64_t* moff = ar.alloc<int64_t>(out.n_members + 1);
     if (!rec || !d_ooff || !ucl || !members || !moff) return ENV_E_NOMEM;
-    DB_CHECK(hipMemset(rec, 0, size_t(std::max<int64_t>(words, 1)) * 4) == hipSuccess);
+    DB_CHECK(hipMemsetAsync(rec, 0, size_t(std::max<int64_t>(words, 1)) * 4, st) == hipSuccess);
     if (n_pairs > 0) {
         int32_t* f = ar.alloc<int32_t>(n_pairs);
         int32_t* orank = ar.alloc<int32_t>(n_pairs);
         if (!f || !orank) return ENV_E_NOMEM;
         DB_LAUNCH(n_pairs, k_not_in_cluster, in_cl, n_pairs, f);
         size_t ts = 0;
-        DB_CHECK(hipcub::DeviceScan::ExclusiveSum(nullptr, ts, f, orank, int(n_pairs)) == hipSuccess);
+        DB_CHECK(hipcub::DeviceScan::ExclusiveSum(nullptr, ts, f, orank, int(n_pairs), st) == hipSuccess);
         void* tmp = ar.alloc<char>(int64_t(ts));
         if (!tmp) return ENV_E_NOMEM;
-        DB_CHECK(hipcub::DeviceScan::ExclusiveSum(tmp, ts, f, orank, int(n_pairs)) == hipSuccess);
+        DB_CHECK(hipcub::DeviceScan::ExclusiveSum(tmp, ts, f, orank, int(n_pairs), st) == hipSuccess);
         DB_LAUNCH(n_pairs, k_place_pairs, pL, pg, in_cl, orank, pstart, d_ooff, n_pairs, a.fp64, upd);
     }
     if (nC > 0) {
@@ -773,20 +792,21 @@ env_status device_build(const BlockPlan& plan, const PairSources& src, const Pai
                   upd, members, ucl, rec, words);
     }
     DB_LAUNCH(n_pairs, k_pair_records, upd, pc, pp, pr2, pL, n_pairs, a.fp64, rec, words);
-    DB_CHECK(hipMemset(moff, 0, sizeof(int64_t)) == hipSuccess);
+    DB_CHECK(hipMemsetAsync(moff, 0, sizeof(int64_t), st) == hipSuccess);
     if (out.n_members > 0) {
         int64_t* sz = ar.alloc<int64_t>(out.n_members);
         if (!sz) return ENV_E_NOMEM;
         DB_LAUNCH(out.n_members, k_member_sizes, members, pL, out.n_members, sz);
         size_t ts = 0;
-        DB_CHECK(hipcub::DeviceScan::InclusiveSum(nullptr, ts, sz, moff + 1, int(out.n_members)) == hipSuccess);
+        DB_CHECK(hipcub::DeviceScan::InclusiveSum(nullptr, ts, sz, moff + 1, int(out.n_members), st) ==
+                 hipSuccess);
         void* tmp = ar.alloc<char>(int64_t(ts));
         if (!tmp) return ENV_E_NOMEM;
-        DB_CHECK(hipcub::DeviceScan::InclusiveSum(tmp, ts, sz, moff + 1, int(out.n_members)) == hipSuccess);
-        DB_CHECK(hipMemcpy(&out.hm_words, moff + out.n_members, sizeof(int64_t), hipMemcpyDeviceToHost) ==
+        DB_CHECK(hipcub::DeviceScan::InclusiveSum(tmp, ts, sz, moff + 1, int(out.n_members), st) ==
                  hipSuccess);
+        DB_CHECK(download1(&out.hm_words, moff + out.n_members, st));
     }
-    DB_CHECK(hipDeviceSynchronize() == hipSuccess);
+    DB_CHECK(hipStreamSynchronize(st) == hipSuccess);
     lap("records");
     out.d_rec = rec;
     out.d_pairs = upd;

@@ -137,3 +137,37 @@ def test_large_device_build_equals_host_packer(precision):
     finally:
         A.close()
         B.close()
+
+
+@pytest.mark.parametrize("case", ["zero_density", "all_screened", "all_screened_neutral", "one_atom"])
+def test_degenerate_builds(case):
+    """No density at all (nuclei only), every pair screened out (with and
+    without the neutral scaling, which still counts the dropped charges),
+    and a single atom: the device build equals the host packer's."""
+    print(f"[devbuild] degenerate {case}", flush=True)
+    env, pts = _workload("tiny", 1024)
+    kw = {"precision": "fp64"}
+    frag, P = None, None
+    if case == "zero_density":
+        P = np.zeros((env.nbf, env.nbf))
+    elif case.startswith("all_screened"):
+        kw["screen_threshold"] = 1e30
+        kw["neutralize"] = case.endswith("neutral")
+    if case == "one_atom":
+        from paper_1011_4687_amd.envpot import Environment
+        sh = [(0, l, ex, co) for (a, l, ex, co) in _shells(env) if a == 0]
+        nb = sum((l + 1) * (l + 2) // 2 for (_, l, _, _) in sh)
+        rng = np.random.default_rng(7)
+        C = rng.normal(size=(nb, 2))
+        P1 = C @ C.T
+        A = Environment(env.xyz[:1], env.Z[:1], np.zeros(1, np.int32), sh, P1, **kw)
+        B = Environment(env.xyz[:1], env.Z[:1], np.zeros(1, np.int32), sh, P1, host_pack=True, **kw)
+    else:
+        A, B, _, _ = _both(env, frag=frag, P=P, **kw)
+    try:
+        i = _same(A, B, pts)
+        if case != "one_atom":
+            assert i["n_pairs"] == 0
+    finally:
+        A.close()
+        B.close()
