@@ -448,9 +448,27 @@ def cells_leg(args, torch, envpot, synth):
                     one.item()
                 r[f"single_point_mode{mode}_us"] = e0.elapsed_time(e1) * 1e3 / k
                 r[f"single_point_mode{mode}_roundtrip_us"] = (time.perf_counter() - t0) * 1e6 / kk
+                # resident kernel: host position in, host V out, no launch per move
+                # (the time includes the Python call into the library)
+                E.resident_start(mode=mode, idle_s=10.0)
+                hp = pts[:kk]
+                for j in range(32):
+                    E.resident_eval(hp[j])
+                t0 = time.perf_counter()
+                vres = [E.resident_eval(hp[j]) for j in range(kk)]
+                r[f"resident_mode{mode}_roundtrip_us"] = (time.perf_counter() - t0) * 1e6 / kk
+                E.resident_stop()
+                same = []
+                for j in range(8):
+                    p1.copy_(host[j])
+                    E.eval_single(p1, one, mode=mode)
+                    same.append(one.item() == vres[j])
+                r[f"resident_mode{mode}_equals_single"] = bool(all(same))
             rep[prec] = r
             log(f"[bench] cells {prec}: {ms:.3f} ms per {n} points; one point "
-                f"{r['single_point_mode0_us']:.1f} / {r['single_point_mode1_us']:.1f} us; "
+                f"{r['single_point_mode0_us']:.1f} / {r['single_point_mode1_us']:.1f} us per launch, "
+                f"host round trip {r['single_point_mode0_roundtrip_us']:.1f} us, resident "
+                f"{r['resident_mode0_roundtrip_us']:.1f} / {r['resident_mode1_roundtrip_us']:.1f} us; "
                 f"{r['accuracy_vs_oracle_16']}")
             E.close()
     torch.cuda.synchronize()

@@ -619,6 +619,31 @@ env_status env_cells_eval(env_cells* h, const double* points, int64_t n, double*
 env_status env_cells_eval_single(env_cells* h, const double* point, double* out, int32_t mode,
                                  void* stream);
 
+/* Resident single-point mode (the same moves without a launch or a copy call
+ * per move): one kernel stays on the GPU with the workgroups of `mode` (as
+ * in env_cells_eval_single) and takes positions from a mailbox in pinned
+ * host memory; the host writes a position and waits for V, which the last
+ * workgroup of the round writes back.  Same decomposition and fixed-order
+ * sums as env_cells_eval_single, so the values are equal bit for bit.
+ *   start: launch the kernel on a stream of the library's own (ENV_OK at
+ *     once when it already runs with this mode and idle_s); the kernel
+ *     exits by itself after idle_s seconds (0 < idle_s <= 3600) without a
+ *     position, so one that is never stopped still ends;
+ *   eval:  point and out are host pointers; returns when out is written
+ *     (a kernel that left for lack of positions is launched again first);
+ *     ENV_E_STATE before start, ENV_E_DEVICE when V does not arrive within
+ *     timeout_s seconds (the kernel is then stopped);
+ *   stop:  ask the kernel to exit and wait for it (env_cells_destroy does
+ *     this too).
+ * While the kernel runs it occupies its workgroups' compute units and
+ * every other call on the device shares the rest.  Calls on one handle
+ * must not overlap.
+ * Errors: ENV_E_ARG (NULL, bad mode, idle_s or timeout_s), ENV_E_NOMEM,
+ * ENV_E_DEVICE. */
+env_status env_cells_resident_start(env_cells* h, int32_t mode, double idle_s);
+env_status env_cells_resident_eval(env_cells* h, const double* point, double* out, double timeout_s);
+env_status env_cells_resident_stop(env_cells* h);
+
 void env_cells_destroy(env_cells* h);
 
 void env_potential_destroy(env_potential* h);

@@ -3,11 +3,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
+#include <xmmintrin.h>
 
 #include "cells_internal.h"
 #include "envpot_internal.h"
@@ -26,19 +29,85 @@ struct env_cells {
     double* d_part = nullptr;      // single-point mode: one partial per workgroup
     unsigned int* d_ticket = nullptr;
     int one_grid = 128;            // workgroups of single-point mode 0
+    // resident single-point mode
+    envpot::CellMailbox* box = nullptr;  // pinned fine-grained host memory
+    envpot::CellRelay* d_relay = nullptr;
+    double* d_rpart = nullptr;
+    unsigned int* d_rticket = nullptr;
+    hipStream_t rstream = nullptr;       // the resident kernel's own stream
+    bool resident = false;               // launched and not yet joined
+    int rmode = 0;
+    double ridle = 0.0;
+    uint64_t seq = 0;                    // last posted position
 };
 
 namespace {
 
 using envpot::DeviceGuard;
 
+env_status resident_stop(env_cells* h);
+
 void free_cells(env_cells* h) {
     DeviceGuard g(h->device);
+    (void)resident_stop(h);
+    if (h->rstream) (void)hipStreamDestroy(h->rstream);
+    if (h->box) (void)hipHostFree(h->box);
+    (void)hipFree(h->d_relay);
+    (void)hipFree(h->d_rpart);
+    (void)hipFree(h->d_rticket);
     (void)hipFree(h->d_cells);
     (void)hipFree(h->d_nuc);
     (void)hipFree(h->d_split);
     (void)hipFree(h->d_part);
     (void)hipFree(h->d_ticket);
+}
+
+// Ask the resident kernel to exit and join it (also after it left on its
+// own for lack of positions).
+env_status resident_stop(env_cells* h) {
+    if (!h->resident) return ENV_OK;
+    __atomic_store_n(&h->box->stop, 1u, __ATOMIC_RELEASE);
+    const bool ok = hipStreamSynchronize(h->rstream) == hipSuccess;
+    h->resident = false;
+    return ok ? ENV_OK : ENV_E_DEVICE;
+}
+
+env_status resident_launch(env_cells* h) {
+    const int grid = h->rmode == 0 ? h->one_grid : envpot::kCellsPaperGrid;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device) != hipSuccess || khz <= 0)
+        return ENV_E_DEVICE;
+    envpot::CellMailbox* b = h->box;
+    b->stop = 0;
+    b->running = 1;
+    b->req_seq = h->seq;
+    b->done_seq = h->seq;
+    std::atomic_thread_fence(std::memory_order_seq_cst);
+    envpot::CellRelay r{};
+    r.seq = h->seq;
+    if (hipMemcpyAsync(h->d_relay, &r, sizeof(r), hipMemcpyHostToDevice, h->rstream) != hipSuccess ||
+        hipMemsetAsync(h->d_rticket, 0, sizeof(unsigned int), h->rstream) != hipSuccess ||
+        hipStreamSynchronize(h->rstream) != hipSuccess)
+        return ENV_E_DEVICE;
+    envpot::CellResidentArgs a{};
+    a.box = b;
+    a.relay = h->d_relay;
+    a.cells = h->d_cells;
+    a.m = h->m;
+    a.nuc = h->d_nuc;
+    a.n_nuc = h->n_nuc;
+    a.part = h->d_rpart;
+    a.ticket = h->d_rticket;
+    a.start_seq = h->seq;
+    const double tps = double(khz) * 1e3;
+    a.idle_ticks = uint64_t(h->ridle * tps);
+    a.grace_ticks = uint64_t(tps);
+    if (envpot::launch_cells_resident(a, grid, h->precision, h->rstream) != 0) {
+        b->running = 0;
+        return ENV_E_DEVICE;
+    }
+    h->resident = true;
+    return ENV_OK;
 }
 
 template <typename T>
@@ -192,6 +261,74 @@ env_status env_cells_eval_single(env_cells* h, const double* point, double* out,
     a.out = out;
     const int grid = mode == 0 ? h->one_grid : envpot::kCellsPaperGrid;
     return envpot::launch_cells_one(a, grid, h->precision, stream) == 0 ? ENV_OK : ENV_E_DEVICE;
+}
+
+env_status env_cells_resident_start(env_cells* h, int32_t mode, double idle_s) {
+    if (!h || (mode != 0 && mode != 1) || !(idle_s > 0.0) || !(idle_s <= 3600.0)) return ENV_E_ARG;
+    DeviceGuard g(h->device);
+    if (h->resident && __atomic_load_n(&h->box->running, __ATOMIC_ACQUIRE) != 0 && h->rmode == mode &&
+        h->ridle == idle_s)
+        return ENV_OK;
+    if (resident_stop(h) != ENV_OK) return ENV_E_DEVICE;
+    if (!h->box) {
+        void* p = nullptr;
+        if (hipHostMalloc(&p, sizeof(envpot::CellMailbox), hipHostMallocCoherent) != hipSuccess) return ENV_E_NOMEM;
+        h->box = static_cast<envpot::CellMailbox*>(p);
+        std::memset(h->box, 0, sizeof(envpot::CellMailbox));
+        const int gmax = std::max(h->one_grid, envpot::kCellsPaperGrid);
+        if (hipMalloc(reinterpret_cast<void**>(&h->d_relay), sizeof(envpot::CellRelay)) != hipSuccess ||
+            hipMalloc(reinterpret_cast<void**>(&h->d_rpart), size_t(gmax) * sizeof(double)) != hipSuccess ||
+            hipMalloc(reinterpret_cast<void**>(&h->d_rticket), sizeof(unsigned int)) != hipSuccess)
+            return ENV_E_NOMEM;
+        if (hipStreamCreateWithFlags(&h->rstream, hipStreamNonBlocking) != hipSuccess) return ENV_E_DEVICE;
+    }
+    h->rmode = mode;
+    h->ridle = idle_s;
+    return resident_launch(h);
+}
+
+env_status env_cells_resident_eval(env_cells* h, const double* point, double* out, double timeout_s) {
+    if (!h || !point || !out || !(timeout_s > 0.0)) return ENV_E_ARG;
+    if (!h->resident) return ENV_E_STATE;
+    envpot::CellMailbox* b = h->box;
+    if (__atomic_load_n(&b->running, __ATOMIC_ACQUIRE) == 0) {
+        // the kernel left after idle_s without a position: start it again
+        DeviceGuard g(h->device);
+        if (resident_stop(h) != ENV_OK || resident_launch(h) != ENV_OK) return ENV_E_DEVICE;
+    }
+    for (int c = 0; c < 3; ++c) b->point[c] = point[c];
+    const uint64_t k = ++h->seq;
+    __atomic_store_n(&b->req_seq, k, __ATOMIC_RELEASE);
+    const auto t0 = std::chrono::steady_clock::now();
+    for (uint64_t it = 0;; ++it) {
+        if (__atomic_load_n(&b->done_seq, __ATOMIC_ACQUIRE) == k) {
+            *out = b->value;
+            return ENV_OK;
+        }
+        if ((it & 1023) == 1023) {
+            if (__atomic_load_n(&b->running, __ATOMIC_ACQUIRE) == 0 &&
+                __atomic_load_n(&b->done_seq, __ATOMIC_ACQUIRE) != k) {
+                // left for lack of positions just before this one arrived
+                DeviceGuard g(h->device);
+                h->seq = k - 1;
+                if (resident_stop(h) != ENV_OK || resident_launch(h) != ENV_OK) return ENV_E_DEVICE;
+                h->seq = k;
+                __atomic_store_n(&b->req_seq, k, __ATOMIC_RELEASE);
+            }
+            if (std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > timeout_s) {
+                DeviceGuard g(h->device);
+                (void)resident_stop(h);
+                return ENV_E_DEVICE;
+            }
+        }
+        _mm_pause();
+    }
+}
+
+env_status env_cells_resident_stop(env_cells* h) {
+    if (!h) return ENV_E_ARG;
+    DeviceGuard g(h->device);
+    return resident_stop(h);
 }
 
 void env_cells_destroy(env_cells* h) {

@@ -144,24 +144,22 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return t;
 }
 
+// This workgroup's share of the cells at one point (every stride-th cell
+// from its first; kOneUnroll loaded before any is used, so their memory
+// latencies overlap), summed over the workgroup in fixed order.
 template <bool F64>
-__global__ __launch_bounds__(kCellBlock) void k_cells_one(CellOneArgs a) {
-    __shared__ double sh[kCellBlock / 64];
-    __shared__ int last;
-    const GLB double* __restrict__ pt = glb(a.pt);
-    const double px = pt[0], py = pt[1], pz = pt[2];
-    const PTS double* __restrict__ cd = gpts(reinterpret_cast<const double*>(a.cells));
+__device__ __forceinline__ double cells_block_partial(const uint32_t* cells, int64_t m_total, double px, double py,
+                                                      double pz, double* sh) {
+    const PTS double* __restrict__ cd = gpts(reinterpret_cast<const double*>(cells));
     const int64_t stride = (int64_t)gridDim.x * kCellBlock;
-    // each thread takes every stride-th cell; kOneUnroll of them are loaded
-    // before any is used, so their memory latencies overlap
     constexpr int kOneUnroll = 4;
     double acc = 0.0;
-    for (int64_t m0 = (int64_t)blockIdx.x * kCellBlock + threadIdx.x; m0 < a.m; m0 += kOneUnroll * stride) {
+    for (int64_t m0 = (int64_t)blockIdx.x * kCellBlock + threadIdx.x; m0 < m_total; m0 += kOneUnroll * stride) {
         double cx[kOneUnroll], cy[kOneUnroll], cz[kOneUnroll], cq[kOneUnroll];
 #pragma unroll
         for (int u = 0; u < kOneUnroll; ++u) {
             const int64_t m = m0 + u * stride;
-            const bool ok = m < a.m;
+            const bool ok = m < m_total;
             const PTS double* c = cd + (ok ? m : m0) * (kCellWords / 2);
             cx[u] = c[0];
             cy[u] = c[1];
@@ -186,32 +184,137 @@ __global__ __launch_bounds__(kCellBlock) void k_cells_one(CellOneArgs a) {
             acc += (double)tile;
         }
     }
-    const double bs = block_sum(acc, sh);
+    return block_sum(acc, sh);
+}
+
+// Publish this workgroup's partial and take a ticket; true in every thread
+// of the last workgroup to finish.
+__device__ __forceinline__ bool cells_ticket(double bs, double* part, unsigned int* ticket, int* last) {
     if (threadIdx.x == 0) {
         // the partial goes to the device-coherent level, and the ticket's
         // release orders it before the increment (cheaper than a full fence:
         // measured 0.5-1 us of the 9-10 us launch)
-        __hip_atomic_store(a.part + blockIdx.x, bs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned int t = __hip_atomic_fetch_add(a.ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        last = (t == gridDim.x - 1) ? 1 : 0;
+        __hip_atomic_store(part + blockIdx.x, bs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned int t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        *last = (t == gridDim.x - 1) ? 1 : 0;
     }
     __syncthreads();
-    if (!last) return;
-    // the last workgroup: every partial is written; read them past the caches
+    return *last != 0;
+}
+
+// The last workgroup: every workgroup partial in index order, minus from
+// the nuclear sum; valid in thread 0.
+__device__ __forceinline__ double cells_finish(const double* part, const double* nucp, int n_nuc, double px,
+                                              double py, double pz, double* sh) {
+    // every partial is written; read them past the caches
     __threadfence();
     double v = 0.0;
     for (int b = threadIdx.x; b < (int)gridDim.x; b += kCellBlock)
-        v += __hip_atomic_load(a.part + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v += __hip_atomic_load(part + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const double total = block_sum(v, sh);
+    double vn = 0.0;
     if (threadIdx.x == 0) {
-        const GLB double* __restrict__ nuc = glb(a.nuc);
-        double vn = 0.0;
-        for (int q = 0; q < a.n_nuc; ++q) {
+        const GLB double* __restrict__ nuc = glb(nucp);
+        for (int q = 0; q < n_nuc; ++q) {
             const double dx = px - nuc[4 * q], dy = py - nuc[4 * q + 1], dz = pz - nuc[4 * q + 2];
             vn += nuc[4 * q + 3] * rsqrt(__builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz)));
         }
-        a.out[0] = vn - total;
+    }
+    return vn - total;
+}
+
+template <bool F64>
+__global__ __launch_bounds__(kCellBlock) void k_cells_one(CellOneArgs a) {
+    __shared__ double sh[kCellBlock / 64];
+    __shared__ int last;
+    const GLB double* __restrict__ pt = glb(a.pt);
+    const double px = pt[0], py = pt[1], pz = pt[2];
+    const double bs = cells_block_partial<F64>(a.cells, a.m, px, py, pz, sh);
+    if (!cells_ticket(bs, a.part, a.ticket, &last)) return;
+    const double v = cells_finish(a.part, a.nuc, a.n_nuc, px, py, pz, sh);
+    if (threadIdx.x == 0) {
+        a.out[0] = v;
         __hip_atomic_store(a.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Resident single-point mode: the same rounds as k_cells_one, one per
+// position the host posts, without a launch per position.  Workgroup 0's
+// thread 0 alone polls the host mailbox (fine-grained host memory, system
+// scope) and relays each position through device memory (agent scope) to
+// every workgroup; the last workgroup of a round writes V and then the
+// round's sequence number back into the mailbox.  Exit: the host's stop
+// flag, or no position for idle_ticks of the 100 MHz real-time counter
+// (workgroup 0 decides and relays; the others also give up a second after
+// that on their own, so every wave ends).
+template <bool F64>
+__global__ __launch_bounds__(kCellBlock) void k_cells_resident(CellResidentArgs a) {
+    __shared__ double sh[kCellBlock / 64];
+    __shared__ int last;
+    __shared__ double spt[3];
+    __shared__ int scmd;
+    CellMailbox* box = a.box;
+    CellRelay* relay = a.relay;
+    uint64_t seen = a.start_seq;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int cmd = 0;
+            uint64_t t0 = wall_clock64();
+            if (blockIdx.x == 0) {
+                // relaxed polls (an acquire per poll would invalidate the
+                // caches every time); one acquire fence once a change is seen
+                for (;;) {
+                    const uint64_t r = __hip_atomic_load(&box->req_seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    const uint32_t stop = __hip_atomic_load(&box->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    if (stop) break;
+                    if (r != seen) {
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+                        for (int c = 0; c < 3; ++c) {
+                            const double v = __hip_atomic_load(&box->point[c], __ATOMIC_RELAXED,
+                                                               __HIP_MEMORY_SCOPE_SYSTEM);
+                            __hip_atomic_store(&relay->point[c], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                        cmd = 1;
+                        seen = r;
+                        break;
+                    }
+                    if (wall_clock64() - t0 > a.idle_ticks) break;
+                    __builtin_amdgcn_s_sleep(2);
+                }
+                if (!cmd) __hip_atomic_store(&box->running, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(&relay->cmd, (uint32_t)cmd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&relay->seq, cmd ? seen : ~0ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                for (;;) {
+                    const uint64_t r = __hip_atomic_load(&relay->seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (r != seen) {
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                        cmd = (int)__hip_atomic_load(&relay->cmd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        seen = r;
+                        break;
+                    }
+                    if (wall_clock64() - t0 > a.idle_ticks + a.grace_ticks) break;
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+            if (cmd)
+                for (int c = 0; c < 3; ++c)
+                    spt[c] = __hip_atomic_load(&relay->point[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            scmd = cmd;
+        }
+        __syncthreads();
+        if (!scmd) return;
+        const double px = spt[0], py = spt[1], pz = spt[2];
+        const double bs = cells_block_partial<F64>(a.cells, a.m, px, py, pz, sh);
+        if (cells_ticket(bs, a.part, a.ticket, &last)) {
+            const double v = cells_finish(a.part, a.nuc, a.n_nuc, px, py, pz, sh);
+            if (threadIdx.x == 0) {
+                __hip_atomic_store(a.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&box->value, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(&box->done_seq, seen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -229,6 +332,15 @@ int launch_cells(const CellArgs& a, int S, int precision, int np, void* stream) 
         else if (np == 2) hipLaunchKernelGGL((k_cells<2, false>), grid, dim3(kCellBlock), 0, st, a);
         else hipLaunchKernelGGL((k_cells<4, false>), grid, dim3(kCellBlock), 0, st, a);
     }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_cells_resident(const CellResidentArgs& a, int grid, int precision, void* stream) {
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (precision == ENV_PREC_FP64)
+        hipLaunchKernelGGL((k_cells_resident<true>), dim3(grid), dim3(kCellBlock), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_cells_resident<false>), dim3(grid), dim3(kCellBlock), 0, st, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

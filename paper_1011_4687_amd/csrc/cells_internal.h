@@ -35,7 +35,45 @@ struct CellOneArgs {
     double* out;             // V at the point
 };
 
+// Mailbox of the resident single-point mode, in pinned fine-grained host
+// memory: the host posts a position and its sequence number, the kernel
+// answers with V and the same number.  Written by the host: point,
+// req_seq, stop; by the kernel: value, done_seq, running (0 at its exit).
+struct CellMailbox {
+    double point[3];
+    uint64_t req_seq;
+    double value;
+    uint64_t done_seq;
+    uint32_t stop;
+    uint32_t running;
+};
+
+// Device memory: workgroup 0 relays each position (cmd 1) or the exit
+// (cmd 0) to the other workgroups.
+struct CellRelay {
+    double point[3];
+    uint64_t seq;
+    uint32_t cmd;
+    uint32_t pad;
+};
+
+struct CellResidentArgs {
+    CellMailbox* box;
+    CellRelay* relay;        // seq = start_seq, cmd = 0 at launch
+    const uint32_t* cells;
+    int64_t m;
+    const double* nuc;
+    int32_t n_nuc;
+    int32_t pad;
+    double* part;            // one partial per workgroup
+    unsigned int* ticket;    // 0 at launch
+    uint64_t start_seq;      // the mailbox's done_seq at launch
+    uint64_t idle_ticks;     // real-time-counter ticks without a position before exiting
+    uint64_t grace_ticks;    // extra ticks the other workgroups wait for workgroup 0's relay
+};
+
 int launch_cells(const CellArgs& a, int S, int precision, int np, void* stream);
 int launch_cells_one(const CellOneArgs& a, int grid, int precision, void* stream);
+int launch_cells_resident(const CellResidentArgs& a, int grid, int precision, void* stream);
 
 }  // namespace envpot

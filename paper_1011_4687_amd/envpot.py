@@ -222,6 +222,12 @@ def lib():
         L.env_cells_eval.restype = c_int32
         L.env_cells_eval_single.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]
         L.env_cells_eval_single.restype = c_int32
+        L.env_cells_resident_start.argtypes = [c_void_p, c_int32, c_double]
+        L.env_cells_resident_start.restype = c_int32
+        L.env_cells_resident_eval.argtypes = [c_void_p, POINTER(c_double), POINTER(c_double), c_double]
+        L.env_cells_resident_eval.restype = c_int32
+        L.env_cells_resident_stop.argtypes = [c_void_p]
+        L.env_cells_resident_stop.restype = c_int32
         L.env_cells_destroy.argtypes = [c_void_p]
         L.env_cells_destroy.restype = None
         L.env_server_create.argtypes = [POINTER(c_void_p), c_int32, ctypes.c_char_p, c_int32, c_int64,
@@ -853,6 +859,25 @@ class CellEnvironment:
                                            c_void_p(stream.cuda_stream)),
                "env_cells_eval_single")
         return out
+
+    def resident_start(self, mode: int = 0, idle_s: float = 10.0):
+        """Launch the resident single-point kernel (workgroups of `mode`)."""
+        _check(lib().env_cells_resident_start(c_void_p(self.handle), int(mode), float(idle_s)),
+               "env_cells_resident_start")
+
+    def resident_eval(self, point, timeout_s: float = 10.0) -> float:
+        """V at one host point (3 numbers) through the resident kernel's mailbox."""
+        if getattr(self, "_rbuf", None) is None:
+            self._rbuf = ((c_double * 3)(), c_double(0.0))
+        p, out = self._rbuf
+        p[0], p[1], p[2] = float(point[0]), float(point[1]), float(point[2])
+        st = lib().env_cells_resident_eval(c_void_p(self.handle), p, ctypes.byref(out), float(timeout_s))
+        if st != ENV_OK:
+            raise EnvError(st, "env_cells_resident_eval")
+        return out.value
+
+    def resident_stop(self):
+        _check(lib().env_cells_resident_stop(c_void_p(self.handle)), "env_cells_resident_stop")
 
     def close(self):
         if self.handle:

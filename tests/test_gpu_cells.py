@@ -113,3 +113,45 @@ def test_create_errors():
     bad[3, 1] = np.nan
     with pytest.raises(EnvError):
         CellEnvironment(xyz, Z, bad)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_resident_single_point(precision):
+    """The resident kernel answers positions posted through host memory with
+    the values of the one-launch-per-position mode, bit for bit, in both
+    decompositions; it is launched again after leaving for lack of
+    positions; eval before start is refused; destroy ends it."""
+    import time
+    import torch
+    from paper_1011_4687_amd.envpot import ENV_E_STATE, CellEnvironment, EnvError
+    print(f"[cells] resident single point {precision}", flush=True)
+    env, pts = _paper_workload()
+    E = CellEnvironment.from_synth(env, precision=precision)
+    idx = sample_indices(len(pts), 16, seed=7)
+    x = torch.from_numpy(np.ascontiguousarray(pts[idx])).cuda()
+    with pytest.raises(EnvError) as ei:
+        E.resident_eval(pts[idx[0]])
+    assert ei.value.status == ENV_E_STATE
+    for mode in (0, 1):
+        ref = torch.empty(len(idx), dtype=torch.float64, device="cuda")
+        for j in range(len(idx)):
+            E.eval_single(x[j], ref[j:j + 1], mode=mode)
+        torch.cuda.synchronize()
+        ref = ref.cpu().numpy()
+        E.resident_start(mode=mode, idle_s=5.0)
+        got = np.array([E.resident_eval(pts[i]) for i in idx])
+        assert np.array_equal(got, ref), (mode, np.abs(got - ref).max())
+        t0 = time.perf_counter()
+        for j in range(200):
+            E.resident_eval(pts[idx[j % len(idx)]])
+        print(f"[cells] resident mode {mode}: {(time.perf_counter() - t0) / 200 * 1e6:.1f} us per move", flush=True)
+        E.resident_stop()
+        if mode == 0:
+            # leaves after 0.2 s without a position; the next move launches it again
+            E.resident_start(mode=0, idle_s=0.2)
+            assert E.resident_eval(pts[idx[0]]) == ref[0]
+            time.sleep(0.6)
+            assert E.resident_eval(pts[idx[1]]) == ref[1]
+            E.resident_stop()
+    E.resident_start(mode=1, idle_s=5.0)
+    E.close()  # stops the kernel
