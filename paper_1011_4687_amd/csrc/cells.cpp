@@ -270,17 +270,23 @@ env_status env_cells_resident_start(env_cells* h, int32_t mode, double idle_s) {
         h->ridle == idle_s)
         return ENV_OK;
     if (resident_stop(h) != ENV_OK) return ENV_E_DEVICE;
+    // buffers and stream on first use (each one retried if an earlier start failed)
     if (!h->box) {
         void* p = nullptr;
         if (hipHostMalloc(&p, sizeof(envpot::CellMailbox), hipHostMallocCoherent) != hipSuccess) return ENV_E_NOMEM;
         h->box = static_cast<envpot::CellMailbox*>(p);
         std::memset(h->box, 0, sizeof(envpot::CellMailbox));
-        const int gmax = std::max(h->one_grid, envpot::kCellsPaperGrid);
-        if (hipMalloc(reinterpret_cast<void**>(&h->d_relay), sizeof(envpot::CellRelay)) != hipSuccess ||
-            hipMalloc(reinterpret_cast<void**>(&h->d_rpart), size_t(gmax) * sizeof(double)) != hipSuccess ||
-            hipMalloc(reinterpret_cast<void**>(&h->d_rticket), sizeof(unsigned int)) != hipSuccess)
-            return ENV_E_NOMEM;
-        if (hipStreamCreateWithFlags(&h->rstream, hipStreamNonBlocking) != hipSuccess) return ENV_E_DEVICE;
+    }
+    const int gmax = std::max(h->one_grid, envpot::kCellsPaperGrid);
+    if (!h->d_relay && hipMalloc(reinterpret_cast<void**>(&h->d_relay), sizeof(envpot::CellRelay)) != hipSuccess)
+        return ENV_E_NOMEM;
+    if (!h->d_rpart && hipMalloc(reinterpret_cast<void**>(&h->d_rpart), size_t(gmax) * sizeof(double)) != hipSuccess)
+        return ENV_E_NOMEM;
+    if (!h->d_rticket && hipMalloc(reinterpret_cast<void**>(&h->d_rticket), sizeof(unsigned int)) != hipSuccess)
+        return ENV_E_NOMEM;
+    if (!h->rstream && hipStreamCreateWithFlags(&h->rstream, hipStreamNonBlocking) != hipSuccess) {
+        h->rstream = nullptr;
+        return ENV_E_DEVICE;
     }
     h->rmode = mode;
     h->ridle = idle_s;
