@@ -636,8 +636,10 @@ env_status env_cells_eval_single(env_cells* h, const double* point, double* out,
  *   stop:  ask the kernel to exit and wait for it (env_cells_destroy does
  *     this too).
  * While the kernel runs it occupies its workgroups' compute units and
- * every other call on the device shares the rest.  Calls on one handle
- * must not overlap.
+ * every other call on the device shares the rest; a device-wide wait
+ * (hipDeviceSynchronize, torch.cuda.synchronize(), env_potential_export_image,
+ * and HIP calls that wait for the whole device, such as hipFree) waits for
+ * it to leave, so stop it first.  Calls on one handle must not overlap.
  * Errors: ENV_E_ARG (NULL, bad mode, idle_s or timeout_s), ENV_E_NOMEM,
  * ENV_E_DEVICE. */
 env_status env_cells_resident_start(env_cells* h, int32_t mode, double idle_s);

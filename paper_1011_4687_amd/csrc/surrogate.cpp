@@ -335,7 +335,7 @@ env_status env_surrogate_create(env_potential* fallback, const env_surrogate_spe
         return st;
     }
     sg_pack(s->d_params, s->d_W, s->d_WT, nullptr);
-    if (sg_last_error() != 0 || hipDeviceSynchronize() != hipSuccess) {
+    if (sg_last_error() != 0 || hipStreamSynchronize(nullptr) != hipSuccess) {
         destroy(s);
         return ENV_E_DEVICE;
     }
