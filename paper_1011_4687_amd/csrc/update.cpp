@@ -59,6 +59,20 @@ void free_update_state(UpdateState* u) {
     (void)hipFree(u->d_clusters);
     (void)hipFree(u->d_members);
     (void)hipFree(u->d_charge);
+    (void)hipFree(u->d_shell_of_bf);
+    (void)hipFree(u->d_bf0);
+    (void)hipFree(u->d_shell_l);
+    (void)hipFree(u->d_adj_begin);
+    (void)hipFree(u->d_adj_J);
+    (void)hipFree(u->d_adj_blk);
+    (void)hipFree(u->d_adj_tr);
+    (void)hipFree(u->d_cscale);
+    (void)hipFree(u->d_Wd);
+    (void)hipFree(u->d_Wt);
+    (void)hipFree(u->d_err);
+    (void)hipFree(u->d_gpb);
+    (void)hipFree(u->d_dropb);
+    (void)hipFree(u->d_gq);
     delete u;
 }
 
@@ -145,12 +159,40 @@ UpdateState* block_state(const PairList& pl, const PairSources& src, env_status*
     if (s == ENV_OK) s = upload_vec(u->woff, &u->d_woff, u->device_bytes);
     if (s == ENV_OK) s = alloc_dev(size_t(u->woff.back()), &u->d_W, u->device_bytes);
     if (s == ENV_OK) s = alloc_dev(size_t(std::max(pl.n_groups, 1)), &u->d_scale, u->device_bytes);
+    // the device parse of CSR densities: basis and block lists, element buffers
+    if (s == ENV_OK) s = upload_vec(u->shell_of_bf, &u->d_shell_of_bf, u->device_bytes);
+    if (s == ENV_OK) s = upload_vec(u->bf0, &u->d_bf0, u->device_bytes);
+    if (s == ENV_OK) s = upload_vec(u->shell_l, &u->d_shell_l, u->device_bytes);
+    if (s == ENV_OK) s = upload_vec(u->adj_begin, &u->d_adj_begin, u->device_bytes);
+    if (s == ENV_OK) s = upload_vec(u->adj_J, &u->d_adj_J, u->device_bytes);
+    if (s == ENV_OK) s = upload_vec(u->adj_blk, &u->d_adj_blk, u->device_bytes);
+    if (s == ENV_OK) s = upload_vec(u->adj_tr, &u->d_adj_tr, u->device_bytes);
+    if (s == ENV_OK) s = upload_vec(u->cscale, &u->d_cscale, u->device_bytes);
+    if (s == ENV_OK) s = alloc_dev(size_t(u->woff.back()), &u->d_Wd, u->device_bytes);
+    if (s == ENV_OK) s = alloc_dev(size_t(u->woff.back()), &u->d_Wt, u->device_bytes);
+    if (s == ENV_OK) s = alloc_dev(size_t(1), &u->d_err, u->device_bytes);
     if (s != ENV_OK) {
         free_update_state(u);
         *st = s;
         return nullptr;
     }
     return u;
+}
+
+// The group ranges of the per-group charge sums, once pairs and dropped
+// pairs are attached.
+env_status group_tables(UpdateState* u) {
+    std::vector<int64_t> dropb(size_t(u->n_groups) + 1, 0);
+    for (int64_t j = 0; j < int64_t(u->drop_group.size()); ++j) {
+        const int32_t g = u->drop_group[j];
+        if (g < 0 || g >= u->n_groups || (j > 0 && g < u->drop_group[j - 1])) return ENV_E_ARG;
+        ++dropb[size_t(g) + 1];
+    }
+    for (int g = 0; g < u->n_groups; ++g) dropb[g + 1] += dropb[g];
+    env_status s = upload_vec(u->group_pair_begin, &u->d_gpb, u->device_bytes);
+    if (s == ENV_OK) s = upload_vec(dropb, &u->d_dropb, u->device_bytes);
+    if (s == ENV_OK) s = alloc_dev(2 * size_t(std::max(u->n_groups, 1)), &u->d_gq, u->device_bytes);
+    return s;
 }
 
 }  // namespace
@@ -209,6 +251,7 @@ UpdateState* make_update_state(const PairList& pl, const PairSources& src, const
     if (s == ENV_OK) s = upload_vec(moff, &u->d_moff, u->device_bytes);
     if (s == ENV_OK) s = alloc_dev(size_t(moff.back()), &u->d_hm, u->device_bytes);
     if (s == ENV_OK) s = alloc_dev(size_t(n_pairs + n_drop), &u->d_charge, u->device_bytes);
+    if (s == ENV_OK) s = group_tables(u);
     if (s != ENV_OK) {
         free_update_state(u);
         *st = s;
@@ -241,6 +284,7 @@ UpdateState* make_update_state_device(const PairList& meta, const PairSources& s
                        db.n_clusters * int64_t(sizeof(UpdCluster)) + (2 * db.n_members + 1) * 8;
     env_status s = alloc_dev(size_t(db.hm_words), &u->d_hm, u->device_bytes);
     if (s == ENV_OK) s = alloc_dev(size_t(db.n_pairs + db.n_drop), &u->d_charge, u->device_bytes);
+    if (s == ENV_OK) s = group_tables(u);
     if (s != ENV_OK) {
         free_update_state(u);
         *st = s;
@@ -275,87 +319,155 @@ env_status env_potential_update_density(env_potential* h, const env_density* P, 
                      std::chrono::duration<double, std::milli>(now - tlast).count());
         tlast = now;
     };
-    // weights of the known blocks, written through each shell's block list
-    // (columns ascending: one step per element; unsorted columns restart the
-    // walk); an element of an unknown block makes the density invalid
-    std::vector<double> Wd(size_t(u->woff.back()), 0.0), Wt(size_t(u->woff.back()), 0.0);
-    auto row = [&](int mu, auto&& next) -> env_status {
-        const int I = u->shell_of_bf[mu], x = mu - u->bf0[I];
-        const int64_t a0 = u->adj_begin[I], a1 = u->adj_begin[I + 1];
-        int64_t ptr = a0;
-        int nu, prev = -1;
-        double v;
-        while (next(nu, v)) {
-            if (!std::isfinite(v)) return ENV_E_ARG;
-            if (v == 0.0) continue;
-            const int J = u->shell_of_bf[nu], y = nu - u->bf0[J];
-            if (nu < prev) ptr = a0;
-            prev = nu;
-            while (ptr < a1 && u->adj_J[ptr] < J) ++ptr;
-            if (ptr == a1 || u->adj_J[ptr] != J) return ENV_E_ARG;  // a block the build did not see
-            const int32_t b = u->adj_blk[ptr];
-            const int nJb = ncart(u->shell_l[u->blk_J[b]]);
-            if (u->adj_tr[ptr]) Wt[u->woff[b] + y * nJb + x] += v;  // element (J, I) of block (I, J)
-            else Wd[u->woff[b] + x * nJb + y] += v;
-        }
-        return ENV_OK;
-    };
-    if (P->format == ENV_DENSITY_DENSE) {
-        for (int mu = 0; mu < nbf; ++mu) {
-            int nu = 0;
-            const double* rowv = P->values + size_t(mu) * nbf;
-            const env_status r = row(mu, [&](int& c, double& v) {
-                if (nu >= nbf) return false;
-                c = nu;
-                v = rowv[nu++];
-                return true;
-            });
-            if (r != ENV_OK) return r;
-        }
-    } else {
-        if (P->row_ptr[0] != 0) return ENV_E_ARG;
-        for (int mu = 0; mu < nbf; ++mu) {
-            if (P->row_ptr[mu + 1] < P->row_ptr[mu]) return ENV_E_ARG;
-            int64_t k = P->row_ptr[mu];
-            const int64_t ke = P->row_ptr[mu + 1];
-            bool bad = false;
-            const env_status r = row(mu, [&](int& c, double& v) {
-                if (k >= ke) return false;
-                c = P->col[k];
-                v = P->values[k++];
-                if (c < 0 || c >= nbf) {
-                    bad = true;
-                    return false;
-                }
-                return true;
-            });
-            if (bad) return ENV_E_ARG;
-            if (r != ENV_OK) return r;
-        }
-    }
-    lap("density blocks");
-    // symmetry (block (J, I) is the transpose of (I, J)), then the weights
-    // f P_xy s_x s_y with f = 2 off the diagonal blocks
-    std::vector<double> W(size_t(u->woff.back()), 0.0);
-    for (int64_t b = 0; b < u->n_blocks; ++b) {
-        const int I = u->blk_I[b], J = u->blk_J[b];
-        const int nI = ncart(u->shell_l[I]), nJ = ncart(u->shell_l[J]);
-        const double* a = &Wd[u->woff[b]];
-        const double* t = &Wt[u->woff[b]];
-        for (int x = 0; x < nI; ++x)
-            for (int y = 0; y < nJ; ++y) {
-                const double p = a[x * nJ + y], q = (I == J) ? a[y * nJ + x] : t[x * nJ + y];
-                if (std::fabs(p - q) > 1e-10 * (std::fabs(p) + std::fabs(q))) return ENV_E_ARG;
-            }
-        const double f = (I == J) ? 1.0 : 2.0;
-        double* w = &W[u->woff[b]];
-        for (int x = 0; x < nI; ++x)
-            for (int y = 0; y < nJ; ++y)
-                w[x * nJ + y] = f * a[x * nJ + y] * u->cscale[u->bf0[I] + x] * u->cscale[u->bf0[J] + y];
-    }
-    lap("block weights");
     DeviceGuard g(h->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
+    // a CSR density is parsed on the device (ENVPOT_HOST_PARSE=1: on the
+    // host, as a dense one always is); both give the same weights W
+    const char* hpe = std::getenv("ENVPOT_HOST_PARSE");
+    const bool dev_parse = P->format == ENV_DENSITY_CSR && nbf > 0 && u->d_Wd && !(hpe && *hpe && *hpe != '0');
+    std::vector<double> W;
+    if (dev_parse) {
+        if (P->row_ptr[0] != 0) return ENV_E_ARG;
+        for (int mu = 0; mu < nbf; ++mu)
+            if (P->row_ptr[mu + 1] < P->row_ptr[mu]) return ENV_E_ARG;
+        const int64_t nnz = P->row_ptr[nbf];
+        const int64_t nw = u->woff.back();
+        int64_t* d_rp = nullptr;
+        int32_t* d_col = nullptr;
+        double* d_val = nullptr;
+        env_status pst = ENV_OK;
+        if (hipMallocAsync(reinterpret_cast<void**>(&d_rp), size_t(nbf + 1) * sizeof(int64_t), st) != hipSuccess ||
+            hipMallocAsync(reinterpret_cast<void**>(&d_col), size_t(std::max<int64_t>(nnz, 1)) * sizeof(int32_t),
+                           st) != hipSuccess ||
+            hipMallocAsync(reinterpret_cast<void**>(&d_val), size_t(std::max<int64_t>(nnz, 1)) * sizeof(double),
+                           st) != hipSuccess)
+            pst = ENV_E_NOMEM;
+        int32_t herr = 0;
+        if (pst == ENV_OK &&
+            (hipMemcpyAsync(d_rp, P->row_ptr, size_t(nbf + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st) !=
+                 hipSuccess ||
+             (nnz > 0 && hipMemcpyAsync(d_col, P->col, size_t(nnz) * sizeof(int32_t), hipMemcpyHostToDevice, st) !=
+                             hipSuccess) ||
+             (nnz > 0 && hipMemcpyAsync(d_val, P->values, size_t(nnz) * sizeof(double), hipMemcpyHostToDevice,
+                                        st) != hipSuccess) ||
+             (nw > 0 && (hipMemsetAsync(u->d_Wd, 0, size_t(nw) * sizeof(double), st) != hipSuccess ||
+                         hipMemsetAsync(u->d_Wt, 0, size_t(nw) * sizeof(double), st) != hipSuccess)) ||
+             hipMemsetAsync(u->d_err, 0, sizeof(int32_t), st) != hipSuccess))
+            pst = ENV_E_DEVICE;
+        if (pst == ENV_OK) {
+            ParseArgs pa{};
+            pa.row_ptr = d_rp;
+            pa.col = d_col;
+            pa.val = d_val;
+            pa.nnz = nnz;
+            pa.nbf = nbf;
+            pa.shell_of_bf = u->d_shell_of_bf;
+            pa.bf0 = u->d_bf0;
+            pa.shell_l = u->d_shell_l;
+            pa.adj_begin = u->d_adj_begin;
+            pa.adj_J = u->d_adj_J;
+            pa.adj_blk = u->d_adj_blk;
+            pa.adj_tr = u->d_adj_tr;
+            pa.blk = u->d_blk;
+            pa.woff = u->d_woff;
+            pa.n_blocks = u->n_blocks;
+            pa.cscale = u->d_cscale;
+            pa.Wd = u->d_Wd;
+            pa.Wt = u->d_Wt;
+            pa.W = u->d_W;
+            pa.err = u->d_err;
+            if (launch_parse_csr(pa, stream) != 0 || launch_block_weights(pa, nw, stream) != 0 ||
+                hipMemcpyAsync(&herr, u->d_err, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess)
+                pst = ENV_E_DEVICE;
+        }
+        (void)hipFreeAsync(d_rp, st);
+        (void)hipFreeAsync(d_col, st);
+        (void)hipFreeAsync(d_val, st);
+        if (hipStreamSynchronize(st) != hipSuccess && pst == ENV_OK) pst = ENV_E_DEVICE;
+        if (pst != ENV_OK) return pst;
+        if (herr != 0) return ENV_E_ARG;  // the records are untouched: only W was written
+        lap("device parse");
+    } else {
+        // weights of the known blocks, written through each shell's block list
+        // (columns ascending: one step per element; unsorted columns restart the
+        // walk); an element of an unknown block makes the density invalid
+        std::vector<double> Wd(size_t(u->woff.back()), 0.0), Wt(size_t(u->woff.back()), 0.0);
+        auto row = [&](int mu, auto&& next) -> env_status {
+            const int I = u->shell_of_bf[mu], x = mu - u->bf0[I];
+            const int64_t a0 = u->adj_begin[I], a1 = u->adj_begin[I + 1];
+            int64_t ptr = a0;
+            int nu, prev = -1;
+            double v;
+            while (next(nu, v)) {
+                if (!std::isfinite(v)) return ENV_E_ARG;
+                if (v == 0.0) continue;
+                const int J = u->shell_of_bf[nu], y = nu - u->bf0[J];
+                if (nu < prev) ptr = a0;
+                prev = nu;
+                while (ptr < a1 && u->adj_J[ptr] < J) ++ptr;
+                if (ptr == a1 || u->adj_J[ptr] != J) return ENV_E_ARG;  // a block the build did not see
+                const int32_t b = u->adj_blk[ptr];
+                const int nJb = ncart(u->shell_l[u->blk_J[b]]);
+                if (u->adj_tr[ptr]) Wt[u->woff[b] + y * nJb + x] += v;  // element (J, I) of block (I, J)
+                else Wd[u->woff[b] + x * nJb + y] += v;
+            }
+            return ENV_OK;
+        };
+        if (P->format == ENV_DENSITY_DENSE) {
+            for (int mu = 0; mu < nbf; ++mu) {
+                int nu = 0;
+                const double* rowv = P->values + size_t(mu) * nbf;
+                const env_status r = row(mu, [&](int& c, double& v) {
+                    if (nu >= nbf) return false;
+                    c = nu;
+                    v = rowv[nu++];
+                    return true;
+                });
+                if (r != ENV_OK) return r;
+            }
+        } else {
+            if (P->row_ptr[0] != 0) return ENV_E_ARG;
+            for (int mu = 0; mu < nbf; ++mu) {
+                if (P->row_ptr[mu + 1] < P->row_ptr[mu]) return ENV_E_ARG;
+                int64_t k = P->row_ptr[mu];
+                const int64_t ke = P->row_ptr[mu + 1];
+                bool bad = false;
+                const env_status r = row(mu, [&](int& c, double& v) {
+                    if (k >= ke) return false;
+                    c = P->col[k];
+                    v = P->values[k++];
+                    if (c < 0 || c >= nbf) {
+                        bad = true;
+                        return false;
+                    }
+                    return true;
+                });
+                if (bad) return ENV_E_ARG;
+                if (r != ENV_OK) return r;
+            }
+        }
+        lap("density blocks");
+        // symmetry (block (J, I) is the transpose of (I, J)), then the weights
+        // f P_xy s_x s_y with f = 2 off the diagonal blocks
+        W.assign(size_t(u->woff.back()), 0.0);
+        for (int64_t b = 0; b < u->n_blocks; ++b) {
+            const int I = u->blk_I[b], J = u->blk_J[b];
+            const int nI = ncart(u->shell_l[I]), nJ = ncart(u->shell_l[J]);
+            const double* a = &Wd[u->woff[b]];
+            const double* t = &Wt[u->woff[b]];
+            for (int x = 0; x < nI; ++x)
+                for (int y = 0; y < nJ; ++y) {
+                    const double p = a[x * nJ + y], q = (I == J) ? a[y * nJ + x] : t[x * nJ + y];
+                    if (std::fabs(p - q) > 1e-10 * (std::fabs(p) + std::fabs(q))) return ENV_E_ARG;
+                }
+            const double f = (I == J) ? 1.0 : 2.0;
+            double* w = &W[u->woff[b]];
+            for (int x = 0; x < nI; ++x)
+                for (int y = 0; y < nJ; ++y)
+                    w[x * nJ + y] = f * a[x * nJ + y] * u->cscale[u->bf0[I] + x] * u->cscale[u->bf0[J] + y];
+        }
+        lap("block weights");
+    }
     UpdateArgs A{};
     A.pairs = u->d_pairs;
     A.n_pairs = u->n_pairs;
@@ -388,20 +500,20 @@ env_status env_potential_update_density(env_potential* h, const env_density* P, 
         return fail();
     // electron counts per group; with ENV_NEUTRALIZE the scale to the group's
     // nuclear charge (screened-out pairs included, as at create)
-    std::vector<double> q(size_t(u->n_pairs + u->n_drop));
+    // (the charges of every pair, summed per group on the device in fixed order)
+    std::vector<double> gq(2 * size_t(u->n_groups), 0.0);
     if (launch_update_charges(A, stream) != 0) return fail();
-    if (!q.empty() && hipMemcpyAsync(q.data(), u->d_charge, q.size() * sizeof(double), hipMemcpyDeviceToHost, st) !=
-                          hipSuccess)
+    if (u->n_groups > 0 &&
+        (launch_group_charges(u->d_charge, u->d_gpb, u->d_dropb, u->n_pairs, u->n_groups, u->d_gq, stream) != 0 ||
+         hipMemcpyAsync(gq.data(), u->d_gq, gq.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess))
         return fail();
     if (hipStreamSynchronize(st) != hipSuccess) return ENV_E_DEVICE;
     lap("upload, charges");
     std::vector<double> qkept(u->n_groups, 0.0), qall(u->n_groups, 0.0), scale(std::max(u->n_groups, 1), 1.0);
-    for (int gi = 0; gi < u->n_groups; ++gi)
-        for (int64_t k = u->group_pair_begin[gi]; k < u->group_pair_begin[gi + 1]; ++k) qkept[gi] += q[k];
-    for (int64_t j = 0; j < u->n_drop; ++j) qall[u->drop_group[j]] += q[u->n_pairs + j];
     double electrons = 0.0;
     for (int gi = 0; gi < u->n_groups; ++gi) {
-        qall[gi] += qkept[gi];
+        qkept[gi] = gq[2 * size_t(gi)];
+        qall[gi] = gq[2 * size_t(gi) + 1] + qkept[gi];
         if (u->neutralize && qall[gi] != 0.0) scale[gi] = u->group_charge[gi] / qall[gi];
         electrons += scale[gi] * qkept[gi];
     }

@@ -221,7 +221,117 @@ __global__ __launch_bounds__(kUpdBlock) void k_upd_clusters(UpdateArgs A) {
 
 unsigned blocks_for(int64_t n) { return unsigned((n + kUpdBlock - 1) / kUpdBlock); }
 
+// One thread per stored element of a CSR density (ParseArgs).
+__global__ __launch_bounds__(kUpdBlock) void k_parse_csr(ParseArgs a) {
+    const int64_t k = (int64_t)blockIdx.x * kUpdBlock + threadIdx.x;
+    if (k >= a.nnz) return;
+    int lo = 0, hi = a.nbf;  // the row: row_ptr[lo] <= k < row_ptr[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a.row_ptr[mid] <= k) lo = mid;
+        else hi = mid;
+    }
+    const int mu = lo, nu = a.col[k];
+    const double v = a.val[k];
+    if (nu < 0 || nu >= a.nbf || !isfinite(v)) {
+        atomicOr(a.err, 1);
+        return;
+    }
+    if (v == 0.0) return;
+    const int I = a.shell_of_bf[mu], J = a.shell_of_bf[nu];
+    const int x = mu - a.bf0[I], y = nu - a.bf0[J];
+    int64_t b0 = a.adj_begin[I], b1 = a.adj_begin[I + 1];  // first partner >= J
+    const int64_t end = b1;
+    while (b0 < b1) {
+        const int64_t mid = (b0 + b1) >> 1;
+        if (a.adj_J[mid] < J) b0 = mid + 1;
+        else b1 = mid;
+    }
+    if (b0 == end || a.adj_J[b0] != J) {
+        atomicOr(a.err, 2);
+        return;
+    }
+    const int b = a.adj_blk[b0];
+    const int lJ = a.shell_l[a.blk[2 * b + 1]];
+    const int nJb = (lJ + 1) * (lJ + 2) / 2;
+    if (a.adj_tr[b0]) atomicAdd(&a.Wt[a.woff[b] + y * nJb + x], v);  // element (J, I) of block (I, J)
+    else atomicAdd(&a.Wd[a.woff[b] + x * nJb + y], v);
+}
+
+// One thread per block weight: symmetry against the transposed element,
+// then W = f P s_x s_y (f = 2 off the diagonal blocks).
+__global__ __launch_bounds__(kUpdBlock) void k_block_weights(ParseArgs a) {
+    const int64_t total = a.woff[a.n_blocks];
+    const int64_t e = (int64_t)blockIdx.x * kUpdBlock + threadIdx.x;
+    if (e >= total) return;
+    int64_t lo = 0, hi = a.n_blocks;  // the block: woff[lo] <= e < woff[hi]
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a.woff[mid] <= e) lo = mid;
+        else hi = mid;
+    }
+    const int b = (int)lo;
+    const int I = a.blk[2 * b], J = a.blk[2 * b + 1];
+    const int lJ = a.shell_l[J];
+    const int nJ = (lJ + 1) * (lJ + 2) / 2;
+    const int64_t r = e - a.woff[b];
+    const int x = (int)(r / nJ), y = (int)(r % nJ);
+    const double p = a.Wd[e];
+    const double q = (I == J) ? a.Wd[a.woff[b] + y * nJ + x] : a.Wt[e];
+    if (fabs(p - q) > 1e-10 * (fabs(p) + fabs(q))) atomicOr(a.err, 4);
+    const double f = (I == J) ? 1.0 : 2.0;
+    a.W[e] = f * p * a.cscale[a.bf0[I] + x] * a.cscale[a.bf0[J] + y];
+}
+
+// One workgroup per fragment group: its kept and its dropped pairs'
+// charges, each summed by strided threads and then a fixed LDS tree.
+__global__ __launch_bounds__(kUpdBlock) void k_group_charges(const double* __restrict__ charge,
+                                                             const int64_t* __restrict__ gpb,
+                                                             const int64_t* __restrict__ dropb, int64_t n_pairs,
+                                                             double* __restrict__ gq) {
+    __shared__ double sk[kUpdBlock], sd[kUpdBlock];
+    const int g = blockIdx.x, t = threadIdx.x;
+    double a = 0.0, d = 0.0;
+    for (int64_t k = gpb[g] + t; k < gpb[g + 1]; k += kUpdBlock) a += charge[k];
+    for (int64_t j = dropb[g] + t; j < dropb[g + 1]; j += kUpdBlock) d += charge[n_pairs + j];
+    sk[t] = a;
+    sd[t] = d;
+    __syncthreads();
+    for (int s = kUpdBlock / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            sk[t] += sk[t + s];
+            sd[t] += sd[t + s];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        gq[2 * g] = sk[0];
+        gq[2 * g + 1] = sd[0];
+    }
+}
+
 }  // namespace
+
+int launch_group_charges(const double* charge, const int64_t* gpb, const int64_t* dropb, int64_t n_pairs,
+                         int n_groups, double* gq, void* stream) {
+    if (n_groups <= 0) return 0;
+    hipLaunchKernelGGL(k_group_charges, dim3(n_groups), dim3(kUpdBlock), 0, static_cast<hipStream_t>(stream), charge,
+                       gpb, dropb, n_pairs, gq);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_parse_csr(const ParseArgs& a, void* stream) {
+    if (a.nnz <= 0) return 0;
+    hipLaunchKernelGGL(k_parse_csr, dim3(blocks_for(a.nnz)), dim3(kUpdBlock), 0, static_cast<hipStream_t>(stream), a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_block_weights(const ParseArgs& a, int64_t total, void* stream) {
+    if (total <= 0) return 0;
+    hipLaunchKernelGGL(k_block_weights, dim3(blocks_for(total)), dim3(kUpdBlock), 0,
+                       static_cast<hipStream_t>(stream), a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
 
 int launch_update_charges(const UpdateArgs& a, void* stream) {
     const int64_t n = a.n_pairs + a.n_drop;

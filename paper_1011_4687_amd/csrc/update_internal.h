@@ -160,8 +160,59 @@ struct UpdateState {
     int64_t* d_moff = nullptr;
     double* d_hm = nullptr;
     double* d_charge = nullptr;
+    // device parse of a CSR density (ParseArgs): the basis and block lists
+    int32_t* d_shell_of_bf = nullptr;
+    int32_t* d_bf0 = nullptr;
+    int32_t* d_shell_l = nullptr;
+    int64_t* d_adj_begin = nullptr;
+    int32_t* d_adj_J = nullptr;
+    int32_t* d_adj_blk = nullptr;
+    uint8_t* d_adj_tr = nullptr;
+    double* d_cscale = nullptr;
+    double* d_Wd = nullptr;   // the density's elements by block, as given and transposed
+    double* d_Wt = nullptr;
+    int32_t* d_err = nullptr;
+    // per-group electron counts on the device: pair and dropped-pair ranges
+    // of every group, and the two sums per group
+    int64_t* d_gpb = nullptr;     // per group + 1 (group_pair_begin)
+    int64_t* d_dropb = nullptr;   // per group + 1 (dropped pairs are group-major)
+    double* d_gq = nullptr;       // per group: kept, dropped
     int64_t device_bytes = 0;
 };
+
+// A CSR density parsed on the device into the block weights W: one thread
+// per stored element finds its block through the row shell's block list
+// (binary search by partner shell) and adds the value at its place, as
+// given (Wd) or transposed (Wt; a stored element occurs once, so the sum
+// is the value itself); then one thread per weight checks the symmetry
+// against the transposed element and forms f P s_x s_y.  err collects
+// bit 1 (column out of range or non-finite value), bit 2 (an element of a
+// block the build did not see), bit 4 (asymmetric).
+struct ParseArgs {
+    const int64_t* row_ptr;   // nbf + 1
+    const int32_t* col;       // nnz
+    const double* val;        // nnz
+    int64_t nnz;
+    int32_t nbf;
+    int32_t pad;
+    const int32_t* shell_of_bf;
+    const int32_t* bf0;       // per shell + 1
+    const int32_t* shell_l;
+    const int64_t* adj_begin; // per shell + 1
+    const int32_t* adj_J;
+    const int32_t* adj_blk;
+    const uint8_t* adj_tr;
+    const int32_t* blk;       // per block: I, J
+    const int64_t* woff;      // per block + 1
+    int64_t n_blocks;
+    const double* cscale;     // per basis function
+    double* Wd;
+    double* Wt;
+    double* W;
+    int32_t* err;
+};
+int launch_parse_csr(const ParseArgs& a, void* stream);
+int launch_block_weights(const ParseArgs& a, int64_t total, void* stream);  // total = woff[n_blocks]
 
 // Offsets of the far-field matrices M_L (ncomp x ncomp, row-major) in d_M.
 constexpr int kFarMatOff[kLMax + 2] = {0, 1, 17, 117, 517, 1742};
@@ -177,6 +228,10 @@ UpdateState* make_update_state_device(const PairList& meta, const PairSources& s
 void free_update_state(UpdateState* u);
 
 int launch_update_charges(const UpdateArgs& a, void* stream);
+// Per group g: gq[2g] = sum of the kept pairs' charges, gq[2g+1] = sum of
+// the dropped pairs' charges, each in a fixed order (one workgroup per group).
+int launch_group_charges(const double* charge, const int64_t* gpb, const int64_t* dropb, int64_t n_pairs,
+                         int n_groups, double* gq, void* stream);
 int launch_update_pairs(const UpdateArgs& a, void* stream);
 int launch_update_members(const UpdateArgs& a, void* stream);
 int launch_update_clusters(const UpdateArgs& a, void* stream);

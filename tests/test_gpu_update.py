@@ -149,3 +149,57 @@ def test_update_errors():
     assert np.abs(V - _gpu(F, pts[:256])).max() <= 2e-6
     E.close()
     F.close()
+
+
+def _csr(P):
+    """CSR triple (row_ptr, col, values) of the nonzero elements of a dense P."""
+    P = np.asarray(P)
+    rows, cols = np.nonzero(P)
+    row_ptr = np.zeros(P.shape[0] + 1, dtype=np.int64)
+    np.add.at(row_ptr, rows + 1, 1)
+    return np.cumsum(row_ptr), cols.astype(np.int32), P[rows, cols].astype(np.float64)
+
+
+@pytest.mark.parametrize("precision", ["fp32c", "fp64"])
+def test_update_device_parse_matches_host_parse(precision, monkeypatch):
+    """A CSR density is parsed on the device; the records it gives equal, bit
+    for bit, those of the host parse of the same density (ENVPOT_HOST_PARSE=1),
+    and the errors the host parse finds are found on the device too (an
+    element of a block the build did not see, an asymmetric density, a
+    column out of range, a non-finite value), leaving the records as they
+    were."""
+    from oracle import oracle as O
+    from paper_1011_4687_amd.envpot import ENV_E_ARG, Environment, EnvError
+    print(f"[update] device parse {precision}", flush=True)
+    env, pts = _mid()
+    P1 = env.density_dense(O.neutral_scales(env))
+    P2 = _perturbed(env, 6)
+    kw = dict(precision=precision, neutralize=True)
+    A = Environment(env.xyz, env.Z, env.fragment, _shells(env), P1, **kw)
+    B = Environment(env.xyz, env.Z, env.fragment, _shells(env), P1, **kw)
+    A.update_density(_csr(P2))
+    monkeypatch.setenv("ENVPOT_HOST_PARSE", "1")
+    B.update_density(_csr(P2))
+    monkeypatch.delenv("ENVPOT_HOST_PARSE")
+    ra, sa = A.export_image()
+    rb, sb = B.export_image()
+    assert np.array_equal(ra, rb) and np.array_equal(sa, sb)
+    assert A.info()["electrons"] == B.info()["electrons"]
+    assert np.array_equal(_gpu(A, pts[:512]), _gpu(B, pts[:512]))
+    bad_block = P2.copy()
+    bad_block[0, env.nbf - 1] = bad_block[env.nbf - 1, 0] = 1e-3
+    asym = P2.copy()
+    a, b = next((p, q) for p, q in np.argwhere(P2 != 0) if p != q)
+    asym[a, b] += 0.1
+    rp, col, val = _csr(P2)
+    bad_col = (rp, col.copy(), val)
+    bad_col[1][7] = env.nbf
+    nan_val = (rp, col, val.copy())
+    nan_val[2][11] = np.nan
+    for bad in (_csr(bad_block), _csr(asym), bad_col, nan_val):
+        with pytest.raises(EnvError) as ei:
+            A.update_density(bad)
+        assert ei.value.status == ENV_E_ARG
+    assert np.array_equal(A.export_image()[0], ra)
+    A.close()
+    B.close()
