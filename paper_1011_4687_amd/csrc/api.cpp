@@ -35,6 +35,7 @@ void free_device(env_potential* h) {
     DeviceGuard g(h->device);
     (void)hipFree(h->d_rec);
     (void)hipFree(h->d_segs);
+    (void)hipFree(h->d_boxes);
     (void)hipFree(h->d_split);
     (void)hipFree(h->d_nuc);
     (void)hipFree(h->d_boys);
@@ -44,6 +45,7 @@ void free_device(env_potential* h) {
     h->upd = nullptr;
     h->d_rec = nullptr;
     h->d_segs = nullptr;
+    h->d_boxes = nullptr;
     h->d_split = nullptr;
     h->d_nuc = nullptr;
     h->d_boys = nullptr;
@@ -54,6 +56,25 @@ int env_int(const char* name, int dflt) {
     const char* s = std::getenv(name);
     if (!s || !*s) return dflt;
     return std::atoi(s);
+}
+
+// Far-field boxes of the unsplit segments, from the records on the device
+// (the same for the host packer's and the device build's records).
+env_status segment_boxes(env_potential* h, const std::vector<Segment>& base, bool fp64) {
+    h->use_boxes = env_int("ENVPOT_NO_FARBOX", 0) != 1;
+    const int64_t nb = std::max<int64_t>(int64_t(base.size()), 1) * kSegBoxWords * int64_t(sizeof(double));
+    if (hipMalloc(reinterpret_cast<void**>(&h->d_boxes), size_t(nb)) != hipSuccess) return ENV_E_NOMEM;
+    h->device_bytes += nb;
+    if (base.empty()) return ENV_OK;
+    Segment* tmp = nullptr;
+    if (hipMalloc(reinterpret_cast<void**>(&tmp), base.size() * sizeof(Segment)) != hipSuccess) return ENV_E_NOMEM;
+    env_status st = ENV_OK;
+    if (hipMemcpy(tmp, base.data(), base.size() * sizeof(Segment), hipMemcpyHostToDevice) != hipSuccess ||
+        launch_segment_boxes(tmp, int(base.size()), h->d_rec, fp64 ? 1 : 0, h->d_boxes, nullptr) != 0 ||
+        hipStreamSynchronize(nullptr) != hipSuccess)
+        st = ENV_E_DEVICE;
+    (void)hipFree(tmp);
+    return st;
 }
 
 }  // namespace
@@ -106,6 +127,7 @@ EvalArgs make_args(const env_potential* h, const double* points, int64_t n, doub
     a.rec = h->d_rec;
     a.nuc = h->d_nuc;
     a.boys = h->d_boys;
+    a.boxes = h->use_boxes ? h->d_boxes : nullptr;
     a.out = out;
     a.bp = h->bp;
     return a;
@@ -324,6 +346,7 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
     in.n_clusters = lay.n_clusters;
     in.n_cluster_members = lay.n_members;
     in.pairs_built_on_device = dev_build ? 1 : 0;
+    for (size_t i = 0; i < lay.base.size(); ++i) lay.base[i].box = int32_t(i);
     std::vector<Segment> allsegs;
     std::vector<int32_t> allsplit;
     for (int k = 0; k <= kMaxSplitLog2; ++k) {
@@ -369,6 +392,7 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
         }
         if (st == ENV_OK) st = upload(allsegs, &h->d_segs, h->device_bytes);
         if (st == ENV_OK) st = upload(allsplit, &h->d_split, h->device_bytes);
+        if (st == ENV_OK) st = segment_boxes(h, lay.base, fp64);
         if (st == ENV_OK) st = upload(pl.nuc, &h->d_nuc, h->device_bytes);
         if (st == ENV_OK) {
             if (fp64) st = upload(t64, reinterpret_cast<double**>(&h->d_boys), h->device_bytes);

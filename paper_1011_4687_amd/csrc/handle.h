@@ -34,6 +34,8 @@ struct env_potential {
     // device buffers
     uint32_t* d_rec = nullptr;
     envpot::Segment* d_segs = nullptr;
+    double* d_boxes = nullptr;          // per unsplit segment (Segment::box)
+    bool use_boxes = true;              // ENVPOT_NO_FARBOX=1 at create: test every pair
     int32_t* d_split = nullptr;
     double* d_nuc = nullptr;
     void* d_boys = nullptr;

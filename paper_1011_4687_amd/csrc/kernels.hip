@@ -174,7 +174,9 @@ __device__ __forceinline__ double near_f64(const GLB uint32_t* __restrict__ r, d
 }
 
 // FP32C pairs of one L.  Record: P (3 doubles), r2far, p, c1, h[nc], D[nc].
-template <int L, int NP>
+// FAR: every point-pair is known to be in the far field (segment box test),
+// so the per-pair near test is left out.
+template <int L, int NP, bool FAR>
 __device__ __forceinline__ void pairs_f32(const GLB uint32_t* __restrict__ rec, int npairs,
                                           const double* cx, const double* cy, const double* cz,
                                           const float* tab, double* ele) {
@@ -203,10 +205,12 @@ __device__ __forceinline__ void pairs_f32(const GLB uint32_t* __restrict__ rec, 
                     Z[k] = (float)(cur.pz - cz[k]);
                     r2[k] = __builtin_fmaf(X[k], X[k], __builtin_fmaf(Y[k], Y[k], Z[k] * Z[k]));
                 }
-                float m = r2[0];
+                if constexpr (!FAR) {
+                    float m = r2[0];
 #pragma unroll
-                for (int k = 1; k < NP; ++k) m = fminf(m, r2[k]);
-                if (__builtin_expect(__builtin_amdgcn_ballot_w64(m < cur.r2far) != 0, 0)) break;
+                    for (int k = 1; k < NP; ++k) m = fminf(m, r2[k]);
+                    if (__builtin_expect(__builtin_amdgcn_ballot_w64(m < cur.r2far) != 0, 0)) break;
+                }
 #pragma unroll
                 for (int k = 0; k < NP; ++k) {
                     const float ri = rsqrt_raw(r2[k]);
@@ -261,7 +265,7 @@ __device__ __forceinline__ void pairs_f32(const GLB uint32_t* __restrict__ rec, 
 }
 
 // FP64 pairs of one L.  Record: P, r2far, p, c1 (doubles), h[nc], D[nc].
-template <int L, int NP>
+template <int L, int NP, bool FAR>
 __device__ __forceinline__ void pairs_f64(const GLB uint32_t* __restrict__ rec, int npairs,
                                           const double* cx, const double* cy, const double* cz,
                                           const GLB double* __restrict__ tab, double* ele) {
@@ -284,7 +288,7 @@ __device__ __forceinline__ void pairs_f64(const GLB uint32_t* __restrict__ rec, 
             r2[k] = __builtin_fma(X[k], X[k], __builtin_fma(Y[k], Y[k], Z[k] * Z[k]));
             nearp |= r2[k] < cur.r2far;
         }
-        if (__builtin_amdgcn_ballot_w64(nearp) == 0) {
+        if (FAR || __builtin_amdgcn_ballot_w64(nearp) == 0) {
 #pragma unroll
             for (int k = 0; k < NP; ++k) {
                 const double ri = rsqrt_far(r2[k]);
@@ -404,6 +408,7 @@ __device__ __forceinline__ void block_work_impl(const PTS double* __restrict__ p
                                                 const GLB uint32_t* __restrict__ recs,
                                                 const GLB double* __restrict__ nuc,
                                                 const GLB double* __restrict__ boys64,
+                                                const GLB double* __restrict__ boxes,
                                                 double* __restrict__ out,
                                                 int64_t pblock, int s, const float* tab32) {
     const int64_t base = pblock * (kBlock * NP) + threadIdx.x;
@@ -431,6 +436,7 @@ __device__ __forceinline__ void block_work_impl(const PTS double* __restrict__ p
     for (;;) {
         int L, npairs;
         const GLB uint32_t* rec;
+        bool all_far = false;  // member runs and clusters: tested pair by pair
         if (pend != 0) {
             L = __builtin_ctz(pend);
             pend &= pend - 1;
@@ -502,23 +508,58 @@ __device__ __forceinline__ void block_work_impl(const PTS double* __restrict__ p
             L = sL;
             rec = recs + so;
             npairs = sn;
+            // segment box test: every point of the wave beyond the largest
+            // far-field radius of the segment's pairs
+            if (boxes && npairs > 0) {
+                const GLB double* bx = boxes + (int64_t)kSegBoxWords * sp->box;
+                const double lim = bx[6] * (1.0 + 1e-6);
+                bool nearp = false;
+#pragma unroll
+                for (int k = 0; k < NP; ++k) {
+                    const double gx = fmax(0.0, fmax(bx[0] - cx[k], cx[k] - bx[3]));
+                    const double gy = fmax(0.0, fmax(bx[1] - cy[k], cy[k] - bx[4]));
+                    const double gz = fmax(0.0, fmax(bx[2] - cz[k], cz[k] - bx[5]));
+                    nearp |= __builtin_fma(gx, gx, __builtin_fma(gy, gy, gz * gz)) < lim;
+                }
+                all_far = __builtin_amdgcn_ballot_w64(nearp) == 0;
+            }
         }
         if constexpr (F64) {
             const GLB double* tab = boys64;
-            switch (L) {
-                case 0: pairs_f64<0, NP>(rec, npairs, cx, cy, cz, tab, ve); break;
-                case 1: pairs_f64<1, NP>(rec, npairs, cx, cy, cz, tab, ve); break;
-                case 2: pairs_f64<2, NP>(rec, npairs, cx, cy, cz, tab, ve); break;
-                case 3: pairs_f64<3, NP>(rec, npairs, cx, cy, cz, tab, ve); break;
-                default: pairs_f64<4, NP>(rec, npairs, cx, cy, cz, tab, ve); break;
+            if (all_far) {
+                switch (L) {
+                    case 0: pairs_f64<0, NP, true>(rec, npairs, cx, cy, cz, tab, ve); break;
+                    case 1: pairs_f64<1, NP, true>(rec, npairs, cx, cy, cz, tab, ve); break;
+                    case 2: pairs_f64<2, NP, true>(rec, npairs, cx, cy, cz, tab, ve); break;
+                    case 3: pairs_f64<3, NP, true>(rec, npairs, cx, cy, cz, tab, ve); break;
+                    default: pairs_f64<4, NP, true>(rec, npairs, cx, cy, cz, tab, ve); break;
+                }
+            } else {
+                switch (L) {
+                    case 0: pairs_f64<0, NP, false>(rec, npairs, cx, cy, cz, tab, ve); break;
+                    case 1: pairs_f64<1, NP, false>(rec, npairs, cx, cy, cz, tab, ve); break;
+                    case 2: pairs_f64<2, NP, false>(rec, npairs, cx, cy, cz, tab, ve); break;
+                    case 3: pairs_f64<3, NP, false>(rec, npairs, cx, cy, cz, tab, ve); break;
+                    default: pairs_f64<4, NP, false>(rec, npairs, cx, cy, cz, tab, ve); break;
+                }
             }
         } else {
-            switch (L) {
-                case 0: pairs_f32<0, NP>(rec, npairs, cx, cy, cz, tab32, ve); break;
-                case 1: pairs_f32<1, NP>(rec, npairs, cx, cy, cz, tab32, ve); break;
-                case 2: pairs_f32<2, NP>(rec, npairs, cx, cy, cz, tab32, ve); break;
-                case 3: pairs_f32<3, NP>(rec, npairs, cx, cy, cz, tab32, ve); break;
-                default: pairs_f32<4, NP>(rec, npairs, cx, cy, cz, tab32, ve); break;
+            if (all_far) {
+                switch (L) {
+                    case 0: pairs_f32<0, NP, true>(rec, npairs, cx, cy, cz, tab32, ve); break;
+                    case 1: pairs_f32<1, NP, true>(rec, npairs, cx, cy, cz, tab32, ve); break;
+                    case 2: pairs_f32<2, NP, true>(rec, npairs, cx, cy, cz, tab32, ve); break;
+                    case 3: pairs_f32<3, NP, true>(rec, npairs, cx, cy, cz, tab32, ve); break;
+                    default: pairs_f32<4, NP, true>(rec, npairs, cx, cy, cz, tab32, ve); break;
+                }
+            } else {
+                switch (L) {
+                    case 0: pairs_f32<0, NP, false>(rec, npairs, cx, cy, cz, tab32, ve); break;
+                    case 1: pairs_f32<1, NP, false>(rec, npairs, cx, cy, cz, tab32, ve); break;
+                    case 2: pairs_f32<2, NP, false>(rec, npairs, cx, cy, cz, tab32, ve); break;
+                    case 3: pairs_f32<3, NP, false>(rec, npairs, cx, cy, cz, tab32, ve); break;
+                    default: pairs_f32<4, NP, false>(rec, npairs, cx, cy, cz, tab32, ve); break;
+                }
             }
         }
     }
@@ -537,7 +578,7 @@ template <int NP, bool F64>
 __device__ __forceinline__ void block_work(const EvalArgs& a, int64_t pblock, int s,
                                            const float* tab32) {
     block_work_impl<NP, F64>(gpts(a.pts), a.n, glb(a.segs), glb(a.split), glb(a.rec), glb(a.nuc),
-                             glb(static_cast<const double*>(a.boys)), a.out, pblock, s, tab32);
+                             glb(static_cast<const double*>(a.boys)), glb(a.boxes), a.out, pblock, s, tab32);
 }
 
 // Stage the FP32 Boys table into LDS (one copy per workgroup; the near
@@ -651,6 +692,46 @@ __global__ __launch_bounds__(kBlock) void k_sum_splits_multi(const SumDesc* __re
     q.out[i] = s;
 }
 
+// Box of an unsplit segment of pairs (one workgroup per segment): the
+// smallest and largest pair centre coordinates and the largest stored r2far.
+// Cluster and empty segments get r2far max = +inf (never all far).
+__global__ __launch_bounds__(kBlock) void k_segment_boxes(const Segment* __restrict__ segs,
+                                                          const uint32_t* __restrict__ rec, int fp64,
+                                                          double* __restrict__ boxes) {
+    __shared__ double red[7][kBlock];
+    const Segment sg = segs[blockIdx.x];
+    const bool pairs = !(sg.flags & kSegCluster) && sg.n_pairs > 0;
+    double v[7] = {HUGE_VAL, HUGE_VAL, HUGE_VAL, -HUGE_VAL, -HUGE_VAL, -HUGE_VAL, 0.0};
+    if (pairs) {
+        const int rw = fp64 ? rec64_words(sg.L) : rec32_words(sg.L);
+        for (int i = threadIdx.x; i < sg.n_pairs; i += kBlock) {
+            const uint32_t* r = rec + sg.rec_off + (int64_t)i * rw;
+            const double* rd = reinterpret_cast<const double*>(r);
+            const double r2f = fp64 ? rd[3] : (double)reinterpret_cast<const float*>(r)[6];
+            for (int d = 0; d < 3; ++d) {
+                v[d] = fmin(v[d], rd[d]);
+                v[3 + d] = fmax(v[3 + d], rd[d]);
+            }
+            v[6] = fmax(v[6], r2f);
+        }
+    }
+    for (int d = 0; d < 7; ++d) red[d][threadIdx.x] = v[d];
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            for (int d = 0; d < 3; ++d) red[d][threadIdx.x] = fmin(red[d][threadIdx.x], red[d][threadIdx.x + w]);
+            for (int d = 3; d < 7; ++d) red[d][threadIdx.x] = fmax(red[d][threadIdx.x], red[d][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < kSegBoxWords) {
+        double o = 0.0;
+        if (threadIdx.x < 6) o = red[threadIdx.x][0];
+        else if (threadIdx.x == 6) o = pairs ? red[6][0] : HUGE_VAL;
+        boxes[(int64_t)blockIdx.x * kSegBoxWords + threadIdx.x] = o;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_sum_splits(const double* __restrict__ part, int S,
                                                        int64_t n, double* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -745,6 +826,14 @@ int launch_sum_multi(const SumDesc* d, int n_desc, int64_t max_n, void* stream) 
     if (n_desc <= 0) return 0;
     const dim3 grid((unsigned)((max_n + kBlock - 1) / kBlock), (unsigned)n_desc);
     hipLaunchKernelGGL(k_sum_splits_multi, grid, dim3(kBlock), 0, static_cast<hipStream_t>(stream), d);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_segment_boxes(const Segment* segs, int n_segs, const uint32_t* rec, int fp64, double* boxes,
+                         void* stream) {
+    if (n_segs <= 0) return 0;
+    hipLaunchKernelGGL(k_segment_boxes, dim3((unsigned)n_segs), dim3(kBlock), 0, static_cast<hipStream_t>(stream),
+                       segs, rec, fp64, boxes);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
