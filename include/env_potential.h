@@ -420,9 +420,10 @@ env_status env_potential_export_pairs(const env_potential* h, int64_t cap, int32
  * clusters' member records of every fragment group) and the segment tables
  * of the split factors 1, 2, 4, ..., 256, concatenated (seg_words 4-byte
  * words, 8 per segment: L, count, first record word (int64), first and end
- * nucleus, flags, 0).  Call with NULL buffers to get the sizes; a buffer
- * smaller than the size (cap in words) gives ENV_E_ARG.  Waits for the
- * device.  ENV_E_STATE for a host handle. */
+ * nucleus, flags, index of the unsplit segment it comes from).  Call with
+ * NULL buffers to get the sizes; a buffer smaller than the size (cap in
+ * words) gives ENV_E_ARG.  Waits for the device.  ENV_E_STATE for a host
+ * handle. */
 env_status env_potential_export_image(const env_potential* h, uint32_t* rec, int64_t rec_cap,
                                       int64_t* rec_words, uint32_t* segs, int64_t seg_cap,
                                       int64_t* seg_words);

@@ -174,16 +174,31 @@ __device__ __forceinline__ double near_f64(const GLB uint32_t* __restrict__ r, d
 }
 
 // FP32C pairs of one L.  Record: P (3 doubles), r2far, p, c1, h[nc], D[nc].
-// FAR: every point-pair is known to be in the far field (segment box test),
-// so the per-pair near test is left out.
+// FAR: every point-pair is known to be in the far field, and every point C
+// is at least 2|C - O| from each pair centre (segment box test), where O is
+// the wave-uniform origin (ox, oy, oz).  The per-pair near test is left out
+// and X = P - C is formed as fl32(P - O) - fl32(C - O): one FP64 difference
+// per pair and coordinate for the whole wave instead of one per point.  Its
+// error is at most 2^-24 (|P - O| + |C - O| + |X|) <= 3 * 2^-24 |X| per
+// component (against 2^-24 |X| for the rounded exact difference).
 template <int L, int NP, bool FAR>
 __device__ __forceinline__ void pairs_f32(const GLB uint32_t* __restrict__ rec, int npairs,
                                           const double* cx, const double* cy, const double* cz,
+                                          double ox, double oy, double oz,
                                           const float* tab, double* ele) {
     constexpr int RW = rec32_words(L);
     if (npairs <= 0) return;
     Head<L, float> cur;
     if constexpr (kPipelined<L, float>) load_head32<L>(rec, cur);
+    float crx[NP], cry[NP], crz[NP];
+    if constexpr (FAR) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            crx[k] = (float)(cx[k] - ox);
+            cry[k] = (float)(cy[k] - oy);
+            crz[k] = (float)(cz[k] - oz);
+        }
+    }
     // tiles of kTile pairs: FP32 partial sums, promoted to FP64 per tile
     for (int i0 = 0; i0 < npairs; i0 += kTile) {
         const int i1 = min(i0 + kTile, npairs);
@@ -198,12 +213,24 @@ __device__ __forceinline__ void pairs_f32(const GLB uint32_t* __restrict__ rec, 
             for (; i < i1; ++i) {
                 if constexpr (kPipelined<L, float>) load_head32<L>(rec + (int64_t)min(i + 1, npairs - 1) * RW, nxt);
                 else load_head32<L>(rec + (int64_t)i * RW, cur);
+                if constexpr (FAR) {
+                    const float prx = (float)(cur.px - ox), pry = (float)(cur.py - oy),
+                                prz = (float)(cur.pz - oz);
 #pragma unroll
-                for (int k = 0; k < NP; ++k) {
-                    X[k] = (float)(cur.px - cx[k]);
-                    Y[k] = (float)(cur.py - cy[k]);
-                    Z[k] = (float)(cur.pz - cz[k]);
-                    r2[k] = __builtin_fmaf(X[k], X[k], __builtin_fmaf(Y[k], Y[k], Z[k] * Z[k]));
+                    for (int k = 0; k < NP; ++k) {
+                        X[k] = prx - crx[k];
+                        Y[k] = pry - cry[k];
+                        Z[k] = prz - crz[k];
+                        r2[k] = __builtin_fmaf(X[k], X[k], __builtin_fmaf(Y[k], Y[k], Z[k] * Z[k]));
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < NP; ++k) {
+                        X[k] = (float)(cur.px - cx[k]);
+                        Y[k] = (float)(cur.py - cy[k]);
+                        Z[k] = (float)(cur.pz - cz[k]);
+                        r2[k] = __builtin_fmaf(X[k], X[k], __builtin_fmaf(Y[k], Y[k], Z[k] * Z[k]));
+                    }
                 }
                 if constexpr (!FAR) {
                     float m = r2[0];
@@ -401,6 +428,14 @@ __device__ __forceinline__ int clusters_f64(const GLB uint32_t* __restrict__ rec
 
 // One workgroup's share: points of point block `pblock` against the pair
 // range of split `s` (all of it when S == 1).
+// The value of v in the first active lane, as a wave-uniform (scalar) value.
+__device__ __forceinline__ double wave_uniform(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 template <int NP, bool F64>
 __device__ __forceinline__ void block_work_impl(const PTS double* __restrict__ pts, int64_t n,
                                                 const GLB Segment* __restrict__ segs,
@@ -422,6 +457,8 @@ __device__ __forceinline__ void block_work_impl(const PTS double* __restrict__ p
         cz[k] = pts[3 * ic + 2];
         acc[k] = ve[k] = 0.0;
     }
+    // wave-uniform origin of the FP32C far form: the wave's first point
+    const double ox = wave_uniform(cx[0]), oy = wave_uniform(cy[0]), oz = wave_uniform(cz[0]);
     // Wave-uniform work loop over the segments of split s.  A cluster
     // segment is scanned cluster by cluster; a cluster with some point of
     // the wave inside its far-field radius hands its members (one run per L)
@@ -510,6 +547,7 @@ __device__ __forceinline__ void block_work_impl(const PTS double* __restrict__ p
             npairs = sn;
             // segment box test: every point of the wave beyond the largest
             // far-field radius of the segment's pairs
+            // (FP32C: and at least 2|C - O| from it, for the origin form)
             if (boxes && npairs > 0) {
                 const GLB double* bx = boxes + (int64_t)kSegBoxWords * sp->box;
                 const double lim = bx[6] * (1.0 + 1e-6);
@@ -519,7 +557,12 @@ __device__ __forceinline__ void block_work_impl(const PTS double* __restrict__ p
                     const double gx = fmax(0.0, fmax(bx[0] - cx[k], cx[k] - bx[3]));
                     const double gy = fmax(0.0, fmax(bx[1] - cy[k], cy[k] - bx[4]));
                     const double gz = fmax(0.0, fmax(bx[2] - cz[k], cz[k] - bx[5]));
-                    nearp |= __builtin_fma(gx, gx, __builtin_fma(gy, gy, gz * gz)) < lim;
+                    const double g2 = __builtin_fma(gx, gx, __builtin_fma(gy, gy, gz * gz));
+                    nearp |= g2 < lim;
+                    if constexpr (!F64) {
+                        const double ex = cx[k] - ox, ey = cy[k] - oy, ez = cz[k] - oz;
+                        nearp |= g2 < 4.0 * __builtin_fma(ex, ex, __builtin_fma(ey, ey, ez * ez));
+                    }
                 }
                 all_far = __builtin_amdgcn_ballot_w64(nearp) == 0;
             }
@@ -546,19 +589,19 @@ __device__ __forceinline__ void block_work_impl(const PTS double* __restrict__ p
         } else {
             if (all_far) {
                 switch (L) {
-                    case 0: pairs_f32<0, NP, true>(rec, npairs, cx, cy, cz, tab32, ve); break;
-                    case 1: pairs_f32<1, NP, true>(rec, npairs, cx, cy, cz, tab32, ve); break;
-                    case 2: pairs_f32<2, NP, true>(rec, npairs, cx, cy, cz, tab32, ve); break;
-                    case 3: pairs_f32<3, NP, true>(rec, npairs, cx, cy, cz, tab32, ve); break;
-                    default: pairs_f32<4, NP, true>(rec, npairs, cx, cy, cz, tab32, ve); break;
+                    case 0: pairs_f32<0, NP, true>(rec, npairs, cx, cy, cz, ox, oy, oz, tab32, ve); break;
+                    case 1: pairs_f32<1, NP, true>(rec, npairs, cx, cy, cz, ox, oy, oz, tab32, ve); break;
+                    case 2: pairs_f32<2, NP, true>(rec, npairs, cx, cy, cz, ox, oy, oz, tab32, ve); break;
+                    case 3: pairs_f32<3, NP, true>(rec, npairs, cx, cy, cz, ox, oy, oz, tab32, ve); break;
+                    default: pairs_f32<4, NP, true>(rec, npairs, cx, cy, cz, ox, oy, oz, tab32, ve); break;
                 }
             } else {
                 switch (L) {
-                    case 0: pairs_f32<0, NP, false>(rec, npairs, cx, cy, cz, tab32, ve); break;
-                    case 1: pairs_f32<1, NP, false>(rec, npairs, cx, cy, cz, tab32, ve); break;
-                    case 2: pairs_f32<2, NP, false>(rec, npairs, cx, cy, cz, tab32, ve); break;
-                    case 3: pairs_f32<3, NP, false>(rec, npairs, cx, cy, cz, tab32, ve); break;
-                    default: pairs_f32<4, NP, false>(rec, npairs, cx, cy, cz, tab32, ve); break;
+                    case 0: pairs_f32<0, NP, false>(rec, npairs, cx, cy, cz, ox, oy, oz, tab32, ve); break;
+                    case 1: pairs_f32<1, NP, false>(rec, npairs, cx, cy, cz, ox, oy, oz, tab32, ve); break;
+                    case 2: pairs_f32<2, NP, false>(rec, npairs, cx, cy, cz, ox, oy, oz, tab32, ve); break;
+                    case 3: pairs_f32<3, NP, false>(rec, npairs, cx, cy, cz, ox, oy, oz, tab32, ve); break;
+                    default: pairs_f32<4, NP, false>(rec, npairs, cx, cy, cz, ox, oy, oz, tab32, ve); break;
                 }
             }
         }

@@ -1,9 +1,11 @@
 """Segment far-field boxes: an evaluation that skips the per-pair near test
-for every segment whose box all points of a wave are beyond gives the same
-bits as one that tests every pair (ENVPOT_NO_FARBOX=1 at create), in both
-precisions, on the mid and 5000-atom workloads, batched, without allocation,
-and with points far outside the molecule (every segment all far) and inside
-it (few segments all far)."""
+for every segment whose box all points of a wave are beyond agrees with one
+that tests every pair (ENVPOT_NO_FARBOX=1 at create): FP64 bit for bit;
+FP32C, which also forms the coordinate differences of such segments from a
+wave origin (at most 3 FP32 ulps of |X| instead of 1), within 2e-6 Ha.  On
+the mid and 5000-atom workloads, batched, without allocation, and with
+points far outside the molecule (every segment all far) and inside it (few
+segments all far)."""
 import os
 
 import numpy as np
@@ -39,15 +41,26 @@ def _eval(E, pts):
     return v.cpu().numpy()
 
 
-def _check(A, B, pts):
-    va, vb = _eval(A, pts), _eval(B, pts)
-    bad = np.flatnonzero(va != vb)
-    assert bad.size == 0, f"{bad.size} of {va.size} potentials differ, first at {bad[:8]}"
+TOL32 = 2e-6  # Ha: FP32C origin form against the rounded exact difference
+
+
+def _agree(va, vb, precision, what=""):
+    if precision == "fp64":
+        bad = np.flatnonzero(va != vb)
+        assert bad.size == 0, f"{what}: {bad.size} of {va.size} potentials differ, first at {bad[:8]}"
+    else:
+        d = np.abs(va - vb)
+        print(f"[farbox] {what} fp32c max |diff| {d.max():.3e} Ha, rms {np.sqrt(np.mean(d * d)):.3e}", flush=True)
+        assert d.max() <= TOL32
+
+
+def _check(A, B, pts, precision, what=""):
+    _agree(_eval(A, pts), _eval(B, pts), precision, what)
 
 
 @pytest.mark.parametrize("precision", ["fp32c", "fp64"])
 @pytest.mark.parametrize("where", ["workload", "far_outside", "mixed"])
-def test_mid_boxes_same_bits(precision, where):
+def test_mid_boxes_agree(precision, where):
     print(f"[farbox] mid {precision} {where}", flush=True)
     env, pts = _workload("mid", 8192)
     if where == "far_outside":
@@ -58,25 +71,25 @@ def test_mid_boxes_same_bits(precision, where):
         pts = np.concatenate([pts[:4000], rng.uniform(lo, hi, (3000, 3)), pts[4000:5001] + 15.0])
     A, B = _pair(env, precision=precision, neutralize=True)
     try:
-        _check(A, B, pts)
+        _check(A, B, pts, precision, f"mid {where}")
     finally:
         A.close()
         B.close()
 
 
 @pytest.mark.parametrize("precision", ["fp32c", "fp64"])
-def test_large_boxes_same_bits(precision):
+def test_large_boxes_agree(precision):
     print(f"[farbox] large {precision}", flush=True)
     env, pts = _workload("large", 65536)
     A, B = _pair(env, precision=precision, neutralize=True)
     try:
-        _check(A, B, pts)
+        _check(A, B, pts, precision, "large")
     finally:
         A.close()
         B.close()
 
 
-def test_batched_and_noalloc_boxes_same_bits():
+def test_batched_and_noalloc_boxes_agree():
     import torch
     from paper_1011_4687_amd.envpot import Batch
     print("[farbox] batched and noalloc", flush=True)
@@ -90,7 +103,7 @@ def test_batched_and_noalloc_boxes_same_bits():
         oa, ob = ba.eval(x), bb.eval(x)
         torch.cuda.synchronize()
         for u, v in zip(oa, ob):
-            assert torch.equal(u, v)
+            _agree(u.cpu().numpy(), v.cpu().numpy(), "fp32c", "batched")
         n = 3000
         xa = torch.from_numpy(pts[:n]).cuda()
         ua = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -98,7 +111,7 @@ def test_batched_and_noalloc_boxes_same_bits():
         A.eval_noalloc(xa, ua)
         B.eval_noalloc(xa, ub)
         torch.cuda.synchronize()
-        assert torch.equal(ua, ub)
+        _agree(ua.cpu().numpy(), ub.cpu().numpy(), "fp32c", "noalloc")
     finally:
         ba.close()
         bb.close()
