@@ -191,6 +191,7 @@ __device__ __forceinline__ void pairs_f32(const GLB uint32_t* __restrict__ rec, 
     Head<L, float> cur;
     if constexpr (kPipelined<L, float>) load_head32<L>(rec, cur);
     float crx[NP], cry[NP], crz[NP];
+    double oxv = ox, oyv = oy, ozv = oz;
     if constexpr (FAR) {
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
@@ -198,6 +199,10 @@ __device__ __forceinline__ void pairs_f32(const GLB uint32_t* __restrict__ rec, 
             cry[k] = (float)(cy[k] - oy);
             crz[k] = (float)(cz[k] - oz);
         }
+        // the origin in vector registers for the loop: an FP64 add takes one
+        // scalar operand, and the pair centre is already one (an empty asm
+        // with register constraints only; it emits no instruction)
+        asm("" : "+v"(oxv), "+v"(oyv), "+v"(ozv));
     }
     // tiles of kTile pairs: FP32 partial sums, promoted to FP64 per tile
     for (int i0 = 0; i0 < npairs; i0 += kTile) {
@@ -214,8 +219,8 @@ __device__ __forceinline__ void pairs_f32(const GLB uint32_t* __restrict__ rec, 
                 if constexpr (kPipelined<L, float>) load_head32<L>(rec + (int64_t)min(i + 1, npairs - 1) * RW, nxt);
                 else load_head32<L>(rec + (int64_t)i * RW, cur);
                 if constexpr (FAR) {
-                    const float prx = (float)(cur.px - ox), pry = (float)(cur.py - oy),
-                                prz = (float)(cur.pz - oz);
+                    const float prx = (float)(cur.px - oxv), pry = (float)(cur.py - oyv),
+                                prz = (float)(cur.pz - ozv);
 #pragma unroll
                     for (int k = 0; k < NP; ++k) {
                         X[k] = prx - crx[k];
