@@ -76,13 +76,14 @@ struct Segment {
     int32_t box;         // the unsplit segment it comes from: its box in EvalArgs::boxes
 };
 
-// Box of an unsplit segment of pairs, 8 doubles: the smallest and largest
-// x, y, z of its pair centres, the largest r2far of its pairs (as stored),
-// and a pad.  A wave whose every point is farther from the box than
-// sqrt(r2far max) (with a margin of 1e-6 relative, more than the FP32
-// rounding of |X|^2) has all its point-pairs of the segment in the far
-// field, so the kernels run them without the per-pair near test; the
-// results are the same bits.  Cluster segments get r2far max = +inf.
+// Box of an unsplit segment, 8 doubles: the smallest and largest x, y, z of
+// its pair (or cluster) centres, the largest r2far (as stored), and a pad.
+// A wave whose every point is farther from the box than sqrt(r2far max)
+// (with a margin of 1e-6 relative, more than the FP32 rounding of |X|^2)
+// has all its point-pairs of the segment in the far field, so the kernels
+// run them without the per-pair near test (FP32C: with X from the wave
+// origin where every point is also at least 2|C - O| from the box).
+// Empty segments get r2far max = +inf.
 constexpr int kSegBoxWords = 8;
 constexpr int32_t kSegEndGroup = 1;
 constexpr int32_t kSegCluster = 2;
@@ -208,7 +209,7 @@ void build_boys_tables(std::vector<float>& t32, std::vector<double>& t64, BoysPa
 int launch_potential(const EvalArgs& a, int S, int precision, int np, void* stream);
 int launch_sum_splits(const double* partial, int S, int64_t n, double* out, void* stream);
 // Boxes (kSegBoxWords doubles each) of the unsplit segments segs[0, n_segs),
-// one workgroup per segment; cluster and empty segments get r2far max = +inf.
+// one workgroup per segment; empty segments get r2far max = +inf.
 int launch_segment_boxes(const Segment* segs, int n_segs, const uint32_t* rec, int fp64, double* boxes,
                          void* stream);
 int launch_persistent(const BatchArgs& b, int grid, int precision, int np, void* stream);

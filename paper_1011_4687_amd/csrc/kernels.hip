@@ -350,8 +350,14 @@ __device__ __forceinline__ void pairs_f64(const GLB uint32_t* __restrict__ rec, 
 // whose far-field radius no point of the wave is inside is evaluated once
 // from its merged coefficients.  Stops at the first cluster with a point
 // inside that radius and returns its index (n when there is none); the
-// caller then evaluates that cluster's members pair by pair.
-template <int LC, int NP>
+// caller then evaluates that cluster's members pair by pair.  FAR: every
+// cluster is known to be far for every point of the wave (segment box
+// test), so the near test is left out.  X stays the rounded exact
+// difference here: a cluster holds a whole atom's band of charge in one
+// term, so the extra rounding of the wave-origin form (an independent
+// 2^-24 |P - O| per cluster) would not average out over many small terms
+// as it does for pairs.
+template <int LC, int NP, bool FAR>
 __device__ __forceinline__ int clusters_f32(const GLB uint32_t* __restrict__ rec, int i, int n,
                                             const double* cx, const double* cy, const double* cz,
                                             double* ele) {
@@ -379,7 +385,7 @@ __device__ __forceinline__ int clusters_f32(const GLB uint32_t* __restrict__ rec
             r2[k] = __builtin_fmaf(X[k], X[k], __builtin_fmaf(Y[k], Y[k], Z[k] * Z[k]));
             nearp |= r2[k] < r2far;
         }
-        if (__builtin_amdgcn_ballot_w64(nearp) != 0) break;
+        if (!FAR && __builtin_amdgcn_ballot_w64(nearp) != 0) break;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
             const float ri = rsqrt_raw(r2[k]);
@@ -399,7 +405,7 @@ __device__ __forceinline__ int clusters_f32(const GLB uint32_t* __restrict__ rec
     return i;
 }
 
-template <int LC, int NP>
+template <int LC, int NP, bool FAR>
 __device__ __forceinline__ int clusters_f64(const GLB uint32_t* __restrict__ rec, int i, int n,
                                             const double* cx, const double* cy, const double* cz,
                                             double* ele) {
@@ -420,7 +426,7 @@ __device__ __forceinline__ int clusters_f64(const GLB uint32_t* __restrict__ rec
             r2[k] = __builtin_fma(X[k], X[k], __builtin_fma(Y[k], Y[k], Z[k] * Z[k]));
             nearp |= r2[k] < r2far;
         }
-        if (__builtin_amdgcn_ballot_w64(nearp) != 0) break;
+        if (!FAR && __builtin_amdgcn_ballot_w64(nearp) != 0) break;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
             const double ri = rsqrt_far(r2[k]);
@@ -431,8 +437,6 @@ __device__ __forceinline__ int clusters_f64(const GLB uint32_t* __restrict__ rec
     return i;
 }
 
-// One workgroup's share: points of point block `pblock` against the pair
-// range of split `s` (all of it when S == 1).
 // The value of v in the first active lane, as a wave-uniform (scalar) value.
 __device__ __forceinline__ double wave_uniform(double v) {
     const uint64_t b = __builtin_bit_cast(uint64_t, v);
@@ -441,6 +445,8 @@ __device__ __forceinline__ double wave_uniform(double v) {
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// One workgroup's share: points of point block `pblock` against the pair
+// range of split `s` (all of it when S == 1).
 template <int NP, bool F64>
 __device__ __forceinline__ void block_work_impl(const PTS double* __restrict__ pts, int64_t n,
                                                 const GLB Segment* __restrict__ segs,
@@ -473,6 +479,7 @@ __device__ __forceinline__ void block_work_impl(const PTS double* __restrict__ p
     bool fold = false;
     const GLB uint32_t* crec = recs;   // cluster segment in progress: clusters [ci, cn) of merged L lc
     int ci = 0, cn = 0, lc = 0;
+    bool cfar = false;                 // ... and all its clusters far for every point of the wave
     const GLB uint32_t* mtab = recs;   // member table of the cluster being expanded
     uint32_t pend = 0;                 // its member runs (bit L) not yet evaluated
     for (;;) {
@@ -487,11 +494,16 @@ __device__ __forceinline__ void block_work_impl(const PTS double* __restrict__ p
         } else if (ci < cn) {
             if constexpr (F64) {
                 switch (lc) {
-                    case 0: ci = clusters_f64<0, NP>(crec, ci, cn, cx, cy, cz, ve); break;
-                    case 1: ci = clusters_f64<1, NP>(crec, ci, cn, cx, cy, cz, ve); break;
-                    case 2: ci = clusters_f64<2, NP>(crec, ci, cn, cx, cy, cz, ve); break;
-                    case 3: ci = clusters_f64<3, NP>(crec, ci, cn, cx, cy, cz, ve); break;
-                    default: ci = clusters_f64<4, NP>(crec, ci, cn, cx, cy, cz, ve); break;
+                    case 0: ci = cfar ? clusters_f64<0, NP, true>(crec, ci, cn, cx, cy, cz, ve)
+                                        : clusters_f64<0, NP, false>(crec, ci, cn, cx, cy, cz, ve); break;
+                    case 1: ci = cfar ? clusters_f64<1, NP, true>(crec, ci, cn, cx, cy, cz, ve)
+                                        : clusters_f64<1, NP, false>(crec, ci, cn, cx, cy, cz, ve); break;
+                    case 2: ci = cfar ? clusters_f64<2, NP, true>(crec, ci, cn, cx, cy, cz, ve)
+                                        : clusters_f64<2, NP, false>(crec, ci, cn, cx, cy, cz, ve); break;
+                    case 3: ci = cfar ? clusters_f64<3, NP, true>(crec, ci, cn, cx, cy, cz, ve)
+                                        : clusters_f64<3, NP, false>(crec, ci, cn, cx, cy, cz, ve); break;
+                    default: ci = cfar ? clusters_f64<4, NP, true>(crec, ci, cn, cx, cy, cz, ve)
+                                        : clusters_f64<4, NP, false>(crec, ci, cn, cx, cy, cz, ve); break;
                 }
                 if (ci < cn) {
                     const GLB uint32_t* c = crec + (int64_t)ci * cl64_words(lc);
@@ -501,11 +513,16 @@ __device__ __forceinline__ void block_work_impl(const PTS double* __restrict__ p
                 }
             } else {
                 switch (lc) {
-                    case 0: ci = clusters_f32<0, NP>(crec, ci, cn, cx, cy, cz, ve); break;
-                    case 1: ci = clusters_f32<1, NP>(crec, ci, cn, cx, cy, cz, ve); break;
-                    case 2: ci = clusters_f32<2, NP>(crec, ci, cn, cx, cy, cz, ve); break;
-                    case 3: ci = clusters_f32<3, NP>(crec, ci, cn, cx, cy, cz, ve); break;
-                    default: ci = clusters_f32<4, NP>(crec, ci, cn, cx, cy, cz, ve); break;
+                    case 0: ci = cfar ? clusters_f32<0, NP, true>(crec, ci, cn, cx, cy, cz, ve)
+                                        : clusters_f32<0, NP, false>(crec, ci, cn, cx, cy, cz, ve); break;
+                    case 1: ci = cfar ? clusters_f32<1, NP, true>(crec, ci, cn, cx, cy, cz, ve)
+                                        : clusters_f32<1, NP, false>(crec, ci, cn, cx, cy, cz, ve); break;
+                    case 2: ci = cfar ? clusters_f32<2, NP, true>(crec, ci, cn, cx, cy, cz, ve)
+                                        : clusters_f32<2, NP, false>(crec, ci, cn, cx, cy, cz, ve); break;
+                    case 3: ci = cfar ? clusters_f32<3, NP, true>(crec, ci, cn, cx, cy, cz, ve)
+                                        : clusters_f32<3, NP, false>(crec, ci, cn, cx, cy, cz, ve); break;
+                    default: ci = cfar ? clusters_f32<4, NP, true>(crec, ci, cn, cx, cy, cz, ve)
+                                        : clusters_f32<4, NP, false>(crec, ci, cn, cx, cy, cz, ve); break;
                 }
                 if (ci < cn) {
                     const GLB uint32_t* c = crec + (int64_t)ci * cl32_words(lc);
@@ -540,20 +557,11 @@ __device__ __forceinline__ void block_work_impl(const PTS double* __restrict__ p
                 }
             }
             fold = (sf & kSegEndGroup) != 0;
-            if (sf & kSegCluster) {
-                crec = recs + so;
-                ci = 0;
-                cn = sn;
-                lc = sL;
-                continue;
-            }
-            L = sL;
-            rec = recs + so;
-            npairs = sn;
             // segment box test: every point of the wave beyond the largest
-            // far-field radius of the segment's pairs
-            // (FP32C: and at least 2|C - O| from it, for the origin form)
-            if (boxes && npairs > 0) {
+            // far-field radius of the segment's pairs (or clusters)
+            // (FP32C: and at least 2|C - O| from it, for the origin form of
+            // pair segments)
+            if (boxes && sn > 0) {
                 const GLB double* bx = boxes + (int64_t)kSegBoxWords * sp->box;
                 const double lim = bx[6] * (1.0 + 1e-6);
                 bool nearp = false;
@@ -571,6 +579,18 @@ __device__ __forceinline__ void block_work_impl(const PTS double* __restrict__ p
                 }
                 all_far = __builtin_amdgcn_ballot_w64(nearp) == 0;
             }
+            if (sf & kSegCluster) {
+                crec = recs + so;
+                ci = 0;
+                cn = sn;
+                lc = sL;
+                cfar = all_far;
+                all_far = false;
+                continue;
+            }
+            L = sL;
+            rec = recs + so;
+            npairs = sn;
         }
         if constexpr (F64) {
             const GLB double* tab = boys64;
@@ -649,6 +669,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     block_work<NP, F64>(a, blockIdx.x, blockIdx.y, tab32);
 }
 
+// A copy of *p read word by word through the constant address space.
+template <class T>
+__device__ __forceinline__ T load_const(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "whole words");
+    T v;
+    const GLB uint32_t* src = glb(reinterpret_cast<const uint32_t*>(p));
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+    for (int i = 0; i < int(sizeof(T) / 4); ++i) dst[i] = src[i];
+    return v;
+}
+
 // Persistent batched kernel: every workgroup takes work items (instance,
 // point block, pair split) from a global counter until the queue is empty.
 // Items are sorted by decreasing estimated cost, so the long ones start
@@ -668,8 +700,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         const int64_t it = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(it_v >> 32)) << 32) |
                                      (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)it_v));
         if (it >= b.n_items) break;
-        const BatchItem w = b.items[it];
-        const EvalArgs a = b.args[w.inst];
+        // item and instance arguments through the constant address space:
+        // scalar loads the compiler may repeat instead of holding the values
+        const BatchItem w = load_const(b.items + it);
+        const EvalArgs a = load_const(b.args + w.inst);
         block_work<NP, F64>(a, w.pblock, w.split, tab32);
     }
 }
@@ -740,18 +774,22 @@ __global__ __launch_bounds__(kBlock) void k_sum_splits_multi(const SumDesc* __re
     q.out[i] = s;
 }
 
-// Box of an unsplit segment of pairs (one workgroup per segment): the
-// smallest and largest pair centre coordinates and the largest stored r2far.
-// Cluster and empty segments get r2far max = +inf (never all far).
+// Box of an unsplit segment (one workgroup per segment): the smallest and
+// largest pair (or cluster) centre coordinates and the largest stored r2far
+// (a cluster record stores the largest of its members').  Empty segments get
+// r2far max = +inf (never all far).
 __global__ __launch_bounds__(kBlock) void k_segment_boxes(const Segment* __restrict__ segs,
                                                           const uint32_t* __restrict__ rec, int fp64,
                                                           double* __restrict__ boxes) {
     __shared__ double red[7][kBlock];
     const Segment sg = segs[blockIdx.x];
-    const bool pairs = !(sg.flags & kSegCluster) && sg.n_pairs > 0;
+    const bool pairs = sg.n_pairs > 0;
+    const bool cl = (sg.flags & kSegCluster) != 0;
     double v[7] = {HUGE_VAL, HUGE_VAL, HUGE_VAL, -HUGE_VAL, -HUGE_VAL, -HUGE_VAL, 0.0};
     if (pairs) {
-        const int rw = fp64 ? rec64_words(sg.L) : rec32_words(sg.L);
+        // centre: doubles 0-2 of every record; r2far: double 3 (FP64) or
+        // float word 6 (FP32C), in pair and cluster records alike
+        const int rw = cl ? (fp64 ? cl64_words(sg.L) : cl32_words(sg.L)) : (fp64 ? rec64_words(sg.L) : rec32_words(sg.L));
         for (int i = threadIdx.x; i < sg.n_pairs; i += kBlock) {
             const uint32_t* r = rec + sg.rec_off + (int64_t)i * rw;
             const double* rd = reinterpret_cast<const double*>(r);
