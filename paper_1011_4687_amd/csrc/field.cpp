@@ -115,6 +115,7 @@ env_status field_core(env_potential* h, const double* points, int64_t n, double*
     a.rec = h->d_rec;
     a.nuc = h->d_nuc;
     a.boys = h->d_boys_field;
+    a.boxes = h->use_boxes ? h->d_boxes : nullptr;
     a.fp = h->fp;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (S == 1) {

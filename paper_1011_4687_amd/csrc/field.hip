@@ -176,7 +176,11 @@ __device__ __forceinline__ void load_fhead(const GLB uint32_t* __restrict__ r, F
 template <int L>
 constexpr bool kFPipelined = L <= 2;
 
-template <int L, int NP>
+// FAR: every point-pair of the run is in the field's far region (segment
+// box test): no near test.  X stays the rounded exact difference: at two
+// points per lane the potential kernel's wave-origin form would cost as many
+// instructions per pair as it saves.
+template <int L, int NP, bool FAR>
 __device__ __forceinline__ void pairs_f32(const GLB uint32_t* __restrict__ rec, int npairs, const double* cx,
                                           const double* cy, const double* cz, const float* tab, float ratio,
                                           double (*ge)[4]) {
@@ -209,7 +213,7 @@ __device__ __forceinline__ void pairs_f32(const GLB uint32_t* __restrict__ rec, 
                 r2[k] = __builtin_fmaf(X[k], X[k], __builtin_fmaf(Y[k], Y[k], Z[k] * Z[k]));
                 nearp |= r2[k] < r2f;
             }
-            if (__builtin_amdgcn_ballot_w64(nearp) == 0) {
+            if (FAR || __builtin_amdgcn_ballot_w64(nearp) == 0) {
 #pragma unroll
                 for (int k = 0; k < NP; ++k) far_acc<L, float>(h, X[k], Y[k], Z[k], rsqrt_refined(r2[k]), t[k]);
             } else {
@@ -251,7 +255,9 @@ __device__ __forceinline__ void load_fhead64(const GLB uint32_t* __restrict__ r,
     for (int c = 0; c < kNComp[L]; ++c) o.h[c] = rd[kRec64Head + c];
 }
 
-template <int L, int NP>
+// FAR: every point-pair of the run is in the field's far region (segment
+// box test): no near test.
+template <int L, int NP, bool FAR>
 __device__ __forceinline__ void pairs_f64(const GLB uint32_t* __restrict__ rec, int npairs, const double* cx,
                                           const double* cy, const double* cz, const GLB double* __restrict__ tab,
                                           double ratio, double (*ge)[4]) {
@@ -278,7 +284,7 @@ __device__ __forceinline__ void pairs_f64(const GLB uint32_t* __restrict__ rec, 
             r2[k] = __builtin_fma(X[k], X[k], __builtin_fma(Y[k], Y[k], Z[k] * Z[k]));
             nearp |= r2[k] < r2f;
         }
-        if (__builtin_amdgcn_ballot_w64(nearp) == 0) {
+        if (FAR || __builtin_amdgcn_ballot_w64(nearp) == 0) {
 #pragma unroll
             for (int k = 0; k < NP; ++k) far_acc<L, double>(h, X[k], Y[k], Z[k], rsqrt_far(r2[k]), ge[k]);
         } else {
@@ -383,7 +389,8 @@ __device__ __forceinline__ void field_block(const PTS double* __restrict__ pts, 
                                             const GLB int32_t* __restrict__ split,
                                             const GLB uint32_t* __restrict__ recs,
                                             const GLB double* __restrict__ nuc,
-                                            const GLB double* __restrict__ boys64, const FieldParams& fp,
+                                            const GLB double* __restrict__ boys64,
+                                            const GLB double* __restrict__ boxes, const FieldParams& fp,
                                             double* __restrict__ out, int64_t pblock, int s, const float* tab32) {
     const int64_t base = pblock * (kBlock * NP) + threadIdx.x;
     double cx[NP], cy[NP], cz[NP], acc[NP][4], ge[NP][4];
@@ -408,6 +415,7 @@ __device__ __forceinline__ void field_block(const PTS double* __restrict__ pts, 
     for (;;) {
         int L, npairs;
         const GLB uint32_t* rec;
+        bool all_far = false;  // member runs: tested pair by pair
         if (pend != 0) {
             L = __builtin_ctz(pend);
             pend &= pend - 1;
@@ -463,22 +471,58 @@ __device__ __forceinline__ void field_block(const PTS double* __restrict__ pts, 
             L = sL;
             rec = recs + so;
             npairs = sn;
+            // segment box test: every point of the wave beyond the largest
+            // field radius of the segment's pairs (r2far max times the
+            // field's ratio for L)
+            if (boxes && npairs > 0) {
+                const GLB double* bx = boxes + (int64_t)kSegBoxWords * sp->box;
+                const double lim = bx[6] * (F64 ? fp.ratio64[L] : (double)fp.ratio32[L]) * (1.0 + 1e-6);
+                bool nearp = false;
+#pragma unroll
+                for (int k = 0; k < NP; ++k) {
+                    const double gx = fmax(0.0, fmax(bx[0] - cx[k], cx[k] - bx[3]));
+                    const double gy = fmax(0.0, fmax(bx[1] - cy[k], cy[k] - bx[4]));
+                    const double gz = fmax(0.0, fmax(bx[2] - cz[k], cz[k] - bx[5]));
+                    nearp |= __builtin_fma(gx, gx, __builtin_fma(gy, gy, gz * gz)) < lim;
+                }
+                all_far = __builtin_amdgcn_ballot_w64(nearp) == 0;
+            }
         }
         if constexpr (F64) {
-            switch (L) {
-                case 0: pairs_f64<0, NP>(rec, npairs, cx, cy, cz, boys64, fp.ratio64[0], ge); break;
-                case 1: pairs_f64<1, NP>(rec, npairs, cx, cy, cz, boys64, fp.ratio64[1], ge); break;
-                case 2: pairs_f64<2, NP>(rec, npairs, cx, cy, cz, boys64, fp.ratio64[2], ge); break;
-                case 3: pairs_f64<3, NP>(rec, npairs, cx, cy, cz, boys64, fp.ratio64[3], ge); break;
-                default: pairs_f64<4, NP>(rec, npairs, cx, cy, cz, boys64, fp.ratio64[4], ge); break;
+            if (all_far) {
+                switch (L) {
+                    case 0: pairs_f64<0, NP, true>(rec, npairs, cx, cy, cz, boys64, fp.ratio64[0], ge); break;
+                    case 1: pairs_f64<1, NP, true>(rec, npairs, cx, cy, cz, boys64, fp.ratio64[1], ge); break;
+                    case 2: pairs_f64<2, NP, true>(rec, npairs, cx, cy, cz, boys64, fp.ratio64[2], ge); break;
+                    case 3: pairs_f64<3, NP, true>(rec, npairs, cx, cy, cz, boys64, fp.ratio64[3], ge); break;
+                    default: pairs_f64<4, NP, true>(rec, npairs, cx, cy, cz, boys64, fp.ratio64[4], ge); break;
+                }
+            } else {
+                switch (L) {
+                    case 0: pairs_f64<0, NP, false>(rec, npairs, cx, cy, cz, boys64, fp.ratio64[0], ge); break;
+                    case 1: pairs_f64<1, NP, false>(rec, npairs, cx, cy, cz, boys64, fp.ratio64[1], ge); break;
+                    case 2: pairs_f64<2, NP, false>(rec, npairs, cx, cy, cz, boys64, fp.ratio64[2], ge); break;
+                    case 3: pairs_f64<3, NP, false>(rec, npairs, cx, cy, cz, boys64, fp.ratio64[3], ge); break;
+                    default: pairs_f64<4, NP, false>(rec, npairs, cx, cy, cz, boys64, fp.ratio64[4], ge); break;
+                }
             }
         } else {
-            switch (L) {
-                case 0: pairs_f32<0, NP>(rec, npairs, cx, cy, cz, tab32, fp.ratio32[0], ge); break;
-                case 1: pairs_f32<1, NP>(rec, npairs, cx, cy, cz, tab32, fp.ratio32[1], ge); break;
-                case 2: pairs_f32<2, NP>(rec, npairs, cx, cy, cz, tab32, fp.ratio32[2], ge); break;
-                case 3: pairs_f32<3, NP>(rec, npairs, cx, cy, cz, tab32, fp.ratio32[3], ge); break;
-                default: pairs_f32<4, NP>(rec, npairs, cx, cy, cz, tab32, fp.ratio32[4], ge); break;
+            if (all_far) {
+                switch (L) {
+                    case 0: pairs_f32<0, NP, true>(rec, npairs, cx, cy, cz, tab32, fp.ratio32[0], ge); break;
+                    case 1: pairs_f32<1, NP, true>(rec, npairs, cx, cy, cz, tab32, fp.ratio32[1], ge); break;
+                    case 2: pairs_f32<2, NP, true>(rec, npairs, cx, cy, cz, tab32, fp.ratio32[2], ge); break;
+                    case 3: pairs_f32<3, NP, true>(rec, npairs, cx, cy, cz, tab32, fp.ratio32[3], ge); break;
+                    default: pairs_f32<4, NP, true>(rec, npairs, cx, cy, cz, tab32, fp.ratio32[4], ge); break;
+                }
+            } else {
+                switch (L) {
+                    case 0: pairs_f32<0, NP, false>(rec, npairs, cx, cy, cz, tab32, fp.ratio32[0], ge); break;
+                    case 1: pairs_f32<1, NP, false>(rec, npairs, cx, cy, cz, tab32, fp.ratio32[1], ge); break;
+                    case 2: pairs_f32<2, NP, false>(rec, npairs, cx, cy, cz, tab32, fp.ratio32[2], ge); break;
+                    case 3: pairs_f32<3, NP, false>(rec, npairs, cx, cy, cz, tab32, fp.ratio32[3], ge); break;
+                    default: pairs_f32<4, NP, false>(rec, npairs, cx, cy, cz, tab32, fp.ratio32[4], ge); break;
+                }
             }
         }
     }
@@ -506,7 +550,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         __syncthreads();
     }
     field_block<NP, F64>(gpts(a.pts), a.n, glb(a.segs), glb(a.split), glb(a.rec), glb(a.nuc),
-                         glb(static_cast<const double*>(a.boys)), a.fp, a.out, blockIdx.x, blockIdx.y, tab32);
+                         glb(static_cast<const double*>(a.boys)), glb(a.boxes), a.fp, a.out, blockIdx.x,
+                         blockIdx.y, tab32);
 }
 
 }  // namespace

@@ -35,6 +35,7 @@ struct FieldArgs {
     const uint32_t* rec;     // pair and cluster records of the handle's precision
     const double* nuc;       // nuclei, 4 doubles each
     const void* boys;        // field Boys table of the handle's precision
+    const double* boxes;     // segment boxes (Segment::box), or nullptr: test every pair
     double* out;             // S == 1: [n][4] (V, Ex, Ey, Ez); S > 1: partials [S][n][4]
     FieldParams fp;
 };

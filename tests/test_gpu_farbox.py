@@ -117,3 +117,23 @@ def test_batched_and_noalloc_boxes_agree():
         bb.close()
         for E in (A, B, A2, B2):
             E.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32c", "fp64"])
+def test_field_boxes_agree(precision):
+    """The field kernel with segment boxes against every pair tested: bit for
+    bit in both precisions (the field keeps the exact coordinate difference
+    in all-far segments)."""
+    import torch
+    print(f"[farbox] field mid {precision}", flush=True)
+    env, pts = _workload("mid", 8192)
+    A, B = _pair(env, precision=precision, neutralize=True)
+    try:
+        x = torch.from_numpy(np.ascontiguousarray(pts)).cuda()
+        fa = A.eval_field(x).cpu().numpy()
+        fb = B.eval_field(x).cpu().numpy()
+        bad = np.flatnonzero((fa != fb).any(axis=1))
+        assert bad.size == 0, f"{bad.size} of {len(pts)} field rows differ, first at {bad[:8]}"
+    finally:
+        A.close()
+        B.close()
