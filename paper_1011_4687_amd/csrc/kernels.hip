@@ -558,9 +558,10 @@ __device__ __forceinline__ void block_work_impl(const PTS double* __restrict__ p
             }
             fold = (sf & kSegEndGroup) != 0;
             // segment box test: every point of the wave beyond the largest
-            // far-field radius of the segment's pairs (or clusters)
-            // (FP32C: and at least 2|C - O| from it, for the origin form of
-            // pair segments)
+            // far-field radius of the segment's pairs (or clusters), and for
+            // the FP32C origin form of pair segments at least 2|C - O| from
+            // the box
+            const bool cl = (sf & kSegCluster) != 0;
             if (boxes && sn > 0) {
                 const GLB double* bx = boxes + (int64_t)kSegBoxWords * sp->box;
                 const double lim = bx[6] * (1.0 + 1e-6);
@@ -572,14 +573,14 @@ __device__ __forceinline__ void block_work_impl(const PTS double* __restrict__ p
                     const double gz = fmax(0.0, fmax(bx[2] - cz[k], cz[k] - bx[5]));
                     const double g2 = __builtin_fma(gx, gx, __builtin_fma(gy, gy, gz * gz));
                     nearp |= g2 < lim;
-                    if constexpr (!F64) {
+                    if (!F64 && !cl) {
                         const double ex = cx[k] - ox, ey = cy[k] - oy, ez = cz[k] - oz;
                         nearp |= g2 < 4.0 * __builtin_fma(ex, ex, __builtin_fma(ey, ey, ez * ez));
                     }
                 }
                 all_far = __builtin_amdgcn_ballot_w64(nearp) == 0;
             }
-            if (sf & kSegCluster) {
+            if (cl) {
                 crec = recs + so;
                 ci = 0;
                 cn = sn;
