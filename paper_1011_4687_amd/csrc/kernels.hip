@@ -458,7 +458,10 @@ __device__ __forceinline__ void block_work_impl(const PTS double* __restrict__ p
                                                 double* __restrict__ out,
                                                 int64_t pblock, int s, const float* tab32) {
     const int64_t base = pblock * (kBlock * NP) + threadIdx.x;
-    double cx[NP], cy[NP], cz[NP], acc[NP], ve[NP];
+    // the FP64 result of each point lives in LDS (thread-private slots,
+    // touched once per fragment group): registers stay free for the loops
+    __shared__ double acc[NP * kBlock];
+    double cx[NP], cy[NP], cz[NP], ve[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
         const int64_t i = base + (int64_t)k * kBlock;
@@ -466,7 +469,7 @@ __device__ __forceinline__ void block_work_impl(const PTS double* __restrict__ p
         cx[k] = pts[3 * ic];
         cy[k] = pts[3 * ic + 1];
         cz[k] = pts[3 * ic + 2];
-        acc[k] = ve[k] = 0.0;
+        acc[k * kBlock + threadIdx.x] = ve[k] = 0.0;
     }
     // wave-uniform origin of the FP32C far form: the wave's first point
     const double ox = wave_uniform(cx[0]), oy = wave_uniform(cy[0]), oz = wave_uniform(cz[0]);
@@ -536,7 +539,7 @@ __device__ __forceinline__ void block_work_impl(const PTS double* __restrict__ p
             if (fold) {
 #pragma unroll
                 for (int k = 0; k < NP; ++k) {
-                    acc[k] -= ve[k];
+                    acc[k * kBlock + threadIdx.x] -= ve[k];
                     ve[k] = 0.0;
                 }
                 fold = false;
@@ -634,9 +637,9 @@ __device__ __forceinline__ void block_work_impl(const PTS double* __restrict__ p
     }
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-        acc[k] -= ve[k];
+        const double v = acc[k * kBlock + threadIdx.x] - ve[k];
         const int64_t i = base + (int64_t)k * kBlock;
-        if (i < n) out[(int64_t)s * n + i] = acc[k];
+        if (i < n) out[(int64_t)s * n + i] = v;
     }
 }
 
