@@ -183,6 +183,11 @@ env_status env_potential_create(const env_nucleus* nuclei, int32_t n_nuclei,
  * Calls of 32,768 points or more evaluate the points in a spatial (Morton)
  * order and write out in the caller's order (off while the stream is being
  * captured, or with ENVPOT_NO_SORT=1); the same call is bitwise repeatable.
+ * A wave of points that is beyond the largest far-field radius of a pair
+ * segment's bounding box runs that segment without the per-pair near test
+ * (FP32C: with the coordinate differences formed from the wave's first
+ * point, at most 3 FP32 ulps of |P - C|); ENVPOT_NO_FARBOX=1 at create turns
+ * this off (then FP64 gives the same bits, FP32C agrees to rounding).
  * A handle created with ENV_FORCE_CPU takes host pointers instead, ignores
  * the stream and returns after writing out (FP64, the host threads of the
  * paper's switch back to the CPU).
