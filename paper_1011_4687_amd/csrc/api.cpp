@@ -102,11 +102,11 @@ void choose_shape(const env_potential* h, int64_t n, int* np_out, int* k_out) {
         const int64_t waves = (n + 64 * np - 1) / (64 * np);
         const int64_t want = int64_t(h->cu_count) * 4 * (fp64 ? 48 : 24);
         while (k < kMaxSplitLog2 && waves * (int64_t(1) << k) < want) ++k;
-        // long pair lists: split further while one split holds more than 2^18
+        // long pair lists: split further while one split holds more than 2^17
         // pairs, within 2^27 partial sums (1 GiB) (5000 atoms, 1,048,576
-        // points: 64 splits 3.89 s FP32C / 6.29 s FP64 against 4.03 / 6.66 s
-        // with the 8 of the wave rule)
-        while (k < kMaxSplitLog2 && (h->info.n_pairs >> k) > (int64_t(1) << 18) &&
+        // points: 128 splits 3.230 s FP32C / 5.914 s FP64 against 3.248 /
+        // 6.271 s with 64 and 3.288 / 6.444 s with 32)
+        while (k < kMaxSplitLog2 && (h->info.n_pairs >> k) > (int64_t(1) << 17) &&
                (n << (k + 1)) <= (int64_t(1) << 27))
             ++k;
     }
