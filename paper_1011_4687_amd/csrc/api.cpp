@@ -81,6 +81,10 @@ env_status segment_boxes(env_potential* h, const std::vector<Segment>& base, boo
 
 namespace envpot {
 
+// Waves per SIMD that a single call's split factor aims for (both
+// precisions; the device-sized launch uses the same target).
+constexpr int64_t kWantWavesPerSimd = 48;
+
 void choose_shape(const env_potential* h, int64_t n, int* np_out, int* k_out) {
     const bool fp64 = h->precision == ENV_PREC_FP64;
     // a tuned shape for a point count within a factor 2 of n wins
@@ -96,11 +100,12 @@ void choose_shape(const env_potential* h, int64_t n, int* np_out, int* k_out) {
         k = best->klog;
     } else {
         np = fp64 ? 2 : 4;
-        // split factor: enough waves to keep ~24 (FP32C) or ~48 (FP64) per
-        // SIMD in flight over the run (mid, Morton order: FP64 34.3 ms with
-        // 64 splits against 35.3 ms with 32; FP32C best at 24)
+        // split factor: enough waves to keep ~48 per SIMD in flight over the
+        // run (mid, Morton order: FP32C 18.7 ms with 128 splits against
+        // 19.2 ms with 64 and 20.1 ms with 32; FP64 33.6 ms with 64 or 128
+        // against 34.5 ms with 32)
         const int64_t waves = (n + 64 * np - 1) / (64 * np);
-        const int64_t want = int64_t(h->cu_count) * 4 * (fp64 ? 48 : 24);
+        const int64_t want = int64_t(h->cu_count) * 4 * kWantWavesPerSimd;
         while (k < kMaxSplitLog2 && waves * (int64_t(1) << k) < want) ++k;
         // long pair lists: split further while one split holds more than 2^17
         // pairs, within 2^27 partial sums (1 GiB) (5000 atoms, 1,048,576
@@ -150,7 +155,7 @@ env_status eval_devsized(env_potential* h, const double* points, const int64_t* 
         d.split_off[k] = h->split_off[k];
     }
     d.part_cap = part_cap;
-    d.want_waves = int64_t(h->cu_count) * 4 * (fp64 ? 48 : 24);
+    d.want_waves = int64_t(h->cu_count) * 4 * kWantWavesPerSimd;  // the rule of choose_shape
     d.counter = counter;
     DeviceGuard g(h->device);
     if (launch_potential_devsized(d, devsized_grid(h->precision, h->cu_count), h->precision, np, stream) != 0 ||
