@@ -120,13 +120,20 @@ env_status to_device(const std::vector<T>& v, T** dst) {
 }
 
 // Points per lane and cell-split factor of a batched evaluation: enough
-// waves in flight (about 24 per SIMD) over the whole launch.
+// waves in flight over the whole launch, about 24 per SIMD in FP32C and 48
+// in FP64 (268,398 cells, 131,072 points: FP32C 11.0 ms with 64 splits,
+// 11.1 ms median with 128; FP64 15.1 ms with 64 against 15.6 ms with 32).
 void cells_shape(const env_cells* h, int64_t n, int* np, int* klog) {
-    *np = h->precision == ENV_PREC_FP64 ? 2 : 4;
+    const bool fp64 = h->precision == ENV_PREC_FP64;
+    *np = fp64 ? 2 : 4;
     const int64_t waves = (n + 64 * *np - 1) / (64 * *np);
-    const int64_t want = int64_t(h->cu_count) * 4 * 24;
+    const int64_t want = int64_t(h->cu_count) * 4 * (fp64 ? 48 : 24);
     int k = 0;
     while (k < envpot::kMaxSplitLog2 && waves * (int64_t(1) << k) < want && (h->m >> (k + 1)) >= 64) ++k;
+    if (const char* e = std::getenv("ENVPOT_CELLS_SPLIT_LOG2")) {  // tuning override
+        const int v = std::atoi(e);
+        if (v >= 0 && v <= envpot::kMaxSplitLog2 && (h->m >> v) >= 64) k = v;
+    }
     *klog = k;
 }
 
