@@ -28,7 +28,8 @@ struct env_batch {
     int device = -1;
     int precision = ENV_PREC_FP32C;
     int np = 4;
-    int gran = 8;       // items per workgroup's fair share of the work (split granularity)
+    int gran = 16;      // items per workgroup's fair share of the work (split granularity;
+                        // the autotuner's pick on the 64-instance workload)
     int grid = 0;
     int cu_count = 256;
     int n_inst = 0;
